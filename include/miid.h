@@ -1,0 +1,183 @@
+/*
+ * miid.h -- C ABI of the MI355X (gfx950) interpolative-decomposition library.
+ *
+ * Paper: R. Advani and S. O'Hagan, "Efficient Algorithms for Constructing an
+ * Interpolative Decomposition" (arXiv 2105.07076).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrices are column-major.  "ld" arguments are leading dimensions in
+ *    elements.  Indices are 0-based int32.
+ *  - Every matrix/vector argument is a DEVICE pointer owned by the caller
+ *    (the library never allocates device memory); option structs are HOST
+ *    pointers.  `ws` is a caller-owned device workspace of at least the size
+ *    returned by the matching *_workspace() query; its contents on entry are
+ *    irrelevant and on return are unspecified.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    asynchronously; results (including `info`, a DEVICE pointer) are valid
+ *    once the stream has been synchronised.  Tolerance mode (opts.k == 0)
+ *    synchronises the stream a few times to stop early.
+ *  - The return value only reports problems the host can see at call time:
+ *      0                 success (launches enqueued)
+ *      -i                argument i (1-based) is invalid (LAPACK convention)
+ *      MIID_E_WORKSPACE  ws_bytes is smaller than the workspace query
+ *      MIID_E_HIP        a HIP call failed (miid_last_hip_error() tells which)
+ *      MIID_E_UNSUPPORTED shape or option outside the documented limits
+ *    Numerical outcomes are written to `info` on the device.
+ *  - Calls that share a workspace must not overlap in time.
+ */
+#ifndef MIID_H
+#define MIID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MIID_E_WORKSPACE (-100)
+#define MIID_E_HIP (-101)
+#define MIID_E_UNSUPPORTED (-102)
+
+/* element type of A, Z, C (and of the gradients in id_backward) */
+typedef enum { MIID_F32 = 0, MIID_F64 = 1 } miid_dtype;
+
+/* status bits written to miid_info.status */
+#define MIID_RANK_DEFICIENT 1u /* a residual became exactly zero: k_out < k   */
+#define MIID_NONFINITE 2u      /* A holds a NaN or an infinity: outputs unspecified */
+#define MIID_TRANSPOSED 4u     /* m > n: the dual ID of A^T was computed      */
+#define MIID_KMAX_HIT 8u       /* tolerance mode stopped at kmax, not at eps  */
+
+/* option flags */
+#define MIID_NO_REFINE 1u      /* skip the refinement step of the triangular solve */
+
+typedef struct {
+    int32_t k;      /* > 0: fixed rank.  0: tolerance mode: the smallest k with
+                       ||R22||_F <= eps * ||A||_F (estimated from the downdated
+                       column norms), at most kmax                       */
+    int32_t kmax;   /* tolerance mode cap (ignored when k > 0); rows of Z/J */
+    double eps;     /* relative tolerance for tolerance mode             */
+    int32_t nb;     /* panel width of the blocked QR, 0 = library default */
+    uint32_t flags; /* MIID_NO_REFINE                                    */
+} miid_opts;
+
+typedef struct {
+    int32_t k_out;       /* number of columns selected                      */
+    uint32_t status;     /* MIID_* status bits                              */
+    double a_norm;       /* ||A||_F                                          */
+    double r22_norm;     /* ||R22||_F estimate from the downdated norms      */
+    int32_t n_recompute; /* column norms recomputed after cancellation       */
+    int32_t n_steps;     /* pivot steps executed                             */
+} miid_info;
+
+/* library version string (host) */
+const char *miid_version(void);
+/* HIP error code of the last MIID_E_HIP return on this thread */
+int miid_last_hip_error(void);
+
+/* ------------------------------------------------------------------------
+ * Deterministic ID (Section 2.1; truncated QR of Section 4.1).
+ *
+ * Column-pivoted Householder QR A P = Q R with Businger-Golub pivoting on the
+ * residual column norms (largest norm first, ties to the smallest column
+ * index), stopped after k steps; C = A P_k (= A[:, J]) and
+ * Z = [I  R11^{-1} R12] P^T, the least-squares solution of min ||A - C Z||_F
+ * (Section 2.1, eq. final_eq solved by triangular solves).
+ * If m > n the dual ID of A^T is computed (footnote to Section 2): J then
+ * indexes rows of A, Z is k x m and A ~ Z^T A[J, :]; status gets
+ * MIID_TRANSPOSED.
+ *
+ *  A     (1)  m x n, leading dimension lda >= m, read only
+ *  J     (7)  kmax int32 (kmax = opts.k when k > 0): selected indices in
+ *             pivot order; entries >= k_out are -1
+ *  Z     (8)  kmax x N (N = max(m, n)), ldz >= kmax, dtype: Z[:, J[c]] is
+ *             exactly the c-th unit vector, the other columns hold T, rows
+ *             >= k_out are zero; columns in ORIGINAL order
+ *  R11   (10) nullable, kmax x kmax FP64, ldr >= kmax: the triangular factor
+ *             in pivot order (upper triangle; needed by id_backward)
+ *  C     (12) nullable, M x kmax (M = min(m, n)), ldc >= M, dtype: A[:, J]
+ *             (or A[J, :]^T when transposed); columns >= k_out unspecified
+ *  info  (14) device pointer to one miid_info
+ * Limits: 1 <= kmax <= min(m, n, 1024); nb in [1, 64].
+ * ---------------------------------------------------------------------- */
+size_t miid_id_workspace(int64_t m, int64_t n, miid_dtype dtype, const miid_opts *opts);
+int id_cpqr(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
+            const miid_opts *opts, int32_t *J, void *Z, int64_t ldz,
+            double *R11, int64_t ldr, void *C, int64_t ldc, miid_info *info,
+            void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Randomized ID with a Gaussian row sketch.  The paper's randomized method
+ * (Section 2.2) runs the same CPQR on a smaller matrix; here that smaller
+ * matrix is Y = Omega A (l x n), computed on the matrix cores in bfloat16
+ * with FP32 accumulation.  The CPQR of Y (FP32, FP64 norms, FP64 triangular
+ * solve) gives J and T; C = A[:, J].
+ *
+ *  A      (1)  m x n FP32, lda >= m, m <= n (else MIID_E_UNSUPPORTED)
+ *  Omega  (5)  l x m bfloat16 bit patterns, column-major, ldo >= l
+ *  mode   (8)  0: A rounded once to bfloat16 (one matrix-core pass);
+ *              1: A split as hi + lo, both bfloat16 (two passes, error
+ *                 ~ 2^-16 relative in Y)
+ *  J, Z, C, R11, info: as in id_cpqr with dtype FP32; Z is kmax x n
+ *  Y      (15) nullable, l x n FP32, ldy >= l: the sketch
+ * Limits: k < l <= 1024, kmax <= l.
+ * ---------------------------------------------------------------------- */
+size_t miid_rid_workspace(int64_t m, int64_t n, int32_t l, const miid_opts *opts);
+int rid_sketch_cpqr(const float *A, int64_t m, int64_t n, int64_t lda,
+                    const uint16_t *Omega, int32_t l, int64_t ldo, int32_t mode,
+                    const miid_opts *opts, int32_t *J, float *Z, int64_t ldz,
+                    float *C, int64_t ldc, float *Y, int64_t ldy,
+                    double *R11, int64_t ldr, miid_info *info,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched tolerance-mode IDs of many independent small blocks (for instance
+ * the off-diagonal blocks of a hierarchical kernel-matrix compression), in
+ * one persistent launch.  Block b is m[b] x n[b] (column-major, leading
+ * dimension m[b]) at A + a_off[b]; its rank is the smallest k with
+ * ||R22||_F <= eps ||A_b||_F (exact residual norms), at most
+ * kmax_b = min(m[b], n[b], kmax).
+ *
+ *  A      (2)  packed blocks, dtype
+ *  a_off, m, n (3-5) device int64 / int32 / int32 arrays of length nblk
+ *  J      (9)  packed int32: block b owns kmax_b entries at j_off[b]
+ *  Z      (11) packed dtype: block b owns a kmax_b x n[b] column-major
+ *              matrix (leading dimension kmax_b) at z_off[b]; rows >= k_out
+ *              are zero
+ *  info   (13) nblk miid_info entries
+ * Limits: 1 <= m[b] <= 256, m[b] <= n[b] <= 1024, kmax <= 64 (checked on the
+ * device: an out-of-range block gets status MIID_E_UNSUPPORTED-style k_out=-1).
+ * ---------------------------------------------------------------------- */
+size_t miid_batched_workspace(int32_t nblk, miid_dtype dtype);
+int id_batched(int32_t nblk, const void *A, const int64_t *a_off, const int32_t *m,
+               const int32_t *n, miid_dtype dtype, double eps, int32_t kmax,
+               int32_t *J, const int64_t *j_off, void *Z, const int64_t *z_off,
+               miid_info *info, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Adjoint of the ID with the pivots held fixed (the paper has no
+ * derivatives; this is the derivative of T = C^+ A_rest, C = A[:, J]).
+ * Given upstream gradients gC (of C) and gZ (of Z), with M = (C^T C)^{-1} Gz
+ * where Gz is gZ with its J columns zeroed and C^T C = R11^T R11:
+ *     gA          = C M
+ *     gA[:, J]   += gC + A M^T - C (Z M^T + M Z^T)
+ *
+ *  A   (1)   m x n, lda, dtype (the forward input; m <= n)
+ *  J   (6)   k int32, R11 (8): k x k FP64 from id_cpqr, ldr
+ *  Z   (10)  k x n, ldz, dtype, from id_cpqr
+ *  gC  (12)  nullable m x k, ldgc;  gZ (14) nullable k x n, ldgz
+ *  gA  (16)  m x n, ldga, written (not accumulated)
+ * Limits: 1 <= k <= min(m, n, 1024).
+ * ---------------------------------------------------------------------- */
+size_t miid_backward_workspace(int64_t m, int64_t n, int32_t k, miid_dtype dtype);
+int id_backward(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
+                const int32_t *J, int32_t k, const double *R11, int64_t ldr,
+                const void *Z, int64_t ldz, const void *gC, int64_t ldgc,
+                const void *gZ, int64_t ldgz, void *gA, int64_t ldga,
+                void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MIID_H */

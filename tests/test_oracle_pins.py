@@ -1,0 +1,416 @@
+"""Pins for the FP64 oracle: each test checks the oracle against something other
+than itself -- exact rational brute force, closed forms, invariants, library
+routines and the values printed in the paper -- so that a dropped term, a
+wrong sign or index, or a transposed operand in the oracle fails here.
+
+All tests run on the CPU (no GPU marker).
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import idgen
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# exact rational helpers (brute force on tiny integer matrices)
+# --------------------------------------------------------------------------
+def _det_frac(M):
+    """Determinant of a square matrix of Fractions by Gaussian elimination."""
+    M = [list(r) for r in M]
+    n = len(M)
+    det = Fraction(1)
+    for c in range(n):
+        piv = next((r for r in range(c, n) if M[r][c] != 0), None)
+        if piv is None:
+            return Fraction(0)
+        if piv != c:
+            M[c], M[piv] = M[piv], M[c]
+            det = -det
+        det *= M[c][c]
+        for r in range(c + 1, n):
+            f = M[r][c] / M[c][c]
+            if f != 0:
+                for q in range(c, n):
+                    M[r][q] -= f * M[c][q]
+    return det
+
+
+def _gram_det(A, cols):
+    """det(A[:, cols]^T A[:, cols]) exactly (A: list of integer columns)."""
+    if not cols:
+        return Fraction(1)
+    G = [[Fraction(sum(a * b for a, b in zip(A[i], A[j]))) for j in cols] for i in cols]
+    return _det_frac(G)
+
+
+def _greedy_exact(A_cols, k):
+    """Businger-Golub greedy selection in exact arithmetic.
+
+    The squared residual norm of column l after projecting out the chosen set
+    S is det Gram(S + {l}) / det Gram(S); the greedy step maximises it.
+    Returns (pivots, min relative gap between the best and second best
+    squared residual over the steps)."""
+    n = len(A_cols)
+    S = []
+    min_gap = math.inf
+    for _ in range(k):
+        base = _gram_det(A_cols, S)
+        vals = []
+        for l in range(n):
+            if l in S:
+                continue
+            vals.append((_gram_det(A_cols, S + [l]) / base, l))
+        vals.sort(key=lambda t: (-t[0], t[1]))
+        best = vals[0]
+        if len(vals) > 1 and best[0] > 0:
+            min_gap = min(min_gap, float((best[0] - vals[1][0]) / best[0]))
+        S.append(best[1])
+    return S, min_gap
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_pivots_match_exact_rational_greedy(seed):
+    g = idgen.rng(1000 + seed)
+    m = int(g.integers(2, 7))
+    n = int(g.integers(m, 11))
+    k = int(g.integers(1, m + 1))
+    A = g.integers(-4, 5, size=(m, n)).astype(np.float64)
+    cols = [[int(x) for x in A[:, c]] for c in range(n)]
+    if np.linalg.matrix_rank(A) < k:
+        pytest.skip("rank below k")
+    S, gap = _greedy_exact(cols, k)
+    if gap < 1e-9:
+        pytest.skip("exact near-tie; the floating-point choice is not determined")
+    res = oracle.id(A, k=k)
+    assert list(res.J) == S
+
+
+def test_ties_go_to_lowest_original_index():
+    # columns 1 and 3 have identical norm 5; column 0 is smaller
+    A = np.array([[1.0, 3.0, 0.0, 4.0],
+                  [0.0, 4.0, 1.0, 3.0]])
+    res = oracle.id(A, k=1)
+    assert res.J[0] == 1
+
+
+# --------------------------------------------------------------------------
+# maximum-volume subset: Z(J*) is bounded by 1 (Cramer's rule), Definition 1
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(8))
+def test_max_volume_subset_bounds_Z(seed):
+    g = idgen.rng(2000 + seed)
+    m, n, k = 4, 8, 3
+    A = g.standard_normal((m, n))
+    best, best_v = None, -1.0
+    for S in itertools.combinations(range(n), k):
+        v = np.linalg.det(A[:, S].T @ A[:, S])
+        if v > best_v:
+            best, best_v = S, v
+    res = oracle.id(A, k=k, force=np.array(best, dtype=np.int32))
+    assert sorted(res.J) == sorted(best)
+    assert np.abs(res.Z).max() <= 1.0 + 1e-12
+    # the greedy (unforced) subset has volume at least 1/k! of the maximum
+    # (Civril & Magdon-Ismail 2009 bound for greedy volume maximisation)
+    r = oracle.id(A, k=k)
+    v = np.linalg.det(A[:, r.J].T @ A[:, r.J])
+    assert math.sqrt(v / best_v) >= 1.0 / math.factorial(k) - 1e-12
+
+
+# --------------------------------------------------------------------------
+# exact reconstruction when rank(A) = k
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(12, 30, 5), (40, 40, 7), (25, 90, 25)])
+def test_exact_reconstruction_rank_k(shape):
+    m, n, k = shape
+    A = idgen.integer_lowrank(7, m, n, k)
+    res = oracle.id(A, k=k)
+    e = oracle.error(A, res.J, res.Z)
+    assert e <= 1e-12 * np.linalg.norm(A)
+    assert res.r22 <= 1e-12 * np.linalg.norm(A)
+
+
+# --------------------------------------------------------------------------
+# planted ID: known pivot order and known T
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n,k", [(40, 100, 10), (64, 64, 20), (30, 200, 30)])
+def test_planted_id(m, n, k):
+    A, planted, U, perm = idgen.planted_id(11, m, n, k, r=0.9)
+    res = oracle.id(A, k=k)
+    assert list(res.J) == list(planted)
+    # every step separated by 1 - r = 10%
+    assert res.margins.min() >= 0.1 - 1e-9
+    Zrest = res.Z[:, perm[k:]]
+    assert np.abs(Zrest - U).max() <= 1e-11
+    assert oracle.error(A, res.J, res.Z) <= 1e-12 * np.linalg.norm(A)
+
+
+def test_planted_id_with_noise():
+    m, n, k, eta = 60, 150, 12, 1e-9
+    A, planted, U, perm = idgen.planted_id(12, m, n, k, r=0.9, eta=eta)
+    res = oracle.id(A, k=k)
+    assert list(res.J) == list(planted)
+    dmin = 0.9 ** (k - 1)
+    assert np.abs(res.Z[:, perm[k:]] - U).max() <= 100 * eta / dmin
+
+
+# --------------------------------------------------------------------------
+# special cases with closed-form answers
+# --------------------------------------------------------------------------
+def test_diagonal_case():
+    d = np.array([3.0, 7.0, 1.0, 5.0, 2.0, 6.0])
+    A = idgen.diag_case(d, 10)
+    for k in range(1, 7):
+        res = oracle.id(A, k=k)
+        assert list(res.J) == list(np.argsort(-d, kind="stable")[:k])
+        assert np.all(res.T == 0.0)
+
+
+def test_rank_one_picks_largest_column():
+    g = idgen.rng(5)
+    A = g.standard_normal((20, 50))
+    res = oracle.id(A, k=1)
+    assert res.J[0] == int(np.argmax(np.linalg.norm(A, axis=0)))
+    c = A[:, res.J[0]]
+    np.testing.assert_allclose(res.Z[0], c @ A / (c @ c), rtol=1e-13, atol=1e-15)
+
+
+def test_full_rank_k_equals_m_is_exact():
+    g = idgen.rng(6)
+    A = g.standard_normal((16, 40))
+    res = oracle.id(A, k=16)
+    assert oracle.error(A, res.J, res.Z) <= 1e-12 * np.linalg.norm(A)
+
+
+def test_rank_deficient_stops_early():
+    # rank 3 with residuals that become exactly zero: the pivot rule has
+    # nothing left to select (rank below k, Section 2 assumes rank >= k)
+    A = idgen.diag_case(np.array([5.0, 0.0, 3.0, 0.0, 2.0, 0.0]), 10)
+    A[:, 7] = 2.0 * A[:, 0]
+    res = oracle.id(A, k=6)
+    assert res.k == 3
+    assert list(res.J) == [7, 2, 4]   # column 7 = 2 x column 0 has the larger norm
+
+
+def test_zero_matrix():
+    res = oracle.id(np.zeros((5, 9)), k=3)
+    assert res.k == 0
+
+
+def test_dual_id_for_tall_matrix():
+    g = idgen.rng(9)
+    A = g.standard_normal((50, 20)) @ np.diag(0.5 ** np.arange(20))
+    res = oracle.id(A, k=8)
+    assert res.transposed
+    ref = oracle.id(np.ascontiguousarray(A.T), k=8)
+    assert list(res.J) == list(ref.J)
+    assert np.array_equal(res.Z, ref.Z)
+    # A ~ Z^T A[J, :]
+    approx = res.Z.T @ A[res.J, :]
+    assert np.linalg.norm(A - approx) == pytest.approx(oracle.error(A.T, res.J, res.Z), rel=1e-10)
+
+
+# --------------------------------------------------------------------------
+# identities: Z[:, J] = I exactly; ||A - CZ||_F = ||R22||_F; Eckart-Young
+# --------------------------------------------------------------------------
+def test_identities_cfg1():
+    A, k = idgen.cfg1()
+    res = oracle.id(A, k=k)
+    assert np.array_equal(res.Z[:, res.J], np.eye(k))
+    e = oracle.error(A, res.J, res.Z)
+    assert e == pytest.approx(res.r22, rel=1e-6)
+    s = np.linalg.svd(A, compute_uv=False)
+    assert e >= math.sqrt((s[k:] ** 2).sum()) * (1 - 1e-12)
+    # R[:, J] is upper triangular in pivot order (R11), with |diag| = nu1
+    R11 = res.R[:, res.J]
+    assert np.allclose(np.tril(R11, -1), 0.0)
+    np.testing.assert_allclose(np.abs(np.diag(R11)), res.nu1[:k], rtol=1e-12)
+
+
+def test_tolerance_mode():
+    A, _ = idgen.cfg1()
+    a = np.linalg.norm(A)
+    for eps in [1e-1, 1e-3, 1e-6]:
+        res = oracle.id(A, eps=eps)
+        assert res.r22 <= eps * a
+        assert res.resid[res.k - 1] > eps * a
+        fixed = oracle.id(A, k=res.k)
+        assert list(fixed.J) == list(res.J)
+
+
+# --------------------------------------------------------------------------
+# library routines as cross-checks
+# --------------------------------------------------------------------------
+def test_matches_lapack_pivoted_qr():
+    import scipy.linalg as sla
+    A, k = idgen.cfg1()
+    res = oracle.id(A, k=k)
+    _, R, P = sla.qr(A, pivoting=True, mode="economic")
+    assert list(P[:k]) == list(res.J)
+    T = sla.solve_triangular(R[:k, :k], R[:k, k:])
+    np.testing.assert_allclose(res.Z[:, P[k:]], T, rtol=0, atol=1e-11 * np.abs(T).max())
+
+
+def test_matches_scipy_interpolative():
+    import scipy.linalg.interpolative as sli
+    g = idgen.rng(21)
+    A = np.asfortranarray(g.standard_normal((60, 100)) @ np.diag(0.9 ** np.arange(100)))
+    k = 12
+    idx, proj = sli.interp_decomp(A.copy(), k, rand=False)
+    res = oracle.id(A, k=k)
+    assert list(idx[:k]) == list(res.J)
+    Zs = sli.reconstruct_interp_matrix(idx, proj)
+    np.testing.assert_allclose(Zs, res.Z, rtol=0, atol=1e-12)
+
+
+def test_matmul_matches_numpy():
+    g = idgen.rng(3)
+    X = g.standard_normal((7, 13))
+    Y = g.standard_normal((13, 5))
+    np.testing.assert_allclose(oracle.matmul(X, Y), X @ Y, rtol=1e-14, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# values printed in the paper (Tables 1 and 2, synthetic rows, k = 190)
+# --------------------------------------------------------------------------
+def _paper_table():
+    with open(os.path.join(GOLDEN, "paper_tables_synthetic.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["boolean", "gaussian", "uniform"])
+def test_paper_table2_relative_error(name):
+    tab = _paper_table()
+    row = tab["rows"][name]
+    A = idgen.paper_dataset(name, seed=0)
+    k = tab["k"]
+    res = oracle.id(A, k=k)
+    rel = oracle.error(A, res.J, res.Z) / np.linalg.norm(A)
+    assert abs(rel - row["id_rel_error"]) <= tab["abs_tol"]
+    s = np.linalg.svd(A, compute_uv=False)
+    svd_rel = math.sqrt((s[k:] ** 2).sum()) / np.linalg.norm(A)
+    assert abs(svd_rel - row["svd_rel_error"]) <= tab["abs_tol"]
+    # Table 1: max |Z| = 1 for the deterministic ID
+    assert np.abs(res.Z).max() == row["id_max_abs_Z"]
+
+
+# --------------------------------------------------------------------------
+# randomized ID special cases
+# --------------------------------------------------------------------------
+def test_rid_identity_sketch_equals_id():
+    g = idgen.rng(31)
+    A = g.standard_normal((24, 60)) @ np.diag(0.8 ** np.arange(60))
+    res, Y = oracle.rid(A, np.eye(24), k=10)
+    ref = oracle.id(A, k=10)
+    assert np.array_equal(Y, A)
+    assert list(res.J) == list(ref.J)
+    assert np.array_equal(res.Z, ref.Z)
+
+
+def test_rid_exact_for_rank_k():
+    A = idgen.integer_lowrank(32, 50, 120, 6)
+    Om = idgen.omega_bf16(33, 16, 50)
+    res, _ = oracle.rid(A, Om, k=6)
+    assert oracle.error(A, res.J, res.Z) <= 1e-11 * np.linalg.norm(A)
+
+
+# --------------------------------------------------------------------------
+# derivative: finite differences, a dense least-squares reference, and
+# closed-form special cases
+# --------------------------------------------------------------------------
+def _loss_and_parts(A, B, J):
+    C = A[:, J]
+    Z = np.linalg.lstsq(C, A, rcond=None)[0]
+    M = C @ Z
+    return M, B - M, C, Z
+
+
+def test_vjp_finite_differences():
+    g = idgen.rng(41)
+    m, n, k = 18, 40, 6
+    A = g.standard_normal((m, n)) @ np.diag(0.85 ** np.arange(n))
+    B = g.standard_normal((m, n))
+    res = oracle.id(A, k=k)
+    J = res.J
+    M, G, C, Z = _loss_and_parts(A, B, J)
+    gC = -2.0 * G @ res.Z.T
+    gZ = -2.0 * C.T @ G
+    gA = oracle.id_vjp(A, J, res.Z, gC, gZ)
+    h = 1e-6
+    for d in range(8):
+        D = g.standard_normal((m, n))
+        D /= np.linalg.norm(D)
+        Mp, Gp, _, _ = _loss_and_parts(A + h * D, B, J)
+        Mm, Gm, _, _ = _loss_and_parts(A - h * D, B, J)
+        fd = -np.sum((Gp + Gm) * (Mp - Mm)) / (2 * h)
+        an = np.sum(gA * D)
+        assert abs(fd - an) <= 1e-5 * max(1.0, abs(an))
+
+
+def test_vjp_matches_autograd_lstsq():
+    torch = pytest.importorskip("torch")
+    g = idgen.rng(42)
+    m, n, k = 20, 50, 7
+    A = g.standard_normal((m, n)) @ np.diag(0.9 ** np.arange(n))
+    res = oracle.id(A, k=k)
+    J = res.J
+    gC = g.standard_normal((m, k))
+    gZ = g.standard_normal((k, n))
+    At = torch.tensor(A, dtype=torch.float64, requires_grad=True)
+    C = At[:, torch.tensor(J, dtype=torch.long)]
+    Zt = torch.linalg.pinv(C) @ At
+    loss = (C * torch.tensor(gC)).sum() + (Zt * torch.tensor(gZ)).sum()
+    loss.backward()
+    ref = At.grad.numpy()
+    gA = oracle.id_vjp(A, J, res.Z, gC, gZ)
+    # the gradient of Z[:, J] (= I) is zero in exact arithmetic; pinv's
+    # rounding puts O(u) noise there, so compare in Frobenius norm
+    assert np.linalg.norm(gA - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_vjp_full_rank_closed_form():
+    g = idgen.rng(43)
+    m, n = 10, 25
+    A = g.standard_normal((m, n))
+    B = g.standard_normal((m, n))
+    res = oracle.id(A, k=m)
+    C = A[:, res.J]
+    G = B - C @ res.Z
+    gA = oracle.id_vjp(A, res.J, res.Z, -2 * G @ res.Z.T, -2 * C.T @ G)
+    np.testing.assert_allclose(gA, -2 * (B - A), rtol=1e-9, atol=1e-9)
+
+
+def test_vjp_zero_when_target_is_the_approximation():
+    g = idgen.rng(44)
+    A = g.standard_normal((12, 30)) @ np.diag(0.8 ** np.arange(30))
+    res = oracle.id(A, k=5)
+    C = A[:, res.J]
+    B = C @ res.Z
+    G = B - C @ res.Z
+    gA = oracle.id_vjp(A, res.J, res.Z, -2 * G @ res.Z.T, -2 * C.T @ G)
+    assert np.abs(gA).max() == 0.0
+
+
+# --------------------------------------------------------------------------
+# input generators produce what they promise (these guard the recipe)
+# --------------------------------------------------------------------------
+def test_haar_and_bf16_generators():
+    g = idgen.rng(1)
+    Q = idgen.haar(g, 50, 20)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(20), atol=1e-13)
+    Om = idgen.omega_bf16(2, 8, 33)
+    bits = idgen.bf16_bits(Om)
+    back = (bits.astype(np.uint32) << 16).view(np.float32)
+    assert np.array_equal(back.reshape(Om.shape), Om.astype(np.float32))
+    assert idgen.bf16_round(np.array([1.0 + 2 ** -8], dtype=np.float32))[0] == 1.0  # tie to even
+    assert idgen.bf16_round(np.array([1.0 + 3 * 2 ** -8], dtype=np.float32))[0] == 1.0 + 2 ** -6
