@@ -214,3 +214,32 @@ def diag_case(d: np.ndarray, n: int) -> np.ndarray:
     A = np.zeros((m, n))
     A[np.arange(m), np.arange(m)] = d
     return np.asfortranarray(A)
+
+
+def lowrank_plus_noise_device(seed: int, m: int, n: int, s, noise: float, r: int | None = None,
+                              device: str = "cuda", dtype=None):
+    """Device-side version of :func:`lowrank_plus_noise` for the large
+    workloads: the same construction (Haar U, V from QR of seeded Gaussians
+    with the sign fix, A = U diag(s) V^T + noise G) drawn with torch's
+    seeded generator on ``device`` (not bit-identical to the numpy recipe).
+    Returns a column-major (m, n) tensor (stride (1, m))."""
+    import torch
+    dtype = torch.float64 if dtype is None else dtype
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    r = min(m, n, len(s)) if r is None else r
+
+    def haar_t(rows, cols):
+        X = torch.randn(rows, cols, generator=g, device=device, dtype=torch.float64)
+        Q, R = torch.linalg.qr(X, mode="reduced")
+        d = torch.sign(torch.diagonal(R))
+        d[d == 0] = 1.0
+        return Q * d[None, :]
+
+    U = haar_t(m, r)
+    V = haar_t(n, r)
+    sv = torch.as_tensor(np.asarray(s[:r], dtype=np.float64), device=device)
+    At = (V * sv[None, :]) @ U.T                      # (n, m) row-major = A column-major
+    At += noise * torch.randn(n, m, generator=g, device=device, dtype=torch.float64)
+    del U, V
+    return At.to(dtype).t()

@@ -71,6 +71,28 @@ typedef struct {
     int32_t n_steps;     /* pivot steps executed                             */
 } miid_info;
 
+/* Instrumentation (host): kernel timing with HIP events recorded on the
+ * stream each kernel is launched on.  miid_prof_begin(e) samples every e-th
+ * launch of each kernel (e = 0 switches it off); miid_prof_end() waits for
+ * the recorded events, copies up to max_records records and returns their
+ * number.  Kernel ids: */
+#define MIID_K_GEMV 1      /* F-GEMV + row update + downdate, one per pivot step */
+#define MIID_K_PIVOT 2     /* pivot search + pivot column, one per pivot step     */
+#define MIID_K_TRAIL 3     /* trailing update, one per panel                      */
+#define MIID_K_SKETCH 4    /* sketch GEMM Y = Omega A                             */
+#define MIID_K_BATCHED 5   /* persistent batched ID kernel                        */
+#define MIID_K_BWD_GEMM 6  /* adjoint GEMMs                                       */
+#define MIID_K_TRSM 7      /* triangular solve                                    */
+typedef struct {
+    int32_t kernel; /* MIID_K_* */
+    int32_t step;   /* launch index (pivot step for per-step kernels)     */
+    int64_t rows;   /* rows of the operand streamed by this launch        */
+    int64_t cols;   /* columns of that operand                            */
+    float ms;       /* elapsed time between the two events                */
+} miid_prof_record;
+int miid_prof_begin(int sample_every);
+int miid_prof_end(miid_prof_record *out, int max_records);
+
 /* library version string (host) */
 const char *miid_version(void);
 /* HIP error code of the last MIID_E_HIP return on this thread */

@@ -1,0 +1,100 @@
+"""ctypes binding of the miid C ABI (include/miid.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of libmiid.so.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmiid.so")
+
+MIID_F32 = 0
+MIID_F64 = 1
+MIID_E_WORKSPACE = -100
+MIID_E_HIP = -101
+MIID_E_UNSUPPORTED = -102
+
+MIID_RANK_DEFICIENT = 1
+MIID_NONFINITE = 2
+MIID_TRANSPOSED = 4
+MIID_KMAX_HIT = 8
+
+MIID_NO_REFINE = 1
+
+# every symbol declared in include/miid.h
+EXPORTED = [
+    "miid_version", "miid_last_hip_error",
+    "miid_id_workspace", "id_cpqr",
+    "miid_rid_workspace", "rid_sketch_cpqr",
+    "miid_batched_workspace", "id_batched",
+    "miid_backward_workspace", "id_backward",
+]
+
+
+class MiidOpts(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("kmax", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("nb", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class MiidInfo(ctypes.Structure):
+    _fields_ = [("k_out", ctypes.c_int32), ("status", ctypes.c_uint32), ("a_norm", ctypes.c_double),
+                ("r22_norm", ctypes.c_double), ("n_recompute", ctypes.c_int32), ("n_steps", ctypes.c_int32)]
+
+
+class MiidError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmiid.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2105_07076_amd/build.py "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P, I64, I32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    OPTS = ctypes.POINTER(MiidOpts)
+    lib.miid_version.restype = ctypes.c_char_p
+    lib.miid_version.argtypes = []
+    lib.miid_last_hip_error.restype = ctypes.c_int
+    lib.miid_last_hip_error.argtypes = []
+    lib.miid_id_workspace.restype = SZ
+    lib.miid_id_workspace.argtypes = [I64, I64, ctypes.c_int, OPTS]
+    lib.id_cpqr.restype = ctypes.c_int
+    lib.id_cpqr.argtypes = [P, I64, I64, I64, ctypes.c_int, OPTS, P, P, I64, P, I64, P, I64, P, P, SZ, P]
+    if hasattr(lib, "rid_sketch_cpqr"):
+        lib.miid_rid_workspace.restype = SZ
+        lib.miid_rid_workspace.argtypes = [I64, I64, I32, OPTS]
+        lib.rid_sketch_cpqr.restype = ctypes.c_int
+        lib.rid_sketch_cpqr.argtypes = [P, I64, I64, I64, P, I32, I64, I32, OPTS, P, P, I64, P, I64, P, I64,
+                                        P, I64, P, P, SZ, P]
+    if hasattr(lib, "id_batched"):
+        lib.miid_batched_workspace.restype = SZ
+        lib.miid_batched_workspace.argtypes = [I32, ctypes.c_int]
+        lib.id_batched.restype = ctypes.c_int
+        lib.id_batched.argtypes = [I32, P, P, P, P, ctypes.c_int, ctypes.c_double, I32, P, P, P, P, P, P, SZ, P]
+    if hasattr(lib, "id_backward"):
+        lib.miid_backward_workspace.restype = SZ
+        lib.miid_backward_workspace.argtypes = [I64, I64, I32, ctypes.c_int]
+        lib.id_backward.restype = ctypes.c_int
+        lib.id_backward.argtypes = [P, I64, I64, I64, ctypes.c_int, P, I32, P, I64, P, I64, P, I64, P, I64,
+                                    P, I64, P, SZ, P]
+    _lib = lib
+    return lib
+
+
+def check(rc: int, what: str) -> None:
+    if rc == 0:
+        return
+    if rc == MIID_E_HIP:
+        raise MiidError(f"{what}: HIP error {load().miid_last_hip_error()}")
+    names = {MIID_E_WORKSPACE: "workspace too small", MIID_E_UNSUPPORTED: "unsupported shape/options"}
+    raise MiidError(f"{what}: {names.get(rc, f'invalid argument {-rc}')} (rc={rc})")

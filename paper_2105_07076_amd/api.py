@@ -1,0 +1,178 @@
+"""torch-facing wrappers of the miid C ABI.
+
+torch provides device memory (outputs, workspace) and the current HIP stream;
+all arithmetic runs in libmiid.so.  Matrices cross the boundary column-major:
+a torch tensor ``A`` of shape (m, n) is passed as is when it is column-major
+(``A.t().is_contiguous()``), otherwise a column-major copy is made first.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _abi
+
+_DT = {torch.float32: _abi.MIID_F32, torch.float64: _abi.MIID_F64}
+
+
+def colmajor(x: torch.Tensor) -> torch.Tensor:
+    """Column-major view/copy of a 2-D tensor (stride(0) == 1)."""
+    if x.dim() != 2:
+        raise ValueError("expected a matrix")
+    if x.stride(0) == 1 and x.stride(1) >= max(1, x.shape[0]):
+        return x
+    return x.t().contiguous().t()
+
+
+def empty_colmajor(m: int, n: int, dtype, device) -> torch.Tensor:
+    return torch.empty((n, m), dtype=dtype, device=device).t()
+
+
+def _ptr(x: torch.Tensor | None):
+    return None if x is None else ctypes.c_void_p(x.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ld(x: torch.Tensor) -> int:
+    return max(1, x.stride(1))
+
+
+@dataclass
+class IDResult:
+    """J: selected indices (k_out); Z: k_out x N with Z[:, J] = I; C: A[:, J];
+    R11: FP64 triangular factor in pivot order (k_out x k_out) or None."""
+    J: torch.Tensor
+    Z: torch.Tensor
+    C: torch.Tensor | None
+    R11: torch.Tensor | None
+    k: int
+    status: int
+    a_norm: float
+    r22_norm: float
+    n_recompute: int
+    Y: torch.Tensor | None = None
+
+    @property
+    def transposed(self) -> bool:
+        return bool(self.status & _abi.MIID_TRANSPOSED)
+
+
+class Workspace:
+    """Grow-only device workspace (one per device and purpose)."""
+
+    def __init__(self):
+        self.buf: dict = {}
+
+    def get(self, key, nbytes: int, device) -> torch.Tensor:
+        b = self.buf.get((key, device))
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+            self.buf[(key, device)] = b
+        return b
+
+
+_WS = Workspace()
+
+
+def _read_info(info_dev: torch.Tensor) -> _abi.MiidInfo:
+    host = info_dev.cpu().numpy().tobytes()
+    return _abi.MiidInfo.from_buffer_copy(host)
+
+
+def _opts(k, eps, kmax, nb, refine) -> _abi.MiidOpts:
+    o = _abi.MiidOpts()
+    if (k is None) == (eps is None):
+        raise ValueError("give exactly one of k or eps")
+    o.k = int(k) if k is not None else 0
+    o.kmax = int(kmax) if kmax is not None else 0
+    o.eps = float(eps) if eps is not None else 0.0
+    o.nb = int(nb)
+    o.flags = 0 if refine else _abi.MIID_NO_REFINE
+    return o
+
+
+def id_raw(A: torch.Tensor, k: int | None = None, eps: float | None = None, kmax: int | None = None,
+           nb: int = 0, refine: bool = True, want_C: bool = True, want_R11: bool = False,
+           out: dict | None = None):
+    """Enqueue id_cpqr without synchronising.  Returns a dict of device
+    tensors (J, Z, C, R11, info) sized for kmax; ``out`` reuses buffers."""
+    lib = _abi.load()
+    if A.dtype not in _DT or not A.is_cuda:
+        raise TypeError("A must be a float32/float64 CUDA tensor")
+    A = colmajor(A)
+    M, N = A.shape
+    mw, nw = min(M, N), max(M, N)
+    if kmax is None:
+        kmax = min(M, N) if k is None else k
+    kk = k if k is not None else kmax
+    opts = _opts(k, eps, kmax, nb, refine)
+    dt = _DT[A.dtype]
+    ws_bytes = lib.miid_id_workspace(M, N, dt, ctypes.byref(opts))
+    if ws_bytes == 0:
+        _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_id_workspace")
+    ws = _WS.get("id", ws_bytes, A.device)
+    dev = A.device
+    if out is None:
+        out = {
+            "J": torch.empty(kk, dtype=torch.int32, device=dev),
+            "Z": empty_colmajor(kk, nw, A.dtype, dev),
+            "C": empty_colmajor(mw, kk, A.dtype, dev) if want_C else None,
+            "R11": empty_colmajor(kk, kk, torch.float64, dev) if want_R11 else None,
+            "info": torch.empty(ctypes.sizeof(_abi.MiidInfo), dtype=torch.uint8, device=dev),
+        }
+    Z, C, R11 = out["Z"], out["C"], out["R11"]
+    rc = lib.id_cpqr(_ptr(A), M, N, _ld(A), dt, ctypes.byref(opts), _ptr(out["J"]), _ptr(Z), _ld(Z),
+                     _ptr(R11), _ld(R11) if R11 is not None else 1, _ptr(C), _ld(C) if C is not None else 1,
+                     _ptr(out["info"]), _ptr(ws), ws_bytes, _stream())
+    _abi.check(rc, "id_cpqr")
+    return out
+
+
+def _finish(out: dict, Y=None) -> IDResult:
+    info = _read_info(out["info"])
+    k = info.k_out
+    J = out["J"][:k]
+    Z = out["Z"][:k]
+    C = out["C"][:, :k] if out.get("C") is not None else None
+    R11 = out["R11"][:k, :k] if out.get("R11") is not None else None
+    return IDResult(J=J, Z=Z, C=C, R11=R11, k=k, status=info.status, a_norm=info.a_norm,
+                    r22_norm=info.r22_norm, n_recompute=info.n_recompute, Y=Y)
+
+
+def id(A: torch.Tensor, k: int | None = None, eps: float | None = None, kmax: int | None = None,
+       nb: int = 0, refine: bool = True, want_C: bool = True, want_R11: bool = False) -> IDResult:
+    """Deterministic ID of A (m x n, float32/float64, on the GPU).
+
+    Fixed rank ``k``, or tolerance mode ``eps`` (relative, on ||R22||_F) with
+    cap ``kmax``.  m > n gives the dual ID of A^T (``transposed``)."""
+    out = id_raw(A, k=k, eps=eps, kmax=kmax, nb=nb, refine=refine, want_C=want_C, want_R11=want_R11)
+    return _finish(out)
+
+
+def rid(*args, **kwargs):
+    raise NotImplementedError("rid_sketch_cpqr is not built yet")
+
+
+def batched(*args, **kwargs):
+    raise NotImplementedError("id_batched is not built yet")
+
+
+def id_backward(*args, **kwargs):
+    raise NotImplementedError("id_backward is not built yet")
+
+
+class IDFunction(torch.autograd.Function):
+    """(C, Z) = ID(A) with the pivots fixed in the forward pass."""
+
+    @staticmethod
+    def forward(ctx, A, k):  # pragma: no cover - filled in with id_backward
+        raise NotImplementedError
+
+    @staticmethod
+    def backward(ctx, gC, gZ):  # pragma: no cover
+        raise NotImplementedError
