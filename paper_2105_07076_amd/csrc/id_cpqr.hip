@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "common.hpp"
@@ -84,8 +85,10 @@ __global__ void __launch_bounds__(kThreads) k_stage_transpose(const T* __restric
 }
 
 // Column norms of S with FP64 accumulation; sel = -1; argmax partials.
+// Workgroup b owns columns [4 cpw b, 4 cpw (b + 1)), wave w the cpw columns
+// starting at 4 cpw b + w cpw (the same partition as k_gemv).
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_norms(const T* __restrict__ S, int64_t ldw, int64_t n,
+__global__ void __launch_bounds__(kThreads) k_norms(const T* __restrict__ S, int64_t ldw, int64_t n, int cpw,
                                                     double* __restrict__ nu, double* __restrict__ nuref,
                                                     int32_t* __restrict__ sel, ColPartial* __restrict__ part,
                                                     int32_t* __restrict__ recomp) {
@@ -95,8 +98,8 @@ __global__ void __launch_bounds__(kThreads) k_norms(const T* __restrict__ S, int
     ArgMax best{-1.0, INT32_MAX};
     double sum = 0.0;
     int nf = 0;
-    for (int c = 0; c < kColsPerWave; ++c) {
-        const int64_t col = (int64_t)blockIdx.x * kColsPerWG + wave * kColsPerWave + c;
+    for (int c = 0; c < cpw; ++c) {
+        const int64_t col = ((int64_t)blockIdx.x * 4 + wave) * cpw + c;
         if (col >= n) break;
         const T* s = S + col * ldw;
         double acc = 0.0;
@@ -142,45 +145,6 @@ __global__ void k_fill(T* __restrict__ p, int64_t count, T value) {
         p[i] = value;
 }
 
-// Reduce the per-workgroup column partials (identical result in every
-// workgroup: fixed order, no atomics).  Returns best (value, index), the sum
-// of squares, and the non-finite flag through shared memory.
-__device__ void reduce_partials(const ColPartial* __restrict__ part, int npart, ArgMax* out_best, double* out_sum,
-                                int* out_nf) {
-    __shared__ double r_best[kThreads], r_sum[kThreads];
-    __shared__ int32_t r_idx[kThreads], r_nf[kThreads];
-    const int t = threadIdx.x;
-    ArgMax b{-1.0, INT32_MAX};
-    double s = 0.0;
-    int nf = 0;
-    for (int q = t; q < npart; q += kThreads) {
-        const ColPartial cp = part[q];
-        if (argmax_better(cp.best, cp.idx, b.v, b.i)) b = {cp.best, cp.idx};
-        s += cp.sumsq;
-        nf |= cp.nonfinite;
-    }
-    r_best[t] = b.v;
-    r_idx[t] = b.i;
-    r_sum[t] = s;
-    r_nf[t] = nf;
-    __syncthreads();
-    for (int h = kThreads / 2; h > 0; h >>= 1) {
-        if (t < h) {
-            if (argmax_better(r_best[t + h], r_idx[t + h], r_best[t], r_idx[t])) {
-                r_best[t] = r_best[t + h];
-                r_idx[t] = r_idx[t + h];
-            }
-            r_sum[t] += r_sum[t + h];
-            r_nf[t] |= r_nf[t + h];
-        }
-        __syncthreads();
-    }
-    *out_best = ArgMax{r_best[0], r_idx[0]};
-    *out_sum = r_sum[0];
-    *out_nf = r_nf[0];
-    __syncthreads();
-}
-
 // ---------------------------------------------------------------------------
 // a2 + a3 + first half of a4: pivot search, lazy update of the pivot column,
 // partial sums for the reflector.  One thread per row, 256 rows per workgroup.
@@ -194,11 +158,60 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
                                                         int i, int tol_mode, double eps) {
     __shared__ double s_F[kMaxNb];
     __shared__ double s_red[4][kPartAStride];
-    if (st->stop) return;
-    ArgMax best;
-    double sumsq;
-    int nf;
-    reduce_partials(part, npart, &best, &sumsq, &nf);
+    __shared__ double w_best[4], w_sum[4];
+    __shared__ int32_t w_idx[4], w_nf[4];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
+    const int64_t r = (int64_t)blockIdx.x * kRowsPerChunk + tid;
+    const bool active = r >= j && r < m;
+    const int stop_in = st->stop;
+
+    // row r of the panel's reflectors does not depend on the pivot: load first
+    double vr[kMaxNb];
+#pragma unroll
+    for (int q = 0; q < kMaxNb; ++q) vr[q] = (active && q < i) ? (double)V[r + (int64_t)q * ldw] : 0.0;
+
+    // a2: pivot = argmax of the per-workgroup column partials (same order in
+    // every workgroup, no atomics)
+    ArgMax best{-1.0, INT32_MAX};
+    double sumsq = 0.0;
+    int nf = 0;
+    // all partial loads of a thread are issued before any is consumed
+    constexpr int kPU = 8;
+    for (int q0 = tid; q0 < npart; q0 += kPU * kThreads) {
+        ColPartial cp[kPU];
+#pragma unroll
+        for (int k = 0; k < kPU; ++k) {
+            const int q = q0 + k * kThreads;
+            cp[k] = q < npart ? part[q] : ColPartial{-1.0, INT32_MAX, 0, 0.0, 0.0};
+        }
+#pragma unroll
+        for (int k = 0; k < kPU; ++k) {
+            if (argmax_better(cp[k].best, cp[k].idx, best.v, best.i)) best = {cp[k].best, cp[k].idx};
+            sumsq += cp[k].sumsq;
+            nf |= cp[k].nonfinite;
+        }
+    }
+    if (stop_in) return;
+    best = wave_argmax(best);
+    sumsq = wave_sum(sumsq);
+    nf = __any(nf) ? 1 : 0;
+    if (lane == 0) {
+        w_best[wave] = best.v;
+        w_idx[wave] = best.i;
+        w_sum[wave] = sumsq;
+        w_nf[wave] = nf;
+    }
+    __syncthreads();
+    best = ArgMax{w_best[0], w_idx[0]};
+    sumsq = w_sum[0];
+    nf = w_nf[0];
+    for (int w = 1; w < 4; ++w) {
+        if (argmax_better(w_best[w], w_idx[w], best.v, best.i)) best = {w_best[w], w_idx[w]};
+        sumsq += w_sum[w];
+        nf |= w_nf[w];
+    }
+
     const double a_norm = (j == 0) ? sqrt(sumsq) : st->a_norm;
     uint32_t status = 0;
     bool stop = false;
@@ -211,7 +224,7 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
     } else if (tol_mode && sqrt(sumsq) <= eps * a_norm) {
         stop = true;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
         if (j == 0) st->a_norm = a_norm;
         if (stop) {
             st->k_out = j;
@@ -223,33 +236,23 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
     }
     if (stop) return;
     const int64_t p = best.i;
-    if (threadIdx.x < i) s_F[threadIdx.x] = (double)F[p * nb + threadIdx.x];
+    if (tid < i) s_F[tid] = (double)F[p * nb + tid];
+    const double spr = active ? (double)S[r + p * ldw] : 0.0;
     __syncthreads();
 
-    const int64_t r = (int64_t)blockIdx.x * kRowsPerChunk + threadIdx.x;
-    const bool active = r >= j && r < m;
-    double vr[kMaxNb];
-    double ur = 0.0;
-    if (active) {
-        ur = (double)S[r + p * ldw];
+    // a3: lazily updated pivot column u = S[:, p] - V F[p, :]^T (rows j..m-1)
+    double ur = spr;
 #pragma unroll
-        for (int q = 0; q < kMaxNb; ++q) {
-            if (q < i) {
-                vr[q] = (double)V[r + q * ldw];
-                ur -= vr[q] * s_F[q];
-            } else {
-                vr[q] = 0.0;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < kMaxNb; ++q) vr[q] = 0.0;
-    }
+    for (int q = 0; q < kMaxNb; ++q)
+        if (q < i) ur -= vr[q] * s_F[q];
     const T ut = (T)ur;
-    if (r < ldw) u[r] = active ? ut : T(0);
+    // u[j] is kept apart (u[ldw]) so that u is zero at and above row j and the
+    // GEMV can use it directly: v = e_j + scale * u.
+    if (r < ldw) u[r] = (active && r != j) ? ut : T(0);
+    if (r == j) u[ldw] = ut;
+    // a4 partial sums: sum_{r>j} u_r^2 and V[j+1:, q]^T u[j+1:]
     const double w = (active && r > j) ? (double)ut : 0.0;
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    double s0 = wave_sum(w * w);
+    const double s0 = wave_sum(w * w);
     if (lane == 0) s_red[wave][0] = s0;
 #pragma unroll
     for (int q = 0; q < kMaxNb; ++q) {
@@ -259,19 +262,20 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
         }
     }
     __syncthreads();
-    if (threadIdx.x <= i) {
-        const int t = threadIdx.x;
-        partA[(int64_t)blockIdx.x * kPartAStride + t] = s_red[0][t] + s_red[1][t] + s_red[2][t] + s_red[3][t];
-    }
+    if (tid <= i) partA[(int64_t)blockIdx.x * kPartAStride + tid] = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
+
 }
 
 // ---------------------------------------------------------------------------
-// second half of a4 + a5 + a6 (+ a8 when flagged): reflector, F-GEMV over the
-// stale trailing matrix, row j of R, norm downdate / exact recompute, argmax
-// partials.  4 columns per wave, 16 per workgroup; the reflector v lives in
-// LDS (rows j0..ldw).
+// a5 + a6 (+ a8 when flagged): F-GEMV over the stale trailing matrix, row j of
+// R, norm downdate / exact recompute, argmax partials for the next step.
+// C columns per wave, 4 waves per workgroup, lanes over rows with 16-byte
+// loads.  The reflector is v = e_j + scale * u with u read from L2 (zero at
+// rows <= j), so the stream starts without waiting on any reduction.
 // ---------------------------------------------------------------------------
-template <typename T>
+constexpr int kPrefetchA = 4;  // partial-sum entries prefetched per thread
+
+template <typename T, int C>
 __global__ void __launch_bounds__(kThreads) k_gemv(const T* __restrict__ S, int64_t ldw, int64_t m, int64_t n,
                                                    T* __restrict__ V, T* __restrict__ F, int nb,
                                                    const T* __restrict__ u, const double* __restrict__ partA, int NA,
@@ -282,25 +286,112 @@ __global__ void __launch_bounds__(kThreads) k_gemv(const T* __restrict__ S, int6
                                                    int i, double tol) {
     using VT = typename Vec16<T>::type;
     constexpr int VEC = Vec16<T>::n;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* v = reinterpret_cast<T*>(smem_raw);
+    constexpr int U = C >= 4 ? 4 : (C == 2 ? 4 : 8);  // 16-byte loads in flight per column per lane
+    __shared__ double s_y[kMaxNb], s_vj[kMaxNb];
+    __shared__ double s_pa[kPrefetchA * kThreads];
     __shared__ double s_red[kPartAStride];
-    __shared__ double s_y[kMaxNb], s_vj[kMaxNb + 1];
     __shared__ double s_best[4], s_sum[4];
     __shared__ int32_t s_idx[4], s_nrec[4];
 
-    if (st->stop) return;
     const int tid = threadIdx.x;
-    const int64_t p = J[j];
+    // Serpentine sweep: odd steps walk the columns from the far end, so the
+    // part of the matrix read last in one step (still in the memory-side
+    // cache) is read first in the next.
+    const int wg = (j & 1) ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
+    const int64_t col0 = ((int64_t)wg * 4 + wave) * C;
+    const int stop = st->stop;
+    const int64_t p = J[j];  // meaningful only when !stop
+    // the pivot kernel's partial sums (sum u^2, V^T u per row chunk), u[j]
+    // and V[j, 0:i]: loaded now, used after the stream, so that their latency
+    // hides behind it
+    const int na = NA * (i + 1);
+    double pa[kPrefetchA];
+#pragma unroll
+    for (int k = 0; k < kPrefetchA; ++k) {
+        const int e = tid + k * kThreads;
+        pa[k] = e < na ? partA[(int64_t)(e / (i + 1)) * kPartAStride + e % (i + 1)] : 0.0;
+    }
+    const double u0 = (double)u[ldw];
+    const double vjq = tid < i ? (double)V[j + (int64_t)tid * ldw] : 0.0;
+
+    // per-column scalars, loaded together before the stream
+    bool alive[C];
+    double fq[C], nuc[C], nrf[C], sjc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int64_t col = col0 + c;
+        const bool in = col < n;
+        const double nv = in ? nu[col] : -1.0;
+        alive[c] = in && col != p && nv >= 0.0;
+        nuc[c] = nv;
+        nrf[c] = alive[c] ? nuref[col] : 1.0;
+        fq[c] = (alive[c] && lane < i) ? (double)F[col * nb + lane] : 0.0;
+        sjc[c] = alive[c] ? (double)S[col * ldw + j] : 0.0;
+    }
+
+    // a5: acc_c = S[j0:, col_c] . u  (u is zero at rows <= j and >= m)
+    const int64_t j0 = (int64_t)j & ~(int64_t)(VEC - 1);
+    double acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0;
+    const int64_t ngroups = (ldw - j0) / VEC;
+    const VT* up = reinterpret_cast<const VT*>(u + j0);
+    const VT* sp[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) sp[c] = reinterpret_cast<const VT*>(S + (col0 + c) * ldw + j0);
+    int64_t g = lane;
+    for (; g + (U - 1) * kWave < ngroups; g += U * kWave) {
+        VT sv[C][U], uv[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) uv[q] = up[g + q * kWave];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (alive[c]) {
+#pragma unroll
+                for (int q = 0; q < U; ++q) sv[c][q] = sp[c][g + q * kWave];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (alive[c]) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc[c] += (double)get(sv[c][q], e) * (double)get(uv[q], e);
+                }
+            }
+        }
+    }
+    for (; g < ngroups; g += kWave) {
+        const VT uv = up[g];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (alive[c]) {
+                const VT sv = sp[c][g];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc[c] += (double)get(sv, e) * (double)get(uv, e);
+            }
+        }
+    }
+    if (stop) return;
+
+    // a4 (second half): the reflector, identical in every workgroup
+#pragma unroll
+    for (int k = 0; k < kPrefetchA; ++k) s_pa[tid + k * kThreads] = pa[k];
+    __syncthreads();
     if (tid <= i) {
-        double acc = 0.0;
-        for (int c = 0; c < NA; ++c) acc += partA[(int64_t)c * kPartAStride + tid];
-        s_red[tid] = acc;
+        double t = 0.0;
+        if (na <= kPrefetchA * kThreads) {
+            for (int c = 0; c < NA; ++c) t += s_pa[c * (i + 1) + tid];
+        } else {
+            for (int c = 0; c < NA; ++c) t += partA[(int64_t)c * kPartAStride + tid];
+        }
+        s_red[tid] = t;
     }
     __syncthreads();
-    const double u0 = (double)u[j];
     const double alpha = sqrt(u0 * u0 + s_red[0]);
-    if (!(alpha > 0.0)) {
+    if (!(alpha > 0.0)) {  // the pivot column vanished: rank(A) == j
         if (blockIdx.x == 0 && tid == 0) {
             st->k_out = j;
             st->status |= MIID_RANK_DEFICIENT;
@@ -312,85 +403,54 @@ __global__ void __launch_bounds__(kThreads) k_gemv(const T* __restrict__ S, int6
     const double tau = (beta - u0) / beta;
     const double scale = 1.0 / (u0 - beta);
     if (tid < i) {
-        const double vjq = (double)V[j + (int64_t)tid * ldw];
         s_vj[tid] = vjq;
         s_y[tid] = vjq + scale * s_red[1 + tid];
     }
-    const int64_t j0 = (int64_t)j & ~(int64_t)(VEC - 1);
-    for (int64_t r = j0 + tid; r < ldw; r += kThreads) {
-        const T x = r < j ? T(0) : (r == j ? T(1) : (r < m ? (T)((double)u[r] * scale) : T(0)));
-        v[r - j0] = x;
-    }
     if (blockIdx.x == 0) {
-        for (int64_t r = tid; r < ldw; r += kThreads) {
-            const T x = r < j ? T(0) : (r == j ? T(1) : (r < m ? (T)((double)u[r] * scale) : T(0)));
-            V[r + (int64_t)i * ldw] = x;
-        }
+        for (int64_t r = tid; r < ldw; r += kThreads)
+            V[r + (int64_t)i * ldw] = r < j ? T(0) : (r == j ? T(1) : (T)((double)u[r] * scale));
         if (tid == 0) {
             R[(int64_t)j * n + p] = (T)beta;
             sel[p] = j;
         }
     }
-    if (tid == 0 && p / kColsPerWG == blockIdx.x) nu[p] = -1.0;
+    if (tid == 0 && p / (4 * C) == wg) nu[p] = -1.0;
     __syncthreads();
 
-    const int wave = tid / kWave, lane = tid % kWave;
-    const int64_t col0 = (int64_t)blockIdx.x * kColsPerWG + wave * kColsPerWave;
-    bool alive[kColsPerWave];
-    double acc[kColsPerWave];
-#pragma unroll
-    for (int c = 0; c < kColsPerWave; ++c) {
-        const int64_t col = col0 + c;
-        alive[c] = col < n && col != p && nu[col] >= 0.0;
-        acc[c] = 0.0;
-    }
-    const int64_t ngroups = (ldw - j0) / VEC;
-    for (int64_t g = lane; g < ngroups; g += kWave) {
-        const VT vv = *reinterpret_cast<const VT*>(v + g * VEC);
-#pragma unroll
-        for (int c = 0; c < kColsPerWave; ++c) {
-            if (alive[c]) {
-                const VT sv = *reinterpret_cast<const VT*>(S + (col0 + c) * ldw + j0 + g * VEC);
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) acc[c] += (double)get(sv, e) * (double)get(vv, e);
-            }
-        }
-    }
-
+    // a6: F column, row j of R, norm downdate (a8: exact recompute if flagged)
     ArgMax best{-1.0, INT32_MAX};
     double sumsq = 0.0;
     int nrec = 0;
 #pragma unroll
-    for (int c = 0; c < kColsPerWave; ++c) {
+    for (int c = 0; c < C; ++c) {
         if (!alive[c]) continue;
         const int64_t col = col0 + c;
-        const double dot = wave_sum(acc[c]);
-        const double fq = lane < i ? (double)F[col * nb + lane] : 0.0;
-        const double t1 = wave_sum(lane < i ? fq * s_y[lane] : 0.0);
-        const double t2 = wave_sum(lane < i ? fq * s_vj[lane] : 0.0);
+        const double dot = sjc[c] + scale * wave_sum(acc[c]);
+        const double t1 = wave_sum(lane < i ? fq[c] * s_y[lane] : 0.0);
+        const double t2 = wave_sum(lane < i ? fq[c] * s_vj[lane] : 0.0);
         const T fT = (T)(tau * (dot - t1));
         const double f = (double)fT;
-        const double rjl = (double)S[col * ldw + j] - t2 - f;
+        const double rjl = sjc[c] - t2 - f;
         if (lane == 0) {
             F[col * nb + i] = fT;
             R[(int64_t)j * n + col] = (T)rjl;
         }
-        const double nuc = nu[col];
-        double nnew = nuc;
+        double nnew = nuc[c];
         bool rec = false;
-        if (nuc > 0.0) {
-            double t = fabs(rjl) / nuc;
+        if (nuc[c] > 0.0) {
+            double t = fabs(rjl) / nuc[c];
             t = fmax(0.0, (1.0 - t) * (1.0 + t));
-            const double ratio = nuc / nuref[col];
+            const double ratio = nuc[c] / nrf[c];
             if (t * ratio * ratio <= tol)
                 rec = true;
             else
-                nnew = nuc * sqrt(t);
+                nnew = nuc[c] * sqrt(t);
         }
         if (rec) {
+            // exact norm of the lazily updated column, rows j+1..m-1
             double ss = 0.0;
             for (int64_t r = j + 1 + lane; r < m; r += kWave) {
-                double x = (double)S[col * ldw + r] - (double)v[r - j0] * f;
+                double x = (double)S[col * ldw + r] - scale * (double)u[r] * f;
                 for (int q = 0; q < i; ++q) x -= (double)V[r + (int64_t)q * ldw] * (double)F[col * nb + q];
                 ss += x * x;
             }
@@ -411,62 +471,103 @@ __global__ void __launch_bounds__(kThreads) k_gemv(const T* __restrict__ S, int6
     }
     __syncthreads();
     if (tid == 0) {
-        ArgMax b{s_best[0], s_idx[0]};
+        ArgMax b2{s_best[0], s_idx[0]};
         double t = s_sum[0];
         int nr = s_nrec[0];
         for (int w = 1; w < 4; ++w) {
-            if (argmax_better(s_best[w], s_idx[w], b.v, b.i)) b = {s_best[w], s_idx[w]};
+            if (argmax_better(s_best[w], s_idx[w], b2.v, b2.i)) b2 = {s_best[w], s_idx[w]};
             t += s_sum[w];
             nr += s_nrec[w];
         }
-        part[blockIdx.x] = ColPartial{b.v, b.i, 0, t, 0.0};
-        recomp[blockIdx.x] += nr;
+        part[wg] = ColPartial{b2.v, b2.i, 0, t, 0.0};
+        recomp[wg] += nr;
     }
 }
 
 // ---------------------------------------------------------------------------
-// a7: trailing update at the end of a panel, S[r0:, :] -= V[r0:, 0:w] F[:, 0:w]^T.
-// 64 x 64 tiles; each thread owns one row and 16 columns.
+// a7: trailing update at the end of a panel, S[r0:, :] -= V[r0:, 0:w] F[:, 0:w]^T,
+// on the matrix cores.  64 x 64 tile per workgroup, 32 x 32 per wave (2 x 2
+// blocks of 16 x 16), K = w in steps of 4 (v_mfma_{f64,f32}_16x16x4).
+// Operands: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].  Output
+// element e of lane l is column l % 16 and row 4 (l / 16) + e for f32 but
+// row l / 16 + 4 e for f64 (measured on gfx950).
 // ---------------------------------------------------------------------------
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+template <typename T> struct Acc4;
+template <> struct Acc4<double> {
+    using type = d4_t;
+    static __device__ __forceinline__ int row(int lg, int e) { return lg + 4 * e; }
+};
+template <> struct Acc4<float> {
+    using type = f4_t;
+    static __device__ __forceinline__ int row(int lg, int e) { return 4 * lg + e; }
+};
+
+__device__ __forceinline__ d4_t mfma16x16x4(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma16x16x4(float a, float b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_trail(T* __restrict__ S, int64_t ldw, int64_t n,
                                                     const T* __restrict__ V, const T* __restrict__ F, int nb, int w,
                                                     int64_t r0, const DevState* __restrict__ st) {
-    __shared__ T sV[64][kMaxNb + 1];
-    __shared__ T sF[kMaxNb][64];
+    // D = F_tile V_tile^T, so the MFMA's row index runs over columns of S and
+    // its column index over rows of S: one accumulator element of 16
+    // neighbouring lanes is 16 consecutive rows of one column of S.
+    using A4 = typename Acc4<T>::type;
     if (st->stop) return;
     const int64_t rbase = (r0 & ~(int64_t)63) + (int64_t)blockIdx.x * 64;
     const int64_t cbase = (int64_t)blockIdx.y * 64;
     const int tid = threadIdx.x;
-    for (int e = tid; e < 64 * w; e += kThreads) {
-        const int rr = e % 64, q = e / 64;
-        sV[rr][q] = V[rbase + rr + (int64_t)q * ldw];
-    }
-    for (int e = tid; e < 64 * w; e += kThreads) {
-        const int q = e % w, cc = e / w;
-        const int64_t col = cbase + cc;
-        sF[q][cc] = col < n ? F[col * nb + q] : T(0);
-    }
-    __syncthreads();
-    const int rr = tid % 64, cg = tid / 64;
-    const int64_t row = rbase + rr;
-    if (row < r0 || row >= ldw) return;
-    double acc[16];
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
+    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;  // wave's 32 rows x 32 columns
+    const int l16 = lane % 16, lg = lane / 16;
+    A4 acc[2][2];  // [column block][row block]
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int64_t col = cbase + cg * 16 + e;
-        acc[e] = col < n ? (double)S[row + col * ldw] : 0.0;
-    }
-    for (int q = 0; q < w; ++q) {
-        const double vq = (double)sV[rr][q];
+    for (int bc = 0; bc < 2; ++bc)
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[e] -= vq * (double)sF[q][cg * 16 + e];
+        for (int br = 0; br < 2; ++br) {
+            const int64_t row = rbase + wr + br * 16 + l16;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t col = cbase + wc + bc * 16 + Acc4<T>::row(lg, e);
+                acc[bc][br][e] = col < n ? S[row + col * ldw] : T(0);
+            }
+        }
+    for (int k0 = 0; k0 < w; k0 += 4) {
+        const int q = k0 + lg;
+        T a[2], b[2];
+#pragma unroll
+        for (int bc = 0; bc < 2; ++bc) {
+            const int64_t col = cbase + wc + bc * 16 + l16;
+            a[bc] = (q < w && col < n) ? F[col * nb + q] : T(0);
+        }
+#pragma unroll
+        for (int br = 0; br < 2; ++br) {
+            const int64_t row = rbase + wr + br * 16 + l16;
+            b[br] = q < w ? -V[row + (int64_t)q * ldw] : T(0);
+        }
+#pragma unroll
+        for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+            for (int br = 0; br < 2; ++br) acc[bc][br] = mfma16x16x4(a[bc], b[br], acc[bc][br]);
     }
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int64_t col = cbase + cg * 16 + e;
-        if (col < n) S[row + col * ldw] = (T)acc[e];
-    }
+    for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+        for (int br = 0; br < 2; ++br) {
+            const int64_t row = rbase + wr + br * 16 + l16;
+            if (row < r0) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t col = cbase + wc + bc * 16 + Acc4<T>::row(lg, e);
+                if (col < n) S[row + col * ldw] = acc[bc][br][e];
+            }
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -490,55 +591,103 @@ __global__ void k_gather_r11(const T* __restrict__ R, int64_t n, const int32_t* 
     }
 }
 
-// Right-looking back substitution of R11 x = b for NCOL columns held in LDS
-// (work[k][NCOL]); thread (g, c) owns column c and rows q = g (mod G).
+// Blocked back substitution R11 x = b for NCOL right-hand sides held in LDS
+// (work[K][NCOL], overwritten by x).  Row blocks of BS = 256 / NCOL rows are
+// processed bottom-up: the BS x BS diagonal block is staged in LDS and solved
+// by thread (a, c) = (row in block, column); then every row above the block
+// subtracts the block's contribution (thread per row, NCOL columns, R11 read
+// column-wise from global memory with independent loads).
 template <int NCOL>
-__device__ void lds_backsolve(double* work, const double* __restrict__ R11s, int kmax, int K) {
-    constexpr int G = kThreads / NCOL;
-    const int c = threadIdx.x % NCOL, g = threadIdx.x / NCOL;
-    for (int i = K - 1; i >= 0; --i) {
-        if (g == i % G) work[i * NCOL + c] /= R11s[i + (int64_t)i * kmax];
+__device__ void lds_backsolve(double* work, double* sD, const double* __restrict__ R11s, int kmax, int K) {
+    constexpr int BS = kThreads / NCOL;
+    const int tid = threadIdx.x;
+    const int c = tid % NCOL, a = tid / NCOL;
+    const int nblk = (K + BS - 1) / BS;
+    for (int b = nblk - 1; b >= 0; --b) {
+        const int r0 = b * BS;
+        const int bs = min(BS, K - r0);
+        for (int e = tid; e < BS * BS; e += kThreads) {
+            const int ra = e % BS, cb = e / BS;
+            sD[ra * (BS + 1) + cb] = (ra < bs && cb < bs && ra <= cb) ? R11s[(r0 + ra) + (int64_t)(r0 + cb) * kmax] : 0.0;
+        }
         __syncthreads();
-        const double zi = work[i * NCOL + c];
-        const double* col = R11s + (int64_t)i * kmax;
-        for (int q = g; q < i; q += G) work[q * NCOL + c] -= col[q] * zi;
+        for (int i = bs - 1; i >= 0; --i) {
+            if (a == i) work[(r0 + i) * NCOL + c] /= sD[i * (BS + 1) + i];
+            __syncthreads();
+            if (a < i) work[(r0 + a) * NCOL + c] -= sD[a * (BS + 1) + i] * work[(r0 + i) * NCOL + c];
+        }
+        __syncthreads();
+        for (int q = tid; q < r0; q += kThreads) {
+            double acc[NCOL], rq[BS];
+#pragma unroll
+            for (int t = 0; t < BS; ++t) rq[t] = t < bs ? R11s[q + (int64_t)(r0 + t) * kmax] : 0.0;
+#pragma unroll
+            for (int cc = 0; cc < NCOL; ++cc) acc[cc] = work[q * NCOL + cc];
+#pragma unroll
+            for (int t = 0; t < BS; ++t) {
+                if (t < bs) {
+#pragma unroll
+                    for (int cc = 0; cc < NCOL; ++cc) acc[cc] -= rq[t] * work[(r0 + t) * NCOL + cc];
+                }
+            }
+#pragma unroll
+            for (int cc = 0; cc < NCOL; ++cc) work[q * NCOL + cc] = acc[cc];
+        }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
-// Z[:, cols] = R11^{-1} R[:, cols] in FP64 with one refinement step;
+// Z[:, cols] = R11^{-1} R[:, cols] in FP64 with one refinement step
+// (residual R[:, cols] - R11 x in FP64, one more solve);
 // Z[:, J[c]] = e_c exactly; rows >= k_out are zero.
 template <typename T, int NCOL>
-__global__ void __launch_bounds__(kThreads) k_trsm(const T* __restrict__ R, int64_t n,
+__global__ void __launch_bounds__(kThreads, 2) k_trsm(const T* __restrict__ R, int64_t n,
                                                    const double* __restrict__ R11s, int kmax,
                                                    const DevState* __restrict__ st, int ksteps,
                                                    const int32_t* __restrict__ sel, T* __restrict__ Z, int64_t ldz,
                                                    int refine) {
+    constexpr int BS = kThreads / NCOL;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* z = reinterpret_cast<double*>(smem_raw);  // [kmax][NCOL]
     double* work = z + (int64_t)kmax * NCOL;          // [kmax][NCOL]
-    constexpr int G = kThreads / NCOL;
+    __shared__ double sD[BS * (BS + 1)];
     const int K = st->stop ? st->k_out : ksteps;
     const int64_t c0 = (int64_t)blockIdx.x * NCOL;
-    const int c = threadIdx.x % NCOL, g = threadIdx.x / NCOL;
-    const int64_t col = c0 + c;
-    for (int q = g; q < K; q += G) work[q * NCOL + c] = col < n ? (double)R[(int64_t)q * n + col] : 0.0;
-    __syncthreads();
-    lds_backsolve<NCOL>(work, R11s, kmax, K);
-    for (int q = g; q < K; q += G) z[q * NCOL + c] = work[q * NCOL + c];
-    if (refine) {
-        __syncthreads();
-        for (int q = g; q < K; q += G) {
-            double e = col < n ? (double)R[(int64_t)q * n + col] : 0.0;
-            for (int t = q; t < K; ++t) e -= R11s[q + (int64_t)t * kmax] * z[t * NCOL + c];
-            work[q * NCOL + c] = e;
-        }
-        __syncthreads();
-        lds_backsolve<NCOL>(work, R11s, kmax, K);
-        for (int q = g; q < K; q += G) z[q * NCOL + c] += work[q * NCOL + c];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < K * NCOL; e += kThreads) {
+        const int q = e / NCOL, c = e % NCOL;
+        const int64_t col = c0 + c;
+        work[e] = col < n ? (double)R[(int64_t)q * n + col] : 0.0;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kmax * NCOL; e += kThreads) {
+    lds_backsolve<NCOL>(work, sD, R11s, kmax, K);
+    for (int e = tid; e < K * NCOL; e += kThreads) z[e] = work[e];
+    if (refine) {
+        __syncthreads();
+        for (int q = tid; q < K; q += kThreads) {
+            double acc[NCOL];
+#pragma unroll
+            for (int cc = 0; cc < NCOL; ++cc) {
+                const int64_t col = c0 + cc;
+                acc[cc] = col < n ? (double)R[(int64_t)q * n + col] : 0.0;
+            }
+            // start at the wave's first row so that the loads of one t are
+            // contiguous over the wave (R11s is zero below the diagonal)
+#pragma unroll 4
+            for (int t = q & ~(kWave - 1); t < K; ++t) {
+                const double rq = R11s[q + (int64_t)t * kmax];
+#pragma unroll
+                for (int cc = 0; cc < NCOL; ++cc) acc[cc] -= rq * z[t * NCOL + cc];
+            }
+#pragma unroll
+            for (int cc = 0; cc < NCOL; ++cc) work[q * NCOL + cc] = acc[cc];
+        }
+        __syncthreads();
+        lds_backsolve<NCOL>(work, sD, R11s, kmax, K);
+        for (int e = tid; e < K * NCOL; e += kThreads) z[e] += work[e];
+    }
+    __syncthreads();
+    for (int e = tid; e < kmax * NCOL; e += kThreads) {
         const int q = e % kmax, cc = e / kmax;
         const int64_t cl = c0 + cc;
         if (cl >= n) continue;
@@ -618,9 +767,18 @@ struct IdPlan {
     double eps;
     bool refine;
     size_t esz;
+    int cpw;   // columns per wave in the column passes (k_norms, k_gemv)
     int npart, NA;
     size_t oS, oV, oF, ou, onu, onuref, oR, osel, opart, opartA, oR11, ostate, orec, total;
 };
+
+// Columns per wave of the F-GEMV (1, 2 or 4); MIID_GEMV_CPW overrides the
+// default for tuning.
+static int gemv_cols_per_wave() {
+    const char* e = std::getenv("MIID_GEMV_CPW");
+    const int v = e ? std::atoi(e) : 1;
+    return (v == 2 || v == 4) ? v : 1;
+}
 
 static int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan* P) {
     if (M < 1) return -2;
@@ -641,7 +799,8 @@ static int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o,
     P->esz = dtype == MIID_F64 ? 8 : 4;
     P->ldw = (int64_t)align_up((size_t)P->m, 64);
     if ((size_t)P->ldw * P->esz > kMaxVecLds) return MIID_E_UNSUPPORTED;
-    P->npart = (int)((P->n + kColsPerWG - 1) / kColsPerWG);
+    P->cpw = gemv_cols_per_wave();
+    P->npart = (int)((P->n + 4 * P->cpw - 1) / (4 * P->cpw));
     P->NA = (int)((P->ldw + kRowsPerChunk - 1) / kRowsPerChunk);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -652,7 +811,7 @@ static int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o,
     P->oS = take((size_t)P->ldw * P->n * P->esz);
     P->oV = take((size_t)P->ldw * P->nb * P->esz);
     P->oF = take((size_t)P->n * P->nb * P->esz);
-    P->ou = take((size_t)P->ldw * P->esz);
+    P->ou = take((size_t)(P->ldw + 64) * P->esz);
     P->onu = take((size_t)P->n * 8);
     P->onuref = take((size_t)P->n * 8);
     P->oR = take((size_t)P->kmax * P->n * P->esz);
@@ -688,7 +847,6 @@ static int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, in
     static bool attr_done = false;
     if (!attr_done) {
         // dynamic LDS above 64 KB: the reflector (k_gemv) and the solve tiles (k_trsm)
-        MIID_HIP(hipFuncSetAttribute((const void*)k_gemv<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxVecLds));
         MIID_HIP(hipFuncSetAttribute((const void*)k_trsm<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
         MIID_HIP(hipFuncSetAttribute((const void*)k_trsm<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
         attr_done = true;
@@ -707,9 +865,11 @@ static int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, in
         dim3 grid((unsigned)((ldw + 63) / 64), (unsigned)((n + 63) / 64));
         hipLaunchKernelGGL(k_stage_transpose<T>, grid, dim3(kThreads), 0, stream, A, lda, m, n, S, ldw);
     } else {
-        hipLaunchKernelGGL(k_stage_copy<T>, dim3(P.npart), dim3(kThreads), 0, stream, A, lda, m, n, S, ldw);
+        hipLaunchKernelGGL(k_stage_copy<T>, dim3((unsigned)((n + kColsPerWG - 1) / kColsPerWG)), dim3(kThreads), 0,
+                           stream, A, lda, m, n, S, ldw);
     }
-    hipLaunchKernelGGL(k_norms<T>, dim3(P.npart), dim3(kThreads), 0, stream, S, ldw, n, nu, nuref, sel, part, recomp);
+    hipLaunchKernelGGL(k_norms<T>, dim3(P.npart), dim3(kThreads), 0, stream, S, ldw, n, P.cpw, nu, nuref, sel, part,
+                       recomp);
 
     const double tol = sizeof(T) == 8 ? sqrt(2.220446049250313e-16) : sqrt(1.1920928955078125e-07);
     int ksteps = P.kmax;
@@ -721,11 +881,20 @@ static int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, in
         hipLaunchKernelGGL(k_pivot_col<T>, dim3(P.NA), dim3(kThreads), 0, stream, S, ldw, m, V, F, nb, u, part,
                            P.npart, partA, st, J, j, i, (int)P.tol, P.eps);
         prof_close(pr, stream);
-        const int64_t j0 = (int64_t)j & ~(int64_t)(Vec16<T>::n - 1);
-        const size_t lds = (size_t)(ldw - j0) * sizeof(T);
         pr = prof_open(MIID_K_GEMV, j, m - j, n - j, stream);
-        hipLaunchKernelGGL(k_gemv<T>, dim3(P.npart), dim3(kThreads), lds, stream, S, ldw, m, n, V, F, nb, u, partA,
-                           P.NA, st, J, R, nu, nuref, sel, part, recomp, j, i, tol);
+        switch (P.cpw) {
+            case 4:
+                hipLaunchKernelGGL((k_gemv<T, 4>), dim3(P.npart), dim3(kThreads), 0, stream, S, ldw, m, n, V, F, nb,
+                                   u, partA, P.NA, st, J, R, nu, nuref, sel, part, recomp, j, i, tol);
+                break;
+            case 2:
+                hipLaunchKernelGGL((k_gemv<T, 2>), dim3(P.npart), dim3(kThreads), 0, stream, S, ldw, m, n, V, F, nb,
+                                   u, partA, P.NA, st, J, R, nu, nuref, sel, part, recomp, j, i, tol);
+                break;
+            default:
+                hipLaunchKernelGGL((k_gemv<T, 1>), dim3(P.npart), dim3(kThreads), 0, stream, S, ldw, m, n, V, F, nb,
+                                   u, partA, P.NA, st, J, R, nu, nuref, sel, part, recomp, j, i, tol);
+        }
         prof_close(pr, stream);
         const bool panel_end = (i == nb - 1);
         if (panel_end && j + 1 < P.kmax) {
