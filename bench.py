@@ -145,6 +145,33 @@ def main() -> int:
     if piv:
         extra["id_fp64_pivot_col_ms"] = round(sum(r.ms for r in piv) / len(piv), 5)
 
+    # randomized ID (bfloat16 sketch on the matrix cores + FP32 CPQR of Y)
+    log("[bench] mixed RID (split bf16 sketch, l = k + 10)")
+    l = k + 10
+    Om = torch.tensor(idgen.omega_bf16(77, l, m), dtype=torch.bfloat16, device="cuda")
+    out_r = miid_api.rid_raw(A32, Om, k=k, mode=1)
+    for _ in range(args.warmup):
+        miid_api.rid_raw(A32, Om, k=k, mode=1, out=out_r)
+    torch.cuda.synchronize()
+    lib.miid_prof_begin(16)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        miid_api.rid_raw(A32, Om, k=k, mode=1, out=out_r)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    recs_r = prof_records(lib)
+    ms_rid = (t1 - t0) * 1000.0 / args.steps
+    extra["rid_mixed_ms"] = round(ms_rid, 4)
+    extra["rid_speedup_vs_fp64_id"] = round(ms64 / ms_rid, 2)
+    sk = [r for r in recs_r if r.kernel == 4]
+    if sk:
+        sk_ms = sum(r.ms for r in sk) / len(sk)
+        flops = 2.0 * 2 * l * m * n  # two bf16 passes (hi + lo)
+        extra["rid_sketch_ms"] = round(sk_ms, 4)
+        extra["rid_sketch_TFLOPs"] = round(flops / (sk_ms * 1e-3) / 1e12, 1)
+        extra["rid_sketch_GBps_A"] = round(m * n * 4 / (sk_ms * 1e-3) / 1e9, 1)
+    log(f"[bench] RID {ms_rid:.3f} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle

@@ -143,7 +143,7 @@ int id_cpqr(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
  *                 ~ 2^-16 relative in Y)
  *  J, Z, C, R11, info: as in id_cpqr with dtype FP32; Z is kmax x n
  *  Y      (15) nullable, l x n FP32, ldy >= l: the sketch
- * Limits: k < l <= 1024, kmax <= l.
+ * Limits: k <= l <= min(n, 1024) (kmax <= l in tolerance mode), m <= n.
  * ---------------------------------------------------------------------- */
 size_t miid_rid_workspace(int64_t m, int64_t n, int32_t l, const miid_opts *opts);
 int rid_sketch_cpqr(const float *A, int64_t m, int64_t n, int64_t lda,

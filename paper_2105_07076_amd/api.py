@@ -154,8 +154,61 @@ def id(A: torch.Tensor, k: int | None = None, eps: float | None = None, kmax: in
     return _finish(out)
 
 
-def rid(*args, **kwargs):
-    raise NotImplementedError("rid_sketch_cpqr is not built yet")
+def rid_raw(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: float | None = None,
+            kmax: int | None = None, mode: int = 1, nb: int = 0, refine: bool = True, want_C: bool = True,
+            want_Y: bool = False, want_R11: bool = False, out: dict | None = None):
+    """Enqueue rid_sketch_cpqr without synchronising (see :func:`rid`)."""
+    lib = _abi.load()
+    if A.dtype != torch.float32 or not A.is_cuda:
+        raise TypeError("A must be a float32 CUDA tensor")
+    if omega.dtype != torch.bfloat16 or not omega.is_cuda:
+        raise TypeError("omega must be a bfloat16 CUDA tensor (l x m)")
+    A = colmajor(A)
+    om = colmajor(omega)
+    m, n = A.shape
+    l = om.shape[0]
+    if om.shape[1] != m:
+        raise ValueError("omega must be l x m")
+    if kmax is None:
+        kmax = l if k is None else k
+    kk = k if k is not None else kmax
+    opts = _opts(k, eps, kmax, nb, refine)
+    ws_bytes = lib.miid_rid_workspace(m, n, l, ctypes.byref(opts))
+    if ws_bytes == 0:
+        _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_rid_workspace")
+    ws = _WS.get("rid", ws_bytes, A.device)
+    dev = A.device
+    if out is None:
+        out = {
+            "J": torch.empty(kk, dtype=torch.int32, device=dev),
+            "Z": empty_colmajor(kk, n, torch.float32, dev),
+            "C": empty_colmajor(m, kk, torch.float32, dev) if want_C else None,
+            "Y": empty_colmajor(l, n, torch.float32, dev) if want_Y else None,
+            "R11": empty_colmajor(kk, kk, torch.float64, dev) if want_R11 else None,
+            "info": torch.empty(ctypes.sizeof(_abi.MiidInfo), dtype=torch.uint8, device=dev),
+        }
+    Z, C, Y, R11 = out["Z"], out["C"], out["Y"], out["R11"]
+    rc = lib.rid_sketch_cpqr(_ptr(A), m, n, _ld(A), _ptr(om), l, _ld(om), int(mode), ctypes.byref(opts),
+                             _ptr(out["J"]), _ptr(Z), _ld(Z), _ptr(C), _ld(C) if C is not None else 1,
+                             _ptr(Y), _ld(Y) if Y is not None else 1, _ptr(R11), _ld(R11) if R11 is not None else 1,
+                             _ptr(out["info"]), _ptr(ws), ws_bytes, _stream())
+    _abi.check(rc, "rid_sketch_cpqr")
+    return out
+
+
+def rid(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: float | None = None,
+        kmax: int | None = None, mode: int = 1, nb: int = 0, refine: bool = True, want_C: bool = True,
+        want_Y: bool = False, want_R11: bool = False) -> IDResult:
+    """Randomized ID of A (m x n float32, m <= n) with the Gaussian row sketch
+    Y = omega A computed on the matrix cores.
+
+    ``omega`` is an l x m bfloat16 tensor (the random numbers the method
+    draws are an input).  ``mode`` 1 splits A as hi + lo bfloat16 (two
+    passes), 0 rounds it once.  J and T come from the CPQR of Y; C = A[:, J].
+    ``a_norm``/``r22_norm`` in the result refer to Y."""
+    out = rid_raw(A, omega, k=k, eps=eps, kmax=kmax, mode=mode, nb=nb, refine=refine, want_C=want_C,
+                  want_Y=want_Y, want_R11=want_R11)
+    return _finish(out, Y=out["Y"])
 
 
 def batched(*args, **kwargs):

@@ -40,6 +40,8 @@ int miid_prof_begin(int sample_every) {
 int miid_prof_end(miid_prof_record* out, int max_records) {
     ProfState& s = prof_state();
     int count = 0;
+    // the events skip the system-scope fence: wait for the device first
+    MIID_HIP(hipDeviceSynchronize());
     for (auto& slot : s.used) {
         if (hipEventSynchronize(slot.b) != hipSuccess) {
             g_last_hip_error = (int)hipGetLastError();

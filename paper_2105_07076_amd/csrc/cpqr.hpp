@@ -1,0 +1,39 @@
+// cpqr.hpp -- the blocked column-pivoted QR + triangular-solve driver shared
+// by the deterministic ID (id_cpqr) and the randomized ID (rid_sketch_cpqr).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace miid {
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct IdPlan {
+    int64_t M, N;  // caller's shape
+    int64_t m, n;  // working shape, m <= n
+    bool trans;
+    int64_t ldw;
+    int kmax, nb;
+    bool tol;
+    double eps;
+    bool refine;
+    size_t esz;
+    int cpw;   // columns per wave in the column passes (k_norms, k_gemv)
+    int npart, NA;
+    size_t oS, oV, oF, ou, onu, onuref, oR, osel, opart, opartA, oR11, ostate, orec, total;
+};
+
+// Validates the shape/options and lays out the workspace (returns 0 or a
+// negative MIID code).
+int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan* P);
+
+// Enqueues the whole factorisation.  With staged = true the working matrix S
+// (ldw x n, rows >= m zero) already holds the matrix to factor and the
+// staging kernels are skipped; C is gathered from Csrc (crows x n, ldcsrc).
+template <typename T>
+int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t ldz, double* R11out, int64_t ldr, T* C,
+           int64_t ldc, miid_info* info, unsigned char* ws, hipStream_t stream, bool staged, const T* Csrc,
+           int64_t ldcsrc, int64_t crows);
+
+}  // namespace miid

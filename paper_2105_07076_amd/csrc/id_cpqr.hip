@@ -34,6 +34,7 @@
 #include <cstring>
 
 #include "common.hpp"
+#include "cpqr.hpp"
 #include "prof.hpp"
 
 namespace miid {
@@ -47,7 +48,6 @@ constexpr int kPartAStride = kMaxNb + 1;
 constexpr int kMaxK = 1024;
 constexpr size_t kMaxVecLds = 131072;  // bytes of LDS for the reflector in the GEMV
 
-static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // ---------------------------------------------------------------------------
 // a1: staging.  S (ldw x n, padded rows zero) <- A, or A^T for the dual ID.
@@ -757,20 +757,6 @@ __global__ void k_finalize(const DevState* __restrict__ st, const ColPartial* __
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-struct IdPlan {
-    int64_t M, N;  // caller's shape
-    int64_t m, n;  // working shape, m <= n
-    bool trans;
-    int64_t ldw;
-    int kmax, nb;
-    bool tol;
-    double eps;
-    bool refine;
-    size_t esz;
-    int cpw;   // columns per wave in the column passes (k_norms, k_gemv)
-    int npart, NA;
-    size_t oS, oV, oF, ou, onu, onuref, oR, osel, opart, opartA, oR11, ostate, orec, total;
-};
 
 // Columns per wave of the F-GEMV (1, 2 or 4); MIID_GEMV_CPW overrides the
 // default for tuning.
@@ -780,7 +766,7 @@ static int gemv_cols_per_wave() {
     return (v == 2 || v == 4) ? v : 1;
 }
 
-static int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan* P) {
+int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan* P) {
     if (M < 1) return -2;
     if (N < 1) return -3;
     if (dtype != MIID_F32 && dtype != MIID_F64) return -5;
@@ -826,8 +812,9 @@ static int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o,
 }
 
 template <typename T>
-static int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t ldz, double* R11out,
-                  int64_t ldr, T* C, int64_t ldc, miid_info* info, unsigned char* ws, hipStream_t stream) {
+int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t ldz, double* R11out, int64_t ldr, T* C,
+           int64_t ldc, miid_info* info, unsigned char* ws, hipStream_t stream, bool staged, const T* Csrc,
+           int64_t ldcsrc, int64_t crows) {
     T* S = reinterpret_cast<T*>(ws + P.oS);
     T* V = reinterpret_cast<T*>(ws + P.oV);
     T* F = reinterpret_cast<T*>(ws + P.oF);
@@ -861,7 +848,9 @@ static int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, in
         hipLaunchKernelGGL(k_fill<T>, dim3(blocks), dim3(256), 0, stream, R, cnt, T(0));
     }
     // a1: stage + norms
-    if (P.trans) {
+    if (staged) {
+        // S was filled by the caller (the sketch Y = Omega A)
+    } else if (P.trans) {
         dim3 grid((unsigned)((ldw + 63) / 64), (unsigned)((n + 63) / 64));
         hipLaunchKernelGGL(k_stage_transpose<T>, grid, dim3(kThreads), 0, stream, A, lda, m, n, S, ldw);
     } else {
@@ -935,14 +924,21 @@ static int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, in
     }
     // a10: C, info
     if (C) {
-        dim3 grid((unsigned)std::min<int64_t>((m + 255) / 256, 64), (unsigned)P.kmax);
-        hipLaunchKernelGGL(k_gather_c<T>, grid, dim3(256), 0, stream, A, lda, (int)P.trans, m, J, st, ksteps, C, ldc);
+        dim3 grid((unsigned)std::min<int64_t>((crows + 255) / 256, 64), (unsigned)P.kmax);
+        hipLaunchKernelGGL(k_gather_c<T>, grid, dim3(256), 0, stream, Csrc, ldcsrc, (int)P.trans, crows, J, st, ksteps,
+                           C, ldc);
     }
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, stream, st, part, P.npart, recomp, J, P.kmax, ksteps,
                        (int)P.tol, P.eps, (int)P.trans, info);
     MIID_HIP(hipGetLastError());
     return 0;
 }
+
+template int run_id<float>(const IdPlan&, const float*, int64_t, int32_t*, float*, int64_t, double*, int64_t, float*,
+                           int64_t, miid_info*, unsigned char*, hipStream_t, bool, const float*, int64_t, int64_t);
+template int run_id<double>(const IdPlan&, const double*, int64_t, int32_t*, double*, int64_t, double*, int64_t,
+                            double*, int64_t, miid_info*, unsigned char*, hipStream_t, bool, const double*, int64_t,
+                            int64_t);
 
 }  // namespace miid
 
@@ -975,8 +971,10 @@ int id_cpqr(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
     if (dtype == MIID_F64)
-        return run_id<double>(P, (const double*)A, lda, J, (double*)Z, ldz, R11, ldr, (double*)C, ldc, info, w, s);
-    return run_id<float>(P, (const float*)A, lda, J, (float*)Z, ldz, R11, ldr, (float*)C, ldc, info, w, s);
+        return run_id<double>(P, (const double*)A, lda, J, (double*)Z, ldz, R11, ldr, (double*)C, ldc, info, w, s, false,
+                              (const double*)A, lda, P.m);
+    return run_id<float>(P, (const float*)A, lda, J, (float*)Z, ldz, R11, ldr, (float*)C, ldc, info, w, s, false,
+                         (const float*)A, lda, P.m);
 }
 
 }  // extern "C"

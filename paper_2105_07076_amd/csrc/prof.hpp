@@ -36,8 +36,10 @@ inline int prof_open(int32_t kernel, int32_t step, int64_t rows, int64_t cols, h
         slot = s.pool.back();
         s.pool.pop_back();
     } else {
-        if (hipEventCreate(&slot.a) != hipSuccess) return -1;
-        if (hipEventCreate(&slot.b) != hipSuccess) return -1;
+        // no system-scope release on record: the events must not flush the
+        // caches the timed kernel would otherwise find warm
+        if (hipEventCreateWithFlags(&slot.a, hipEventDisableSystemFence) != hipSuccess) return -1;
+        if (hipEventCreateWithFlags(&slot.b, hipEventDisableSystemFence) != hipSuccess) return -1;
     }
     slot.rec = miid_prof_record{kernel, step, rows, cols, 0.0f};
     hipEventRecord(slot.a, stream);

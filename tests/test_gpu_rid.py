@@ -1,0 +1,136 @@
+"""GPU parity of rid_sketch_cpqr (randomized ID with a bfloat16 Gaussian row
+sketch on the matrix cores) against the FP64 oracle.
+
+Three checks per case:
+  * the sketch: Y_gpu vs Y64 = Omega A in FP64 on the same (bf16-exact)
+    Omega and the same FP32 A, normwise;
+  * the CPQR stage: the oracle run on the GPU's own Y (promoted) must give the
+    same pivots (margin-aware, FP32) and T within the FP32 bar;
+  * end to end: ||A - C Z||_F in FP64 against the oracle's randomized ID with
+    an exact FP64 sketch (split form within 1e-5 relative).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import idgen
+import oracle
+from gpu_helpers import U32, pivot_parity, rel, t_part, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# bf16 hi+lo represents a to ~2^-17 relative; FP32 accumulation over m terms
+# adds ~sqrt(m) 2^-24.  A single bf16 rounding is ~2^-9.
+SKETCH_TOL = {1: 3e-5, 0: 6e-3}
+
+
+def _miid():
+    import paper_2105_07076_amd as miid
+    miid.load()
+    return miid
+
+
+def _run(A_np, l, k, mode, seed=77, nb=0):
+    miid = _miid()
+    m, n = A_np.shape
+    A_t = torch.tensor(A_np, dtype=torch.float32, device="cuda")
+    A64 = A_t.double().cpu().numpy()
+    Om = idgen.omega_bf16(seed, l, m)
+    Om_t = torch.tensor(Om, dtype=torch.bfloat16, device="cuda")
+    r = miid.rid(A_t, Om_t, k=k, mode=mode, want_Y=True, nb=nb)
+    torch.cuda.synchronize()
+    return r, A64, Om.astype(np.float64)
+
+
+def _check(A_np, l, k, mode, e2e_tol=None, nb=0):
+    r, A64, Om = _run(A_np, l, k, mode, nb=nb)
+    Y = to_np(r.Y).astype(np.float64)
+    Y64 = oracle.matmul(Om, A64)
+    ey = rel(Y, Y64)
+    assert ey <= SKETCH_TOL[mode], f"sketch error {ey:.3e}"
+    J = to_np(r.J)
+    Z = to_np(r.Z).astype(np.float64)
+    assert r.k == k
+    # CPQR stage on the GPU's own Y
+    ref, ties = pivot_parity(Y, J, k, U32)
+    assert np.array_equal(Z[:, J], np.eye(k))
+    R11 = ref.R[:, ref.J]
+    bar = max(1e-5, 8.0 * U32 * np.linalg.cond(R11))
+    et = rel(t_part(Z, J), t_part(ref.Z, J))
+    assert et <= bar, f"T error {et:.3e} > {bar:.3e}"
+    # C = A[:, J] exactly
+    assert np.array_equal(to_np(r.C).astype(np.float64), A64[:, J])
+    # end to end against the exact-sketch oracle
+    e_gpu = oracle.error(A64, J, Z)
+    if e2e_tol is not None:
+        ore, _ = oracle.rid(A64, Om, k)
+        e_ora = oracle.error(A64, ore.J, ore.Z)
+        assert abs(e_gpu - e_ora) <= e2e_tol * e_ora, f"e2e {e_gpu:.6e} vs {e_ora:.6e}"
+    return r, e_gpu, ties
+
+
+@pytest.mark.parametrize("mode", [1, 0])
+@pytest.mark.parametrize("m,n,l,k", [(64, 200, 26, 16), (100, 333, 50, 40), (257, 1000, 74, 64),
+                                     (33, 65, 33, 20)])
+def test_rid_small(mode, m, n, l, k):
+    g = idgen.rng(m * 7 + n)
+    A = g.standard_normal((m, n)) @ np.diag(0.97 ** np.arange(n))
+    _check(A, l, k, mode, e2e_tol=1e-4 if mode == 1 else None)
+
+
+def test_rid_exact_for_rank_k():
+    A = idgen.integer_lowrank(5, 80, 300, 12).astype(np.float32).astype(np.float64)
+    r, e, _ = _check(A, 22, 12, 1)
+    assert e <= 1e-4 * np.linalg.norm(A)
+
+
+def test_rid_planted_rank_k():
+    """A planted rank-k input: a random sketch does not keep the planted pivot
+    order, but any k columns it picks reconstruct A (rank k, k <= l)."""
+    A, planted, U, perm = idgen.planted_id(9, 120, 500, 20, r=0.9)
+    r, e, ties = _check(A, 30, 20, 1)
+    assert e <= 1e-4 * np.linalg.norm(A)
+
+
+def test_rid_unaligned_lda():
+    """A column-major view with an odd leading dimension takes the scalar path."""
+    miid = _miid()
+    g = idgen.rng(3)
+    big = torch.tensor(g.standard_normal((101, 400)), dtype=torch.float32, device="cuda")
+    A_t = big.t().contiguous().t()[:99]          # 99 x 400, lda = 101
+    Om = torch.tensor(idgen.omega_bf16(4, 30, 99), dtype=torch.bfloat16, device="cuda")
+    r = miid.rid(A_t, Om, k=20, want_Y=True)
+    A64 = A_t.double().cpu().numpy()
+    Y64 = oracle.matmul(Om.double().cpu().numpy(), A64)
+    assert rel(to_np(r.Y).astype(np.float64), Y64) <= SKETCH_TOL[1]
+
+
+def test_rid_cfg2_reduced():
+    """cfg2 construction at 1024 x 4096, k = 256, l = k + 10."""
+    A, k = idgen.cfg2(m=1024, n=4096)
+    _check(A, k + 10, k, 1, e2e_tol=1e-5)
+
+
+def test_rid_cfg2_full_size():
+    """4096 x 16384, k = 256, l = 266, split sketch: the benchmarked launch."""
+    miid = _miid()
+    A_t = idgen.lowrank_plus_noise_device(2, 4096, 16384, np.exp(-np.arange(4096) / 64.0), 1e-8,
+                                          dtype=torch.float32)
+    Om = idgen.omega_bf16(77, 266, 4096)
+    Om_t = torch.tensor(Om, dtype=torch.bfloat16, device="cuda")
+    r = miid.rid(A_t, Om_t, k=256, mode=1, want_Y=True)
+    torch.cuda.synchronize()
+    A64 = A_t.double().cpu().numpy()
+    Y = to_np(r.Y).astype(np.float64)
+    Y64 = oracle.matmul(Om.astype(np.float64), A64)
+    assert rel(Y, Y64) <= SKETCH_TOL[1]
+    J = to_np(r.J)
+    Z = to_np(r.Z).astype(np.float64)
+    ref, ties = pivot_parity(Y, J, 256, U32)
+    assert rel(t_part(Z, J), t_part(ref.Z, J)) <= 1e-5
+    ore, _ = oracle.rid(A64, Om.astype(np.float64), 256)
+    e_gpu = oracle.error(A64, J, Z)
+    e_ora = oracle.error(A64, ore.J, ore.Z)
+    assert abs(e_gpu - e_ora) <= 1e-5 * e_ora
