@@ -172,6 +172,31 @@ def main() -> int:
         extra["rid_sketch_GBps_A"] = round(m * n * 4 / (sk_ms * 1e-3) / 1e9, 1)
     log(f"[bench] RID {ms_rid:.3f} ms")
 
+    # batched IDs: 4096 kernel-matrix blocks, tolerance 1e-6, FP32, one launch
+    log("[bench] batched IDs (4096 blocks, eps = 1e-6)")
+    blocks = idgen.batched_blocks(seed=4, nblk=4096)
+    Ab = torch.tensor(blocks.A, dtype=torch.float32, device="cuda")
+    out_b = miid_api.batched_raw(Ab, blocks.a_off, blocks.m, blocks.n, 1e-6, 64)
+    for _ in range(args.warmup):
+        miid_api.batched_raw(Ab, blocks.a_off, blocks.m, blocks.n, 1e-6, 64, out=out_b)
+    torch.cuda.synchronize()
+    lib.miid_prof_begin(1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        miid_api.batched_raw(Ab, blocks.a_off, blocks.m, blocks.n, 1e-6, 64, out=out_b)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    recs_b = prof_records(lib)
+    ms_b = (t1 - t0) * 1000.0 / args.steps
+    extra["batched_ms"] = round(ms_b, 4)
+    extra["batched_ids_per_s"] = round(4096 / (ms_b * 1e-3), 1)
+    kb = [r for r in recs_b if r.kernel == 5]
+    if kb:
+        kms = sum(r.ms for r in kb) / len(kb)
+        extra["batched_kernel_ms"] = round(kms, 4)
+        extra["batched_GBps_blocks"] = round(blocks.A.size * 4 / (kms * 1e-3) / 1e9, 1)
+    log(f"[bench] batched {ms_b:.3f} ms = {extra['batched_ids_per_s']:.0f} IDs/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle

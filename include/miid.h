@@ -48,6 +48,7 @@ typedef enum { MIID_F32 = 0, MIID_F64 = 1 } miid_dtype;
 #define MIID_NONFINITE 2u      /* A holds a NaN or an infinity: outputs unspecified */
 #define MIID_TRANSPOSED 4u     /* m > n: the dual ID of A^T was computed      */
 #define MIID_KMAX_HIT 8u       /* tolerance mode stopped at kmax, not at eps  */
+#define MIID_BLOCK_UNSUPPORTED 16u /* id_batched: block outside the size limits */
 
 /* option flags */
 #define MIID_NO_REFINE 1u      /* skip the refinement step of the triangular solve */
@@ -168,8 +169,11 @@ int rid_sketch_cpqr(const float *A, int64_t m, int64_t n, int64_t lda,
  *              matrix (leading dimension kmax_b) at z_off[b]; rows >= k_out
  *              are zero
  *  info   (13) nblk miid_info entries
- * Limits: 1 <= m[b] <= 256, m[b] <= n[b] <= 1024, kmax <= 64 (checked on the
- * device: an out-of-range block gets status MIID_E_UNSUPPORTED-style k_out=-1).
+ * Limits: 1 <= m[b] <= 256, m[b] <= n[b] <= 1024, 1 <= kmax <= 64.  A block
+ * outside them is skipped with k_out = 0 and status MIID_BLOCK_UNSUPPORTED;
+ * the others are unaffected (likewise a block holding a NaN only gets its
+ * own MIID_NONFINITE).  Blocks are processed largest first when
+ * nblk <= 8192, in index order otherwise.
  * ---------------------------------------------------------------------- */
 size_t miid_batched_workspace(int32_t nblk, miid_dtype dtype);
 int id_batched(int32_t nblk, const void *A, const int64_t *a_off, const int32_t *m,

@@ -9,6 +9,6 @@ include/miid.h; this package only marshals arguments (torch supplies device
 memory and the stream).
 """
 from ._abi import MiidError, load  # noqa: F401
-from .api import IDResult, id, rid, batched, id_backward, IDFunction  # noqa: F401
+from .api import IDResult, BatchedResult, id, rid, batched, id_backward, IDFunction  # noqa: F401
 
 __all__ = ["IDResult", "id", "rid", "batched", "id_backward", "IDFunction", "MiidError", "load"]

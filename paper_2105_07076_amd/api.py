@@ -211,8 +211,79 @@ def rid(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: float |
     return _finish(out, Y=out["Y"])
 
 
-def batched(*args, **kwargs):
-    raise NotImplementedError("id_batched is not built yet")
+@dataclass
+class BatchedResult:
+    """Packed outputs of :func:`batched`: block b selected k[b] columns
+    J[j_off[b]: j_off[b] + k[b]] and owns the kmax_b x n_b matrix
+    Z[z_off[b]: z_off[b] + kmax_b * n_b] (column-major, rows >= k[b] zero)."""
+    J: torch.Tensor
+    Z: torch.Tensor
+    k: "np.ndarray"
+    status: "np.ndarray"
+    a_norm: "np.ndarray"
+    r22_norm: "np.ndarray"
+    kmax_b: "np.ndarray"
+    j_off: "np.ndarray"
+    z_off: "np.ndarray"
+    n: "np.ndarray"
+
+    def block(self, b: int):
+        """(J_b, Z_b) of block b as host numpy arrays (Z_b is k_b x n_b)."""
+        kb, kk, nb = int(self.kmax_b[b]), int(self.k[b]), int(self.n[b])
+        Jh = self.J[int(self.j_off[b]): int(self.j_off[b]) + kk].cpu().numpy()
+        Zh = self.Z[int(self.z_off[b]): int(self.z_off[b]) + kb * nb].cpu().numpy().reshape(nb, kb).T[:kk]
+        return Jh, Zh
+
+
+def batched_raw(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, out: dict | None = None):
+    """Enqueue id_batched without synchronising.  ``A`` is the packed blocks
+    (1-D float32/float64 CUDA tensor), ``a_off``/``m``/``n`` host sequences."""
+    import numpy as np
+    lib = _abi.load()
+    if A.dtype not in _DT or not A.is_cuda:
+        raise TypeError("A must be a float32/float64 CUDA tensor")
+    dev = A.device
+    if out is None:
+        mh = np.asarray(m, dtype=np.int32)
+        nh = np.asarray(n, dtype=np.int32)
+        kb = np.minimum(np.minimum(mh, nh), kmax).astype(np.int64)
+        j_off = np.zeros(len(mh), dtype=np.int64)
+        j_off[1:] = np.cumsum(kb)[:-1]
+        z_off = np.zeros(len(mh), dtype=np.int64)
+        z_off[1:] = np.cumsum(kb * nh)[:-1]
+        nblk = len(mh)
+        out = {
+            "nblk": nblk, "kmax_b": kb, "j_off_h": j_off, "z_off_h": z_off, "n_h": nh,
+            "a_off": torch.as_tensor(np.asarray(a_off, dtype=np.int64), device=dev),
+            "m": torch.as_tensor(mh, device=dev), "n": torch.as_tensor(nh, device=dev),
+            "j_off": torch.as_tensor(j_off, device=dev), "z_off": torch.as_tensor(z_off, device=dev),
+            "J": torch.empty(int(kb.sum()), dtype=torch.int32, device=dev),
+            "Z": torch.empty(int((kb * nh).sum()), dtype=A.dtype, device=dev),
+            "info": torch.empty(nblk * ctypes.sizeof(_abi.MiidInfo), dtype=torch.uint8, device=dev),
+        }
+    dt = _DT[A.dtype]
+    ws_bytes = lib.miid_batched_workspace(out["nblk"], dt)
+    ws = _WS.get("batched", ws_bytes, dev)
+    rc = lib.id_batched(out["nblk"], _ptr(A), _ptr(out["a_off"]), _ptr(out["m"]), _ptr(out["n"]), dt,
+                        float(eps), int(kmax), _ptr(out["J"]), _ptr(out["j_off"]), _ptr(out["Z"]),
+                        _ptr(out["z_off"]), _ptr(out["info"]), _ptr(ws), ws_bytes, _stream())
+    _abi.check(rc, "id_batched")
+    return out
+
+
+def batched(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64) -> BatchedResult:
+    """Tolerance-mode IDs of many independent blocks in one launch: block b is
+    m[b] x n[b] (column-major) at A[a_off[b]:]; its rank is the smallest k with
+    ||R22||_F <= eps ||A_b||_F, at most min(m_b, n_b, kmax)."""
+    import numpy as np
+    out = batched_raw(A, a_off, m, n, eps, kmax)
+    raw = out["info"].cpu().numpy().tobytes()
+    sz = ctypes.sizeof(_abi.MiidInfo)
+    infos = [_abi.MiidInfo.from_buffer_copy(raw[i * sz:(i + 1) * sz]) for i in range(out["nblk"])]
+    return BatchedResult(J=out["J"], Z=out["Z"], k=np.array([x.k_out for x in infos]),
+                         status=np.array([x.status for x in infos]), a_norm=np.array([x.a_norm for x in infos]),
+                         r22_norm=np.array([x.r22_norm for x in infos]), kmax_b=out["kmax_b"],
+                         j_off=out["j_off_h"], z_off=out["z_off_h"], n=out["n_h"])
 
 
 def id_backward(*args, **kwargs):
