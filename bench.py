@@ -197,6 +197,34 @@ def main() -> int:
         extra["batched_GBps_blocks"] = round(blocks.A.size * 4 / (kms * 1e-3) / 1e9, 1)
     log(f"[bench] batched {ms_b:.3f} ms = {extra['batched_ids_per_s']:.0f} IDs/s")
 
+    # differentiable ID: forward (FP32 ID, k = 128) + adjoint on 2048 x 8192
+    log("[bench] ID forward + adjoint, 2048 x 8192, k = 128, FP32")
+    A5 = idgen.lowrank_plus_noise_device(5, 2048, 8192, np.exp(-np.arange(2048) / 32.0), 1e-6,
+                                         dtype=torch.float32)
+    g5 = torch.Generator(device="cuda")
+    g5.manual_seed(1005)
+    gC5 = torch.randn(128, 2048, generator=g5, device="cuda").t()
+    gZ5 = torch.randn(8192, 128, generator=g5, device="cuda").t()
+    r5 = miid.id(A5, k=128, want_R11=True)
+    for _ in range(args.warmup):
+        miid.id_backward(A5, r5.J, r5.R11, r5.Z, gC5, gZ5)
+    torch.cuda.synchronize()
+    lib.miid_prof_begin(1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        miid.id_backward(A5, r5.J, r5.R11, r5.Z, gC5, gZ5)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    recs5 = prof_records(lib)
+    extra["bwd_cfg5_ms"] = round((t1 - t0) * 1000.0 / args.steps, 4)
+    bg = [r for r in recs5 if r.kernel == 6]
+    if bg:
+        gms = sum(r.ms for r in bg) / len(bg)
+        flops = 2.0 * 2 * 2048 * 128 * 8192
+        extra["bwd_gemm_ms"] = round(gms, 4)
+        extra["bwd_gemm_TFLOPs"] = round(flops / (gms * 1e-3) / 1e12, 1)
+    log(f"[bench] adjoint {extra['bwd_cfg5_ms']} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle

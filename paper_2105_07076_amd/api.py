@@ -286,17 +286,49 @@ def batched(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64) -> Batched
                          j_off=out["j_off_h"], z_off=out["z_off_h"], n=out["n_h"])
 
 
-def id_backward(*args, **kwargs):
-    raise NotImplementedError("id_backward is not built yet")
+def id_backward(A: torch.Tensor, J: torch.Tensor, R11: torch.Tensor, Z: torch.Tensor,
+                gC: torch.Tensor | None, gZ: torch.Tensor | None) -> torch.Tensor:
+    """Gradient of a loss on (C, Z) with respect to A, pivots J fixed
+    (C = A[:, J], Z = C^+ A).  R11 (k x k FP64) and Z come from the forward
+    :func:`id` of the same A.  Enqueued on the current stream."""
+    lib = _abi.load()
+    if A.dtype not in _DT or not A.is_cuda:
+        raise TypeError("A must be a float32/float64 CUDA tensor")
+    A = colmajor(A)
+    m, n = A.shape
+    k = int(J.numel())
+    J = J.to(torch.int32).contiguous()
+    R11 = colmajor(R11.to(torch.float64))
+    Z = colmajor(Z.to(A.dtype))
+    gCc = colmajor(gC.to(A.dtype)) if gC is not None else None
+    gZc = colmajor(gZ.to(A.dtype)) if gZ is not None else None
+    dt = _DT[A.dtype]
+    ws_bytes = lib.miid_backward_workspace(m, n, k, dt)
+    if ws_bytes == 0:
+        _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_backward_workspace")
+    ws = _WS.get("bwd", ws_bytes, A.device)
+    gA = empty_colmajor(m, n, A.dtype, A.device)
+    rc = lib.id_backward(_ptr(A), m, n, _ld(A), dt, _ptr(J), k, _ptr(R11), _ld(R11), _ptr(Z), _ld(Z),
+                         _ptr(gCc), _ld(gCc) if gCc is not None else 1, _ptr(gZc), _ld(gZc) if gZc is not None else 1,
+                         _ptr(gA), _ld(gA), _ptr(ws), ws_bytes, _stream())
+    _abi.check(rc, "id_backward")
+    return gA
 
 
 class IDFunction(torch.autograd.Function):
-    """(C, Z) = ID(A) with the pivots fixed in the forward pass."""
+    """(C, Z) = ID(A) at rank k with the pivots fixed in the forward pass;
+    the backward pass runs id_backward.  A is m x n with m <= n."""
 
     @staticmethod
-    def forward(ctx, A, k):  # pragma: no cover - filled in with id_backward
-        raise NotImplementedError
+    def forward(ctx, A, k):
+        r = id(A.detach(), k=int(k), want_C=True, want_R11=True)
+        if r.transposed:
+            raise ValueError("IDFunction needs m <= n")
+        ctx.save_for_backward(A.detach(), r.J, r.R11, r.Z)
+        return r.C, r.Z
 
     @staticmethod
-    def backward(ctx, gC, gZ):  # pragma: no cover
-        raise NotImplementedError
+    def backward(ctx, gC, gZ):
+        A, J, R11, Z = ctx.saved_tensors
+        gA = id_backward(A, J, R11, Z, gC, gZ)
+        return gA, None
