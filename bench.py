@@ -99,7 +99,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing on the host")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--only", default="all",
+                    help="comma list of sections to run: id64,id32,rid,batched,bwd (default all); "
+                         "the value is the FP64 ID, so id64 always runs")
     args = ap.parse_args()
+    only = set(args.only.split(",")) if args.only != "all" else {"id64", "id32", "rid", "batched", "bwd"}
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the ID hot path is built for a single MI355X "
               "(multi-GPU sharding is described in DESIGN.md, not implemented).", file=sys.stderr)
@@ -125,13 +129,14 @@ def main() -> int:
     log(f"[bench] FP64 ID {ms64:.3f} ms; GEMV {roof['achieved'] if roof else None} GB/s")
 
     extra = {}
-    log("[bench] FP32 ID")
     A32 = A64.to(torch.float32)
-    ms32, recs32, out32 = time_id(miid_api, lib, A32, k, args.steps, args.warmup)
-    r32 = gemv_roofline(recs32, 4)
-    extra["id_fp32_ms"] = round(ms32, 4)
-    extra["id_fp32_gemv_GBps"] = r32["achieved"] if r32 else None
-    extra["id_fp32_gemv_frac"] = r32["frac"] if r32 else None
+    if "id32" in only:
+        log("[bench] FP32 ID")
+        ms32, recs32, out32 = time_id(miid_api, lib, A32, k, args.steps, args.warmup)
+        r32 = gemv_roofline(recs32, 4)
+        extra["id_fp32_ms"] = round(ms32, 4)
+        extra["id_fp32_gemv_GBps"] = r32["achieved"] if r32 else None
+        extra["id_fp32_gemv_frac"] = r32["frac"] if r32 else None
     info64 = miid_api._read_info(out64["info"])
     extra["id_fp64_k_out"] = info64.k_out
     extra["id_fp64_n_recompute"] = info64.n_recompute
@@ -145,85 +150,88 @@ def main() -> int:
     if piv:
         extra["id_fp64_pivot_col_ms"] = round(sum(r.ms for r in piv) / len(piv), 5)
 
-    # randomized ID (bfloat16 sketch on the matrix cores + FP32 CPQR of Y)
-    log("[bench] mixed RID (split bf16 sketch, l = k + 10)")
-    l = k + 10
-    Om = torch.tensor(idgen.omega_bf16(77, l, m), dtype=torch.bfloat16, device="cuda")
-    out_r = miid_api.rid_raw(A32, Om, k=k, mode=1)
-    for _ in range(args.warmup):
-        miid_api.rid_raw(A32, Om, k=k, mode=1, out=out_r)
-    torch.cuda.synchronize()
-    lib.miid_prof_begin(16)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        miid_api.rid_raw(A32, Om, k=k, mode=1, out=out_r)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    recs_r = prof_records(lib)
-    ms_rid = (t1 - t0) * 1000.0 / args.steps
-    extra["rid_mixed_ms"] = round(ms_rid, 4)
-    extra["rid_speedup_vs_fp64_id"] = round(ms64 / ms_rid, 2)
-    sk = [r for r in recs_r if r.kernel == 4]
-    if sk:
-        sk_ms = sum(r.ms for r in sk) / len(sk)
-        flops = 2.0 * 2 * l * m * n  # two bf16 passes (hi + lo)
-        extra["rid_sketch_ms"] = round(sk_ms, 4)
-        extra["rid_sketch_TFLOPs"] = round(flops / (sk_ms * 1e-3) / 1e12, 1)
-        extra["rid_sketch_GBps_A"] = round(m * n * 4 / (sk_ms * 1e-3) / 1e9, 1)
-    log(f"[bench] RID {ms_rid:.3f} ms")
+    if "rid" in only:
+        # randomized ID (bfloat16 sketch on the matrix cores + FP32 CPQR of Y)
+        log("[bench] mixed RID (split bf16 sketch, l = k + 10)")
+        l = k + 10
+        Om = torch.tensor(idgen.omega_bf16(77, l, m), dtype=torch.bfloat16, device="cuda")
+        out_r = miid_api.rid_raw(A32, Om, k=k, mode=1)
+        for _ in range(args.warmup):
+            miid_api.rid_raw(A32, Om, k=k, mode=1, out=out_r)
+        torch.cuda.synchronize()
+        lib.miid_prof_begin(16)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            miid_api.rid_raw(A32, Om, k=k, mode=1, out=out_r)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        recs_r = prof_records(lib)
+        ms_rid = (t1 - t0) * 1000.0 / args.steps
+        extra["rid_mixed_ms"] = round(ms_rid, 4)
+        extra["rid_speedup_vs_fp64_id"] = round(ms64 / ms_rid, 2)
+        sk = [r for r in recs_r if r.kernel == 4]
+        if sk:
+            sk_ms = sum(r.ms for r in sk) / len(sk)
+            flops = 2.0 * 2 * l * m * n  # two bf16 passes (hi + lo)
+            extra["rid_sketch_ms"] = round(sk_ms, 4)
+            extra["rid_sketch_TFLOPs"] = round(flops / (sk_ms * 1e-3) / 1e12, 1)
+            extra["rid_sketch_GBps_A"] = round(m * n * 4 / (sk_ms * 1e-3) / 1e9, 1)
+        log(f"[bench] RID {ms_rid:.3f} ms")
 
-    # batched IDs: 4096 kernel-matrix blocks, tolerance 1e-6, FP32, one launch
-    log("[bench] batched IDs (4096 blocks, eps = 1e-6)")
-    blocks = idgen.batched_blocks(seed=4, nblk=4096)
-    Ab = torch.tensor(blocks.A, dtype=torch.float32, device="cuda")
-    out_b = miid_api.batched_raw(Ab, blocks.a_off, blocks.m, blocks.n, 1e-6, 64)
-    for _ in range(args.warmup):
-        miid_api.batched_raw(Ab, blocks.a_off, blocks.m, blocks.n, 1e-6, 64, out=out_b)
-    torch.cuda.synchronize()
-    lib.miid_prof_begin(1)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        miid_api.batched_raw(Ab, blocks.a_off, blocks.m, blocks.n, 1e-6, 64, out=out_b)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    recs_b = prof_records(lib)
-    ms_b = (t1 - t0) * 1000.0 / args.steps
-    extra["batched_ms"] = round(ms_b, 4)
-    extra["batched_ids_per_s"] = round(4096 / (ms_b * 1e-3), 1)
-    kb = [r for r in recs_b if r.kernel == 5]
-    if kb:
-        kms = sum(r.ms for r in kb) / len(kb)
-        extra["batched_kernel_ms"] = round(kms, 4)
-        extra["batched_GBps_blocks"] = round(blocks.A.size * 4 / (kms * 1e-3) / 1e9, 1)
-    log(f"[bench] batched {ms_b:.3f} ms = {extra['batched_ids_per_s']:.0f} IDs/s")
+    if "batched" in only:
+        # batched IDs: 4096 kernel-matrix blocks, tolerance 1e-6, FP32, one launch
+        log("[bench] batched IDs (4096 blocks, eps = 1e-6)")
+        blocks = idgen.batched_blocks(seed=4, nblk=4096)
+        Ab = torch.tensor(blocks.A, dtype=torch.float32, device="cuda")
+        out_b = miid_api.batched_raw(Ab, blocks.a_off, blocks.m, blocks.n, 1e-6, 64)
+        for _ in range(args.warmup):
+            miid_api.batched_raw(Ab, blocks.a_off, blocks.m, blocks.n, 1e-6, 64, out=out_b)
+        torch.cuda.synchronize()
+        lib.miid_prof_begin(1)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            miid_api.batched_raw(Ab, blocks.a_off, blocks.m, blocks.n, 1e-6, 64, out=out_b)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        recs_b = prof_records(lib)
+        ms_b = (t1 - t0) * 1000.0 / args.steps
+        extra["batched_ms"] = round(ms_b, 4)
+        extra["batched_ids_per_s"] = round(4096 / (ms_b * 1e-3), 1)
+        kb = [r for r in recs_b if r.kernel == 5]
+        if kb:
+            kms = sum(r.ms for r in kb) / len(kb)
+            extra["batched_kernel_ms"] = round(kms, 4)
+            extra["batched_GBps_blocks"] = round(blocks.A.size * 4 / (kms * 1e-3) / 1e9, 1)
+        log(f"[bench] batched {ms_b:.3f} ms = {extra['batched_ids_per_s']:.0f} IDs/s")
 
-    # differentiable ID: forward (FP32 ID, k = 128) + adjoint on 2048 x 8192
-    log("[bench] ID forward + adjoint, 2048 x 8192, k = 128, FP32")
-    A5 = idgen.lowrank_plus_noise_device(5, 2048, 8192, np.exp(-np.arange(2048) / 32.0), 1e-6,
-                                         dtype=torch.float32)
-    g5 = torch.Generator(device="cuda")
-    g5.manual_seed(1005)
-    gC5 = torch.randn(128, 2048, generator=g5, device="cuda").t()
-    gZ5 = torch.randn(8192, 128, generator=g5, device="cuda").t()
-    r5 = miid.id(A5, k=128, want_R11=True)
-    for _ in range(args.warmup):
-        miid.id_backward(A5, r5.J, r5.R11, r5.Z, gC5, gZ5)
-    torch.cuda.synchronize()
-    lib.miid_prof_begin(1)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        miid.id_backward(A5, r5.J, r5.R11, r5.Z, gC5, gZ5)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    recs5 = prof_records(lib)
-    extra["bwd_cfg5_ms"] = round((t1 - t0) * 1000.0 / args.steps, 4)
-    bg = [r for r in recs5 if r.kernel == 6]
-    if bg:
-        gms = sum(r.ms for r in bg) / len(bg)
-        flops = 2.0 * 2 * 2048 * 128 * 8192
-        extra["bwd_gemm_ms"] = round(gms, 4)
-        extra["bwd_gemm_TFLOPs"] = round(flops / (gms * 1e-3) / 1e12, 1)
-    log(f"[bench] adjoint {extra['bwd_cfg5_ms']} ms")
+    if "bwd" in only:
+        # differentiable ID: forward (FP32 ID, k = 128) + adjoint on 2048 x 8192
+        log("[bench] ID forward + adjoint, 2048 x 8192, k = 128, FP32")
+        A5 = idgen.lowrank_plus_noise_device(5, 2048, 8192, np.exp(-np.arange(2048) / 32.0), 1e-6,
+                                             dtype=torch.float32)
+        g5 = torch.Generator(device="cuda")
+        g5.manual_seed(1005)
+        gC5 = torch.randn(128, 2048, generator=g5, device="cuda").t()
+        gZ5 = torch.randn(8192, 128, generator=g5, device="cuda").t()
+        r5 = miid.id(A5, k=128, want_R11=True)
+        for _ in range(args.warmup):
+            miid.id_backward(A5, r5.J, r5.R11, r5.Z, gC5, gZ5)
+        torch.cuda.synchronize()
+        lib.miid_prof_begin(1)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            miid.id_backward(A5, r5.J, r5.R11, r5.Z, gC5, gZ5)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        recs5 = prof_records(lib)
+        extra["bwd_cfg5_ms"] = round((t1 - t0) * 1000.0 / args.steps, 4)
+        bg = [r for r in recs5 if r.kernel == 6]
+        if bg:
+            gms = sum(r.ms for r in bg) / args.steps   # C M and A M^T per call
+            flops = 2.0 * 2 * 2048 * 128 * 8192
+            extra["bwd_gemm_ms"] = round(gms, 4)
+            extra["bwd_gemm_TFLOPs"] = round(flops / (gms * 1e-3) / 1e12, 1)
+        log(f"[bench] adjoint {extra['bwd_cfg5_ms']} ms")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -276,14 +276,14 @@ static int run_bw(const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* 
                        s, A, lda, m, J, C);
     hipLaunchKernelGGL(k_bw_solve<T>, dim3((unsigned)((n + 15) / 16)), dim3(kBwThreads), (size_t)k * 16 * 8, s, gZ,
                        ldgz, n, k, R11, ldr, sel, M);
-    const int pr = prof_open(MIID_K_BWD_GEMM, 0, m, n, s);
+    int pr = prof_take(MIID_K_BWD_GEMM, 0, m, n);
     // gA = C M  (J columns come out zero: M[:, J] = 0)
-    hipLaunchKernelGGL(k_bw_gemm_nn<T>, dim3((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64)), dim3(kBwThreads),
+    MIID_LAUNCH(pr, k_bw_gemm_nn<T>, dim3((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64)), dim3(kBwThreads),
                        0, s, C, m, M, (int64_t)k, gA, ldga, m, n, k);
     // P = A M^T (m x k), split over n
-    hipLaunchKernelGGL(k_bw_gemm_nt<T>, dim3((unsigned)((m + 63) / 64), (unsigned)((k + 63) / 64), (unsigned)B.nz),
-                       dim3(kBwThreads), 0, s, A, lda, M, (int64_t)k, part, m, (int64_t)k, n);
-    prof_close(pr, s);
+    pr = prof_take(MIID_K_BWD_GEMM, 0, m, n);
+    MIID_LAUNCH(pr, k_bw_gemm_nt<T>, dim3((unsigned)((m + 63) / 64), (unsigned)((k + 63) / 64), (unsigned)B.nz),
+                dim3(kBwThreads), 0, s, A, lda, M, (int64_t)k, part, m, (int64_t)k, n);
     hipLaunchKernelGGL(k_bw_reduce<T>, dim3((unsigned)std::min<int64_t>((m * k + 255) / 256, 4096)), dim3(256), 0, s,
                        part, B.nz, m * k, P);
     // Q = Z M^T (k x k), split over n

@@ -370,17 +370,16 @@ int id_batched(int32_t nblk, const void* A, const int64_t* a_off, const int32_t*
     } else {
         hipLaunchKernelGGL(k_iota, dim3(64), dim3(256), 0, s, order, nblk, queue);
     }
-    const int pr = prof_open(MIID_K_BATCHED, 0, nblk, 0, s);
+    const int pr = prof_take(MIID_K_BATCHED, 0, nblk, 0);
     if (dtype == MIID_F64) {
-        hipLaunchKernelGGL(k_batched<double>, dim3(P.grid), dim3(kBThreads), 0, s, (const double*)A, a_off, m, n,
+        MIID_LAUNCH(pr, k_batched<double>, dim3(P.grid), dim3(kBThreads), 0, s, (const double*)A, a_off, m, n,
                            nblk, eps, kmax, J, j_off, (double*)Z, z_off, info, order, queue,
                            reinterpret_cast<double*>(w + P.oSlab), P.slab_elems);
     } else {
-        hipLaunchKernelGGL(k_batched<float>, dim3(P.grid), dim3(kBThreads), 0, s, (const float*)A, a_off, m, n, nblk,
+        MIID_LAUNCH(pr, k_batched<float>, dim3(P.grid), dim3(kBThreads), 0, s, (const float*)A, a_off, m, n, nblk,
                            eps, kmax, J, j_off, (float*)Z, z_off, info, order, queue,
                            reinterpret_cast<float*>(w + P.oSlab), P.slab_elems);
     }
-    prof_close(pr, s);
     MIID_HIP(hipGetLastError());
     return 0;
 }

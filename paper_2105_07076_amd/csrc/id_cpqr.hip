@@ -866,33 +866,30 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
     for (int j = 0; j < P.kmax; ++j) {
         const int jb = (j / nb) * nb;
         const int i = j - jb;
-        int pr = prof_open(MIID_K_PIVOT, j, m - j, 1, stream);
-        hipLaunchKernelGGL(k_pivot_col<T>, dim3(P.NA), dim3(kThreads), 0, stream, S, ldw, m, V, F, nb, u, part,
-                           P.npart, partA, st, J, j, i, (int)P.tol, P.eps);
-        prof_close(pr, stream);
-        pr = prof_open(MIID_K_GEMV, j, m - j, n - j, stream);
+        int pr = prof_take(MIID_K_PIVOT, j, m - j, 1);
+        MIID_LAUNCH(pr, k_pivot_col<T>, dim3(P.NA), dim3(kThreads), 0, stream, S, ldw, m, V, F, nb, u, part,
+                    P.npart, partA, st, J, j, i, (int)P.tol, P.eps);
+        pr = prof_take(MIID_K_GEMV, j, m - j, n - j);
         switch (P.cpw) {
             case 4:
-                hipLaunchKernelGGL((k_gemv<T, 4>), dim3(P.npart), dim3(kThreads), 0, stream, S, ldw, m, n, V, F, nb,
-                                   u, partA, P.NA, st, J, R, nu, nuref, sel, part, recomp, j, i, tol);
+                MIID_LAUNCH(pr, (k_gemv<T, 4>), dim3(P.npart), dim3(kThreads), 0, stream, S, ldw, m, n, V, F, nb, u,
+                            partA, P.NA, st, J, R, nu, nuref, sel, part, recomp, j, i, tol);
                 break;
             case 2:
-                hipLaunchKernelGGL((k_gemv<T, 2>), dim3(P.npart), dim3(kThreads), 0, stream, S, ldw, m, n, V, F, nb,
-                                   u, partA, P.NA, st, J, R, nu, nuref, sel, part, recomp, j, i, tol);
+                MIID_LAUNCH(pr, (k_gemv<T, 2>), dim3(P.npart), dim3(kThreads), 0, stream, S, ldw, m, n, V, F, nb, u,
+                            partA, P.NA, st, J, R, nu, nuref, sel, part, recomp, j, i, tol);
                 break;
             default:
-                hipLaunchKernelGGL((k_gemv<T, 1>), dim3(P.npart), dim3(kThreads), 0, stream, S, ldw, m, n, V, F, nb,
-                                   u, partA, P.NA, st, J, R, nu, nuref, sel, part, recomp, j, i, tol);
+                MIID_LAUNCH(pr, (k_gemv<T, 1>), dim3(P.npart), dim3(kThreads), 0, stream, S, ldw, m, n, V, F, nb, u,
+                            partA, P.NA, st, J, R, nu, nuref, sel, part, recomp, j, i, tol);
         }
-        prof_close(pr, stream);
         const bool panel_end = (i == nb - 1);
         if (panel_end && j + 1 < P.kmax) {
             const int64_t r0 = j + 1;
             const int64_t rbase = r0 & ~(int64_t)63;
             dim3 grid((unsigned)((ldw - rbase + 63) / 64), (unsigned)((n + 63) / 64));
-            pr = prof_open(MIID_K_TRAIL, j / nb, m - r0, n, stream);
-            hipLaunchKernelGGL(k_trail<T>, grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
-            prof_close(pr, stream);
+            pr = prof_take(MIID_K_TRAIL, j / nb, m - r0, n);
+            MIID_LAUNCH(pr, k_trail<T>, grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
         }
         if (P.tol && (j % 8 == 7) && j + 1 < P.kmax) {
             MIID_HIP(hipMemcpyAsync(&host_stop, &st->stop, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
@@ -910,17 +907,16 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
         const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
         hipLaunchKernelGGL(k_gather_r11<T>, dim3(blocks), dim3(256), 0, stream, R, n, J, P.kmax, st, ksteps, R11s,
                            R11out, ldr);
-        const int pr = prof_open(MIID_K_TRSM, 0, P.kmax, n, stream);
+        const int pr = prof_take(MIID_K_TRSM, 0, P.kmax, n);
         if (P.kmax <= 512) {
             const size_t lds = (size_t)2 * P.kmax * 16 * 8;
-            hipLaunchKernelGGL((k_trsm<T, 16>), dim3((unsigned)((n + 15) / 16)), dim3(kThreads), lds, stream, R, n,
+            MIID_LAUNCH(pr, (k_trsm<T, 16>), dim3((unsigned)((n + 15) / 16)), dim3(kThreads), lds, stream, R, n,
                                R11s, P.kmax, st, ksteps, sel, Z, ldz, (int)P.refine);
         } else {
             const size_t lds = (size_t)2 * P.kmax * 8 * 8;
-            hipLaunchKernelGGL((k_trsm<T, 8>), dim3((unsigned)((n + 7) / 8)), dim3(kThreads), lds, stream, R, n, R11s,
+            MIID_LAUNCH(pr, (k_trsm<T, 8>), dim3((unsigned)((n + 7) / 8)), dim3(kThreads), lds, stream, R, n, R11s,
                                P.kmax, st, ksteps, sel, Z, ldz, (int)P.refine);
         }
-        prof_close(pr, stream);
     }
     // a10: C, info
     if (C) {

@@ -1,7 +1,13 @@
-// prof.hpp -- optional kernel timing with HIP events on the launch stream.
-// Enabled by miid_prof_begin(); a sampled launch is bracketed by two events
-// recorded on the stream it runs on, so the elapsed time is that kernel's.
+// prof.hpp -- optional kernel timing with HIP events.  A sampled launch is
+// preceded by an empty marker kernel whose dispatch carries the start event
+// (stamped when the marker ends, i.e. after everything before it on the
+// stream has finished) and is itself launched through hipExtLaunchKernelGGL
+// with the stop event; the elapsed time is the kernel's execution plus one
+// inter-kernel gap.  (An event carried by the timed dispatch itself is stamped
+// when the command processor takes the packet, which can be while the
+// previous kernel still runs.)
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -27,8 +33,8 @@ inline ProfState& prof_state() {
 }
 
 // Returns a slot index when launch number `step` of `kernel` is sampled,
-// else -1.  The start event is recorded on `stream` before the launch.
-inline int prof_open(int32_t kernel, int32_t step, int64_t rows, int64_t cols, hipStream_t stream) {
+// else -1.
+inline int prof_take(int32_t kernel, int32_t step, int64_t rows, int64_t cols) {
     ProfState& s = prof_state();
     if (s.every <= 0 || (step % s.every) != 0 || s.used.size() >= 65536) return -1;
     ProfSlot slot;
@@ -36,20 +42,29 @@ inline int prof_open(int32_t kernel, int32_t step, int64_t rows, int64_t cols, h
         slot = s.pool.back();
         s.pool.pop_back();
     } else {
-        // no system-scope release on record: the events must not flush the
-        // caches the timed kernel would otherwise find warm
-        if (hipEventCreateWithFlags(&slot.a, hipEventDisableSystemFence) != hipSuccess) return -1;
-        if (hipEventCreateWithFlags(&slot.b, hipEventDisableSystemFence) != hipSuccess) return -1;
+        if (hipEventCreate(&slot.a) != hipSuccess) return -1;
+        if (hipEventCreate(&slot.b) != hipSuccess) return -1;
     }
     slot.rec = miid_prof_record{kernel, step, rows, cols, 0.0f};
-    hipEventRecord(slot.a, stream);
     s.used.push_back(slot);
     return (int)s.used.size() - 1;
 }
 
-// Records the end event of slot `idx` (after the launch).
-inline void prof_close(int idx, hipStream_t stream) {
-    if (idx >= 0) hipEventRecord(prof_state().used[idx].b, stream);
-}
+inline hipEvent_t prof_a(int slot) { return prof_state().used[slot].a; }
+
+__global__ void k_prof_marker(int);
+inline hipEvent_t prof_b(int slot) { return prof_state().used[slot].b; }
 
 }  // namespace miid
+
+// Launch `K` (parenthesise template kernels) plainly, or with the timing
+// events of profiling slot `SLOT` when it is sampled.
+#define MIID_LAUNCH(SLOT, K, GRID, BLOCK, SHMEM, STREAM, ...)                                                   \
+    do {                                                                                                        \
+        if ((SLOT) >= 0) {                                                                                      \
+            hipExtLaunchKernelGGL(::miid::k_prof_marker, dim3(1), dim3(64), 0, STREAM, nullptr,                 \
+                                  ::miid::prof_a(SLOT), 0, 0);                                                  \
+            hipExtLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, nullptr, ::miid::prof_b(SLOT), 0, __VA_ARGS__); \
+        } else                                                                                                  \
+            hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                                     \
+    } while (0)

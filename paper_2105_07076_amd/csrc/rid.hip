@@ -213,23 +213,22 @@ int rid_sketch_cpqr(const float* A, int64_t m, int64_t n, int64_t lda, const uin
     {
         dim3 grid((unsigned)((n + kSkCols - 1) / kSkCols), (unsigned)((R.mt_total + kSkMTB - 1) / kSkMTB));
         const bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-        const int pr = prof_open(MIID_K_SKETCH, 0, m, n, s);
+        const int pr = prof_take(MIID_K_SKETCH, 0, m, n);
         if (mode == 1) {
             if (vec)
-                hipLaunchKernelGGL((k_sketch<true, true>), grid, dim3(kSkThreads), 0, s, A, lda, m, n, Wt, R.mpad,
+                MIID_LAUNCH(pr, (k_sketch<true, true>), grid, dim3(kSkThreads), 0, s, A, lda, m, n, Wt, R.mpad,
                                    R.mt_total, S, ldw, Y, ldy, l);
             else
-                hipLaunchKernelGGL((k_sketch<true, false>), grid, dim3(kSkThreads), 0, s, A, lda, m, n, Wt, R.mpad,
+                MIID_LAUNCH(pr, (k_sketch<true, false>), grid, dim3(kSkThreads), 0, s, A, lda, m, n, Wt, R.mpad,
                                    R.mt_total, S, ldw, Y, ldy, l);
         } else {
             if (vec)
-                hipLaunchKernelGGL((k_sketch<false, true>), grid, dim3(kSkThreads), 0, s, A, lda, m, n, Wt, R.mpad,
+                MIID_LAUNCH(pr, (k_sketch<false, true>), grid, dim3(kSkThreads), 0, s, A, lda, m, n, Wt, R.mpad,
                                    R.mt_total, S, ldw, Y, ldy, l);
             else
-                hipLaunchKernelGGL((k_sketch<false, false>), grid, dim3(kSkThreads), 0, s, A, lda, m, n, Wt, R.mpad,
+                MIID_LAUNCH(pr, (k_sketch<false, false>), grid, dim3(kSkThreads), 0, s, A, lda, m, n, Wt, R.mpad,
                                    R.mt_total, S, ldw, Y, ldy, l);
         }
-        prof_close(pr, s);
     }
     MIID_HIP(hipGetLastError());
     return run_id<float>(R.id, A, lda, J, Z, ldz, R11, ldr, C, ldc, info, w, s, true, A, lda, m);

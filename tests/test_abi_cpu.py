@@ -1,0 +1,100 @@
+"""CPU checks of the C ABI: the built library loads without a GPU, exports
+every function include/miid.h declares, its struct layouts match the ctypes
+mirrors, and argument validation returns the documented codes before any
+device work (no compute calls are made here)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "miid.h")
+
+
+def _lib():
+    from paper_2105_07076_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_2105_07076_amd import build
+        build.build()
+    return _abi, _abi.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for must in ["id_cpqr", "rid_sketch_cpqr", "id_batched", "id_backward"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    _abi, lib = _lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", _abi.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\sT\s+(\S+)", out))
+    missing = [n for n in _declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in _declared_functions():
+        assert hasattr(lib, n)
+    assert set(_abi.EXPORTED) <= exported
+
+
+def test_struct_layouts():
+    _abi, _ = _lib()
+    assert ctypes.sizeof(_abi.MiidOpts) == 24
+    assert ctypes.sizeof(_abi.MiidInfo) == 32
+    assert _abi.MiidInfo.r22_norm.offset == 16
+
+
+def test_version_string():
+    _, lib = _lib()
+    assert lib.miid_version().startswith(b"miid")
+
+
+def test_argument_validation_before_any_device_work():
+    _abi, lib = _lib()
+    o = _abi.MiidOpts()
+    o.k = 4
+    P = ctypes.c_void_p
+    dummy = P(0x1000)  # never dereferenced: validation fails first
+    # A null -> -1
+    assert lib.id_cpqr(None, 10, 20, 10, 1, ctypes.byref(o), dummy, dummy, 4, None, 1, None, 1, dummy, dummy,
+                       1 << 30, None) == -1
+    # lda < m -> -4
+    assert lib.id_cpqr(dummy, 10, 20, 9, 1, ctypes.byref(o), dummy, dummy, 4, None, 1, None, 1, dummy, dummy,
+                       1 << 30, None) == -4
+    # bad dtype -> -5
+    assert lib.id_cpqr(dummy, 10, 20, 10, 7, ctypes.byref(o), dummy, dummy, 4, None, 1, None, 1, dummy, dummy,
+                       1 << 30, None) == -5
+    # ldz < k -> -9
+    assert lib.id_cpqr(dummy, 10, 20, 10, 1, ctypes.byref(o), dummy, dummy, 3, None, 1, None, 1, dummy, dummy,
+                       1 << 30, None) == -9
+    # workspace too small
+    assert lib.id_cpqr(dummy, 10, 20, 10, 1, ctypes.byref(o), dummy, dummy, 4, None, 1, None, 1, dummy, dummy,
+                       16, None) == _abi.MIID_E_WORKSPACE
+    # k above min(m, n) -> unsupported
+    o.k = 11
+    assert lib.id_cpqr(dummy, 10, 20, 10, 1, ctypes.byref(o), dummy, dummy, 11, None, 1, None, 1, dummy, dummy,
+                       1 << 30, None) == _abi.MIID_E_UNSUPPORTED
+    assert lib.miid_id_workspace(10, 20, 1, ctypes.byref(o)) == 0
+    o.k = 4
+    assert lib.miid_id_workspace(10, 20, 1, ctypes.byref(o)) > 0
+    # randomized ID: m > n unsupported, bad mode -> -8
+    assert lib.rid_sketch_cpqr(dummy, 30, 20, 30, dummy, 8, 8, 1, ctypes.byref(o), dummy, dummy, 4, None, 1, None,
+                               1, None, 1, dummy, dummy, 1 << 30, None) == _abi.MIID_E_UNSUPPORTED
+    assert lib.rid_sketch_cpqr(dummy, 10, 20, 10, dummy, 8, 8, 2, ctypes.byref(o), dummy, dummy, 4, None, 1, None,
+                               1, None, 1, dummy, dummy, 1 << 30, None) == -8
+    # batched: kmax out of range -> -8
+    assert lib.id_batched(4, dummy, dummy, dummy, dummy, 0, 1e-6, 65, dummy, dummy, dummy, dummy, dummy, dummy,
+                          1 << 30, None) == -8
+    # backward: k > m -> -7
+    assert lib.id_backward(dummy, 10, 20, 10, 0, dummy, 11, dummy, 11, dummy, 11, None, 1, None, 1, dummy, 10,
+                           dummy, 1 << 30, None) == -7
