@@ -57,8 +57,11 @@ def _prof_record_type():
     return _PR
 
 
-def time_id(miid_api, lib, A, k, steps, warmup, sample_every=16):
-    """Time `steps` ID calls; sampled per-kernel HIP events in the same region."""
+def time_id(miid_api, lib, A, k, steps, warmup, sample_every=7):
+    """Time `steps` ID calls; sampled per-kernel HIP events in the same region.
+    The stride is coprime to the panel width so that the sampled pivot steps
+    cover every position inside a panel evenly (the first GEMV after a
+    trailing update is slower than the others)."""
     import torch
     out = miid_api.id_raw(A, k=k)
     for _ in range(warmup):
@@ -159,7 +162,7 @@ def main() -> int:
         for _ in range(args.warmup):
             miid_api.rid_raw(A32, Om, k=k, mode=1, out=out_r)
         torch.cuda.synchronize()
-        lib.miid_prof_begin(16)
+        lib.miid_prof_begin(7)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             miid_api.rid_raw(A32, Om, k=k, mode=1, out=out_r)

@@ -21,7 +21,11 @@ struct IdPlan {
     size_t esz;
     int cpw;   // columns per wave in the column passes (k_norms, k_gemv)
     int npart, NA;
+    // resident path (few rows): rows per lane, grid, columns per workgroup
+    bool res_ok;
+    int res_rpl, res_grid, res_cpb;
     size_t oS, oV, oF, ou, onu, onuref, oR, osel, opart, opartA, oR11, ostate, orec, total;
+    size_t oPart2, oPartF, oSlots, oBar;
 };
 
 // Validates the shape/options and lays out the workspace (returns 0 or a

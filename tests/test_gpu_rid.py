@@ -134,3 +134,50 @@ def test_rid_cfg2_full_size():
     e_gpu = oracle.error(A64, J, Z)
     e_ora = oracle.error(A64, ore.J, ore.Z)
     assert abs(e_gpu - e_ora) <= 1e-5 * e_ora
+
+
+def test_rid_resident_path(monkeypatch):
+    """The optional resident CPQR (MIID_RESIDENT=1: columns of Y held in LDS
+    in FP64, one grid barrier per step) on the reduced 1024 x 4096 workload
+    and a small ragged case."""
+    monkeypatch.setenv("MIID_RESIDENT", "1")
+    A, k = idgen.cfg2(m=1024, n=4096)
+    _check(A, k + 10, k, 1, e2e_tol=1e-5)
+    g = idgen.rng(11)
+    A2 = g.standard_normal((70, 333)) @ np.diag(0.97 ** np.arange(333))
+    _check(A2, 41, 30, 1)
+
+
+@pytest.mark.timeout(170)
+def test_rid_16384x65536_k512():
+    """The large randomized workload: A 16384 x 65536 FP32 (s_i = exp(-i/128),
+    4096 singular triplets, noise 1e-8), Omega 522 x 16384, k = 512, split
+    sketch.  Checked by properties that hold at this size: sampled sketch
+    entries against FP64 dot products; the CPQR stage against the oracle on
+    the GPU's own Y; the error on sampled columns between the spectrum's tail
+    (Eckart-Young) and a small multiple of it."""
+    miid = _miid()
+    m, n, l, k = 16384, 65536, 522, 512
+    A_t = idgen.lowrank_plus_noise_device(3, m, n, np.exp(-np.arange(4096) / 128.0), 1e-8, r=4096,
+                                          dtype=torch.float32)
+    Om = idgen.omega_bf16(78, l, m)
+    Om_t = torch.tensor(Om, dtype=torch.bfloat16, device="cuda")
+    r = miid.rid(A_t, Om_t, k=k, mode=1, want_Y=True)
+    torch.cuda.synchronize()
+    assert r.k == k
+    Y = to_np(r.Y).astype(np.float64)
+    g = idgen.rng(79)
+    cols = np.sort(g.choice(n, 256, replace=False))
+    Acols = A_t[:, torch.tensor(cols, device="cuda")].double().cpu().numpy()
+    Ys = Om.astype(np.float64) @ Acols
+    assert rel(Y[:, cols], Ys) <= SKETCH_TOL[1]
+    J = to_np(r.J)
+    Z = to_np(r.Z).astype(np.float64)
+    ref, ties = pivot_parity(Y, J, k, U32)
+    R11 = ref.R[:, ref.J]
+    bar = max(1e-5, 8.0 * U32 * np.linalg.cond(R11))
+    assert rel(t_part(Z, J), t_part(ref.Z, J)) <= bar
+    C = A_t[:, torch.tensor(J.astype(np.int64), device="cuda")].double().cpu().numpy()
+    err = np.linalg.norm(Acols - C @ Z[:, cols]) / np.linalg.norm(Acols)
+    tail = np.exp(-k / 128.0)
+    assert 0.5 * tail <= err <= 10.0 * tail, f"sampled relative error {err:.3e}, tail {tail:.3e}"
