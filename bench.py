@@ -79,6 +79,33 @@ def time_id(miid_api, lib, A, k, steps, warmup, sample_every=7):
     return ms, recs, out
 
 
+# HBM bytes per k_gemv<double> launch from the FETCH_SIZE / WRITE_SIZE counter
+# passes (scaled against a copy kernel of known size), valid only for the
+# kernel sources they were taken on.
+GEMV_TRAFFIC = {
+    "bytes_per_launch": 528.8e6,
+    "sources": {
+        "paper_2105_07076_amd/csrc/id_cpqr.hip": "d649bc4789caa2f582b2b0c855b6a2e974a33815d70265f3cf5e165993d6a54a",
+        "paper_2105_07076_amd/csrc/common.hpp": "3667dddd26f0fe4488a3519628c81272cffe7f158460fdb3c2a7882679b4564d",
+        "paper_2105_07076_amd/csrc/cpqr.hpp": "2141e9679dacc130355cf161968e90157a3db20b2c863bb60ddd122adfc1b186",
+    },
+}
+
+
+def gemv_traffic():
+    """The counted bytes per launch, or None if a source has changed since."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    for rel, digest in GEMV_TRAFFIC["sources"].items():
+        try:
+            with open(os.path.join(root, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
+        except OSError:
+            return None
+    return GEMV_TRAFFIC["bytes_per_launch"]
+
+
 def gemv_roofline(recs, esz):
     """Algorithmic bytes of the F-GEMV launch at step j: the stale trailing
     block (m - j) x (n - j) read once; achieved = bytes / event time."""
@@ -89,7 +116,7 @@ def gemv_roofline(recs, esz):
     ms = sum(r.ms for r in g)
     achieved = byts / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": gemv_traffic() if esz == 8 else None, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
             "kernel": "k_gemv (F-GEMV + row update + norm downdate)",
             "launches_sampled": len(g), "avg_launch_ms": round(ms / len(g), 5),
             "avg_algorithmic_bytes": int(byts / len(g))}
