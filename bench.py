@@ -206,6 +206,9 @@ def main() -> int:
             extra["rid_sketch_ms"] = round(sk_ms, 4)
             extra["rid_sketch_TFLOPs"] = round(flops / (sk_ms * 1e-3) / 1e12, 1)
             extra["rid_sketch_GBps_A"] = round(m * n * 4 / (sk_ms * 1e-3) / 1e9, 1)
+        stp = [r for r in recs_r if r.kernel == 8]
+        if stp:
+            extra["rid_cpqr_step_us"] = round(1000.0 * sum(r.ms for r in stp) / len(stp), 2)
         log(f"[bench] RID {ms_rid:.3f} ms")
 
     if "batched" in only:

@@ -84,6 +84,7 @@ typedef struct {
 #define MIID_K_BATCHED 5   /* persistent batched ID kernel                        */
 #define MIID_K_BWD_GEMM 6  /* adjoint GEMMs                                       */
 #define MIID_K_TRSM 7      /* triangular solve                                    */
+#define MIID_K_STEP 8      /* fused pivot step (matrices of <= 1024 rows)         */
 typedef struct {
     int32_t kernel; /* MIID_K_* */
     int32_t step;   /* launch index (pivot step for per-step kernels)     */

@@ -33,6 +33,65 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// Workgroup barrier that orders LDS only: global loads and stores issued
+// before it stay in flight (a plain __syncthreads also waits for them).  For
+// kernels whose threads exchange data through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Cross-lane moves within rows of 16 lanes through DPP (a VALU operand
+// modifier, no LDS crossbar round trip).  The four patterns used are
+// butterflies over a row: lane i pairs with i^1 and i^2 (quad permutes),
+// with 7-i within its half row and with 15-i within its row, so after the
+// four steps every lane of a row holds the combination of all sixteen.
+enum : int {
+    kDppXor1 = 0xB1,          // quad_perm [1,0,3,2]
+    kDppXor2 = 0x4E,          // quad_perm [2,3,0,1]
+    kDppHalfMirror = 0x141,   // row_half_mirror
+    kDppMirror = 0x140,       // row_mirror
+};
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int64_t b = __builtin_bit_cast(int64_t, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+
+// Sum over each row of 16 lanes; every lane of the row ends with the same
+// value (both partners of a step add the same two operands).
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    v += dpp_f64<kDppHalfMirror>(v);
+    v += dpp_f64<kDppMirror>(v);
+    return v;
+}
+
+// Sum over the wave: rows by DPP, then the four row sums read from lanes
+// 0, 16, 32, 48 in a fixed order (the result is wave-uniform).
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v = row16_sum(v);
+    double t = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t b = __builtin_bit_cast(int64_t, v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 16 * r);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * r);
+        t += __builtin_bit_cast(double, ((int64_t)hi << 32) | (uint32_t)lo);
+    }
+    return t;
+}
+
 // (value, index) pair ordered by larger value, then smaller index.
 struct ArgMax {
     double v;
@@ -41,6 +100,39 @@ struct ArgMax {
 
 __device__ __forceinline__ bool argmax_better(double va, int32_t ia, double vb, int32_t ib) {
     return va > vb || (va == vb && ia < ib);
+}
+
+template <int CTRL>
+__device__ __forceinline__ ArgMax argmax_step(ArgMax a) {
+    const double ov = dpp_f64<CTRL>(a.v);
+    const int32_t oi = dpp_i32<CTRL>(a.i);
+    if (argmax_better(ov, oi, a.v, a.i)) {
+        a.v = ov;
+        a.i = oi;
+    }
+    return a;
+}
+
+// Argmax over the wave: rows by DPP, then the four row winners in a fixed
+// order (wave-uniform result).
+__device__ __forceinline__ ArgMax wave_argmax_dpp(ArgMax a) {
+    a = argmax_step<kDppXor1>(a);
+    a = argmax_step<kDppXor2>(a);
+    a = argmax_step<kDppHalfMirror>(a);
+    a = argmax_step<kDppMirror>(a);
+    ArgMax b{-1.0, INT32_MAX};
+    bool first = true;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t bits = __builtin_bit_cast(int64_t, a.v);
+        const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffff), 16 * r);
+        const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), 16 * r);
+        const double v = __builtin_bit_cast(double, ((int64_t)hi << 32) | (uint32_t)lo);
+        const int32_t i = __builtin_amdgcn_readlane(a.i, 16 * r);
+        if (first || argmax_better(v, i, b.v, b.i)) b = {v, i};
+        first = false;
+    }
+    return b;
 }
 
 __device__ __forceinline__ ArgMax wave_argmax(ArgMax a) {

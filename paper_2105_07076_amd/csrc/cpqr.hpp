@@ -21,6 +21,10 @@ struct IdPlan {
     size_t esz;
     int cpw;   // columns per wave in the column passes (k_norms, k_gemv)
     int npart, NA;
+    // fused one-launch-per-step path (at most 1024 rows): NP passes of four
+    // columns per wave, fnpart workgroups
+    bool fused;
+    int fnp, fnpart, fgl;  // fgl: 16-byte row groups per lane (5, 9 or 16)
     // resident path (few rows): rows per lane, grid, columns per workgroup
     bool res_ok;
     int res_rpl, res_grid, res_cpb;

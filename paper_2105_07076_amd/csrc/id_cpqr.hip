@@ -485,6 +485,348 @@ __global__ void __launch_bounds__(kThreads) k_gemv(const T* __restrict__ S, int6
 }
 
 // ---------------------------------------------------------------------------
+// a2-a6 (+ a8) in one launch per step for short matrices (the sketch Y of the
+// randomized ID, short IDs: at most 576 rows in FP32, 288 in FP64, panels of
+// at most 32).  The working matrix then sits in the L2 caches and the step is
+// latency-bound: the separate pivot kernel's launch and its reduction over
+// thousands of partials cost more than the GEMV.  Here every workgroup (8
+// waves, one per CU)
+//   1. reduces the previous step's per-workgroup partials to the pivot p, the
+//      residual sum of squares and the stop decision, while the panel's V
+//      columns are staged into LDS and its first column chunk is in flight;
+//   2. forms the lazily updated pivot column u = S[:, p] - V F[p, :]^T and
+//      the reflector (identical in every workgroup: same inputs, same order);
+//   3. runs the F-GEMV over its own columns (16 lanes per column) and V^T v
+//      from LDS, then the row of R, the norm downdate and the exact recompute
+//      of flagged columns, and writes its partial.
+// The partials ping-pong between two buffers (step j reads buffer j & 1 and
+// writes the other), because every workgroup reads all of them.  Column
+// partition: workgroup b owns 32 NP consecutive columns, wave w the 4 NP
+// starting at 32 NP b + 4 NP w.
+// ---------------------------------------------------------------------------
+constexpr int kFusedWaves = 8;
+constexpr int kFusedThreads = kFusedWaves * kWave;
+constexpr int kFusedMaxNb = 32;
+constexpr int kFusedMaxRows = 576;
+
+// sum over the 16 lanes of a row group (every lane of the group ends with it)
+__device__ __forceinline__ double group16_sum(double v) { return row16_sum(v); }
+
+// One column's rows j0..ldw-1 as seen by lane l16 of its 16-lane group:
+// 16-byte groups l16, l16 + 16, ... (GL of them at most), loaded together.
+template <typename T, int GL>
+struct ColChunk {
+    using VT = typename Vec16<T>::type;
+    VT v[GL];
+    __device__ __forceinline__ void load(const T* base, int64_t ngroups, int l16) {
+#pragma unroll
+        for (int t = 0; t < GL; ++t) {
+            const int64_t g = l16 + 16 * t;
+            v[t] = (base && g < ngroups) ? reinterpret_cast<const VT*>(base)[g] : VT{};
+        }
+    }
+    // sum over this lane's rows of x_r * u_r (u in LDS, indexed from j0)
+    __device__ __forceinline__ double dot(const double* su, int64_t ngroups, int l16) const {
+        constexpr int VEC = Vec16<T>::n;
+        double a = 0.0;
+#pragma unroll
+        for (int t = 0; t < GL; ++t) {
+            const int64_t g = l16 + 16 * t;
+            if (g < ngroups) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) a += (double)get(v[t], e) * su[g * VEC + e];
+            }
+        }
+        return a;
+    }
+};
+
+template <typename T, int NP, int GL>
+__global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restrict__ S, int64_t ldw, int64_t m,
+                                                              int64_t n, T* __restrict__ V, T* __restrict__ F, int nb,
+                                                              const ColPartial* __restrict__ part_in,
+                                                              ColPartial* __restrict__ part_out, int npart,
+                                                              DevState* __restrict__ st, int32_t* __restrict__ J,
+                                                              T* __restrict__ R, double* __restrict__ nu,
+                                                              double* __restrict__ nuref, int32_t* __restrict__ sel,
+                                                              int32_t* __restrict__ recomp, int j, int i,
+                                                              int tol_mode, double eps, double tol) {
+    using VT = typename Vec16<T>::type;
+    constexpr int VEC = Vec16<T>::n;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sV = reinterpret_cast<T*>(smem_raw);  // V[:, 0:i], column q at sV + q ldw
+    __shared__ double s_u[kFusedMaxRows];
+    __shared__ double s_F[kFusedMaxNb], s_y[kFusedMaxNb], s_vj[kFusedMaxNb], s_g[kFusedMaxNb];
+    __shared__ double w_best[kFusedWaves], w_sum[kFusedWaves];
+    __shared__ int32_t w_idx[kFusedWaves], w_nf[kFusedWaves], w_nrec[kFusedWaves];
+    __shared__ double s_x0;
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
+    const int l16 = lane & 15, grp = lane >> 4;
+    const int wg = blockIdx.x;
+    const int stop_in = st->stop;
+    const double a_prev = st->a_norm;
+    const int64_t j0 = (int64_t)j & ~(int64_t)(VEC - 1);
+    const int64_t ngroups = (ldw - j0) / VEC;  // VEC-row groups from j0
+
+    // this wave's columns and their per-column data, independent of the pivot
+    int64_t col[NP];
+    bool in[NP];
+    double nuc[NP], nrf[NP], sjc[NP], fq[NP][kFusedMaxNb / 16];
+#pragma unroll
+    for (int ps = 0; ps < NP; ++ps) {
+        col[ps] = (int64_t)wg * 32 * NP + (int64_t)wave * 4 * NP + ps * 4 + grp;
+        in[ps] = col[ps] < n;
+        nuc[ps] = in[ps] ? nu[col[ps]] : -1.0;
+        const bool live = in[ps] && nuc[ps] >= 0.0;
+        nrf[ps] = live ? nuref[col[ps]] : 1.0;
+        sjc[ps] = live ? (double)S[col[ps] * ldw + j] : 0.0;
+#pragma unroll
+        for (int s = 0; s < kFusedMaxNb / 16; ++s) {
+            const int q = l16 + 16 * s;
+            fq[ps][s] = (live && q < i) ? (double)F[col[ps] * nb + q] : 0.0;
+        }
+    }
+    // the first two column chunks and V[:, 0:i] (GL 16-byte groups per
+    // thread at most: i ldw / VEC <= 32 * 16 GL) are in flight while the
+    // pivot is found
+    ColChunk<T, GL> buf[2];
+#pragma unroll
+    for (int ps = 0; ps < (NP < 2 ? NP : 2); ++ps)
+        buf[ps].load((in[ps] && nuc[ps] >= 0.0) ? S + col[ps] * ldw + j0 : nullptr, ngroups, l16);
+    const int64_t vtot = (ldw / VEC) * i;
+    VT vst[GL];
+#pragma unroll
+    for (int k = 0; k < GL; ++k) {
+        const int64_t e = tid + (int64_t)k * kFusedThreads;
+        vst[k] = e < vtot ? reinterpret_cast<const VT*>(V)[e] : VT{};
+    }
+
+    // 1. pivot from the previous step's partials
+    ArgMax best{-1.0, INT32_MAX};
+    double sumsq = 0.0;
+    int nf = 0;
+    for (int q = tid; q < npart; q += kFusedThreads) {
+        const ColPartial cp = part_in[q];
+        if (argmax_better(cp.best, cp.idx, best.v, best.i)) best = {cp.best, cp.idx};
+        sumsq += cp.sumsq;
+        nf |= cp.nonfinite;
+    }
+    if (stop_in) return;
+    best = wave_argmax_dpp(best);
+    sumsq = wave_sum_dpp(sumsq);
+    nf = __any(nf) ? 1 : 0;
+    if (lane == 0) {
+        w_best[wave] = best.v;
+        w_idx[wave] = best.i;
+        w_sum[wave] = sumsq;
+        w_nf[wave] = nf;
+    }
+    lds_barrier();
+    best = ArgMax{w_best[0], w_idx[0]};
+    sumsq = w_sum[0];
+    nf = w_nf[0];
+    for (int w = 1; w < kFusedWaves; ++w) {
+        if (argmax_better(w_best[w], w_idx[w], best.v, best.i)) best = {w_best[w], w_idx[w]};
+        sumsq += w_sum[w];
+        nf |= w_nf[w];
+    }
+    const double a_norm = (j == 0) ? sqrt(sumsq) : a_prev;
+    {
+        uint32_t status = 0;
+        bool stop = false;
+        if (nf) {
+            stop = true;
+            status = MIID_NONFINITE;
+        } else if (!(best.v > 0.0) || best.i == INT32_MAX) {
+            stop = true;
+            status = MIID_RANK_DEFICIENT;
+        } else if (tol_mode && sqrt(sumsq) <= eps * a_norm) {
+            stop = true;
+        }
+        if (wg == 0 && tid == 0) {
+            if (j == 0) st->a_norm = a_norm;
+            if (stop) {
+                st->k_out = j;
+                st->status |= status;
+                st->stop = 1;
+            } else {
+                J[j] = best.i;
+            }
+        }
+        if (stop) return;
+    }
+    const int64_t p = best.i;
+
+    // 2. u = S[:, p] - V F[p, :]^T (rows j..m-1), the reflector
+    const int64_t r0 = tid;
+    const double sp0 = (r0 >= j && r0 < m) ? (double)S[r0 + p * ldw] : 0.0;
+    if (tid < i) s_F[tid] = (double)F[p * nb + tid];
+#pragma unroll
+    for (int k = 0; k < GL; ++k) {
+        const int64_t e = tid + (int64_t)k * kFusedThreads;
+        if (e < vtot) reinterpret_cast<VT*>(sV)[e] = vst[k];
+    }
+    lds_barrier();  // s_F, sV (and the w_* reads above are done)
+    if (tid < i) s_vj[tid] = (double)sV[j + (int64_t)tid * ldw];
+    double ss = 0.0;
+    for (int64_t r = tid; r < ldw; r += kFusedThreads) {
+        double x = 0.0;
+        if (r >= j && r < m) {
+            x = r == r0 ? sp0 : (double)S[r + p * ldw];
+#pragma unroll 8
+            for (int q = 0; q < i; ++q) x -= (double)sV[r + (int64_t)q * ldw] * s_F[q];
+            x = (double)(T)x;
+        }
+        if (r == j) s_x0 = x;
+        s_u[r] = r > j ? x : 0.0;
+        ss += r > j ? x * x : 0.0;
+    }
+    ss = wave_sum_dpp(ss);
+    if (lane == 0) w_sum[wave] = ss;
+    lds_barrier();
+    const double x0 = s_x0;
+    double s0 = 0.0;
+    for (int w = 0; w < kFusedWaves; ++w) s0 += w_sum[w];
+    const double alpha = sqrt(x0 * x0 + s0);
+    if (!(alpha > 0.0)) {  // the pivot column vanished: rank(A) == j
+        if (wg == 0 && tid == 0) {
+            st->k_out = j;
+            st->status |= MIID_RANK_DEFICIENT;
+            st->stop = 1;
+        }
+        return;
+    }
+    const double beta = x0 >= 0.0 ? -alpha : alpha;
+    const double tau = (beta - x0) / beta;
+    const double scale = 1.0 / (x0 - beta);
+    if (wg == 0) {
+        for (int64_t r = tid; r < ldw; r += kFusedThreads)
+            V[r + (int64_t)i * ldw] = r < j ? T(0) : (r == j ? T(1) : (T)(s_u[r] * scale));
+        if (tid == 0) {
+            R[(int64_t)j * n + p] = (T)beta;
+            sel[p] = j;
+        }
+    }
+    if (tid == 0 && p / (32 * NP) == wg) nu[p] = -1.0;
+
+    // 3a. dots with u: the wave's NP columns (one chunk loaded ahead of the
+    // one in use), then V^T u from LDS (column q = 4 wave + group)
+    const double* su = s_u + j0;
+    double acc[NP];
+#pragma unroll
+    for (int ps = 0; ps < NP; ++ps) {
+        const bool alive = in[ps] && col[ps] != p && nuc[ps] >= 0.0;
+        acc[ps] = alive ? buf[ps & 1].dot(su, ngroups, l16) : 0.0;
+        if (ps + 2 < NP)
+            buf[ps & 1].load((in[ps + 2] && nuc[ps + 2] >= 0.0 && col[ps + 2] != p) ? S + col[ps + 2] * ldw + j0
+                                                                                   : nullptr,
+                             ngroups, l16);
+    }
+    {
+        const int q = 4 * wave + grp;
+        double a = 0.0;
+        if (q < i) {
+            const T* vq = sV + (int64_t)q * ldw + j0;
+            for (int64_t g = l16; g < ngroups; g += 16) {
+                const VT vv = *reinterpret_cast<const VT*>(vq + g * VEC);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) a += (double)get(vv, e) * su[g * VEC + e];
+            }
+        }
+        a = group16_sum(a);
+        if (q < i && l16 == 0) s_g[q] = a;
+    }
+#pragma unroll
+    for (int ps = 0; ps < NP; ++ps) acc[ps] = group16_sum(acc[ps]);
+    lds_barrier();
+    if (tid < i) s_y[tid] = s_vj[tid] + scale * s_g[tid];
+    lds_barrier();
+
+    // 3b. F column, row j of R, downdate / recompute, partials
+    ArgMax b2{-1.0, INT32_MAX};
+    double sum2 = 0.0;
+    int nrec = 0;
+#pragma unroll
+    for (int ps = 0; ps < NP; ++ps) {
+        const bool alive = in[ps] && col[ps] != p && nuc[ps] >= 0.0;
+        if (!alive) continue;  // uniform over the 16-lane group
+        double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+        for (int s = 0; s < kFusedMaxNb / 16; ++s) {
+            const int q = l16 + 16 * s;
+            if (q < i) {
+                t1 += fq[ps][s] * s_y[q];
+                t2 += fq[ps][s] * s_vj[q];
+            }
+        }
+        t1 = group16_sum(t1);
+        t2 = group16_sum(t2);
+        const double dot = sjc[ps] + scale * acc[ps];
+        const T fT = (T)(tau * (dot - t1));
+        const double f = (double)fT;
+        const double rjl = sjc[ps] - t2 - f;
+        if (l16 == 0) {
+            F[col[ps] * nb + i] = fT;
+            R[(int64_t)j * n + col[ps]] = (T)rjl;
+        }
+        double nnew = nuc[ps];
+        bool rec = false;
+        if (nuc[ps] > 0.0) {
+            double t = fabs(rjl) / nuc[ps];
+            t = fmax(0.0, (1.0 - t) * (1.0 + t));
+            const double ratio = nuc[ps] / nrf[ps];
+            if (t * ratio * ratio <= tol)
+                rec = true;
+            else
+                nnew = nuc[ps] * sqrt(t);
+        }
+        if (rec) {
+            // exact norm of the lazily updated column, rows j+1..m-1
+            double s2 = 0.0;
+            for (int64_t r = j + 1 + l16; r < m; r += 16) {
+                double x = (double)S[col[ps] * ldw + r] - scale * s_u[r] * f;
+                for (int q = 0; q < i; ++q) x -= (double)sV[r + (int64_t)q * ldw] * (double)F[col[ps] * nb + q];
+                s2 += x * x;
+            }
+            nnew = sqrt(group16_sum(s2));
+            if (l16 == 0) {
+                ++nrec;
+                nuref[col[ps]] = nnew;
+            }
+        }
+        if (l16 == 0) {
+            nu[col[ps]] = nnew;
+            if (argmax_better(nnew, (int32_t)col[ps], b2.v, b2.i)) b2 = {nnew, (int32_t)col[ps]};
+            sum2 += nnew * nnew;
+        }
+    }
+    b2 = wave_argmax_dpp(b2);
+    sum2 = wave_sum_dpp(sum2);
+    nrec = (int)wave_sum_dpp((double)nrec);
+    if (lane == 0) {
+        w_best[wave] = b2.v;
+        w_idx[wave] = b2.i;
+        w_sum[wave] = sum2;
+        w_nrec[wave] = nrec;
+    }
+    lds_barrier();
+    if (tid == 0) {
+        ArgMax b3{w_best[0], w_idx[0]};
+        double t = w_sum[0];
+        int nr = w_nrec[0];
+        for (int w = 1; w < kFusedWaves; ++w) {
+            if (argmax_better(w_best[w], w_idx[w], b3.v, b3.i)) b3 = {w_best[w], w_idx[w]};
+            t += w_sum[w];
+            nr += w_nrec[w];
+        }
+        part_out[wg] = ColPartial{b3.v, b3.i, 0, t, 0.0};
+        if (nr) recomp[wg] += nr;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // a7: trailing update at the end of a panel, S[r0:, :] -= V[r0:, 0:w] F[:, 0:w]^T,
 // on the matrix cores.  64 x 64 tile per workgroup, 32 x 32 per wave (2 x 2
 // blocks of 16 x 16), K = w in steps of 4 (v_mfma_{f64,f32}_16x16x4).
@@ -714,18 +1056,22 @@ __global__ void k_gather_c(const T* __restrict__ A, int64_t lda, int trans, int6
         C[r + (int64_t)cidx * ldc] = trans ? A[src + r * lda] : A[r + src * lda];
 }
 
+// part_alt > 0: the partials ping-pong between part and part + part_alt and
+// the last ones written after K steps are in the buffer of parity K; after
+// zero steps they are the npart0 partials of the norm pass.
 __global__ void k_finalize(const DevState* __restrict__ st, const ColPartial* __restrict__ part, int npart,
-                           const int32_t* __restrict__ recomp, int32_t* __restrict__ J, int kmax, int ksteps,
-                           int tol_mode, double eps, int trans, miid_info* __restrict__ info) {
+                           int part_alt, int npart0, const int32_t* __restrict__ recomp, int32_t* __restrict__ J,
+                           int kmax, int ksteps, int tol_mode, double eps, int trans, miid_info* __restrict__ info) {
     __shared__ double s_sum[kThreads];
     __shared__ int32_t s_rec[kThreads];
     const int t = threadIdx.x;
+    const int Kd = st->stop ? st->k_out : ksteps;
+    if (part_alt > 0 && (Kd & 1)) part += part_alt;
+    const int np = (part_alt > 0 && Kd == 0) ? npart0 : npart;
     double s = 0.0;
     int rc = 0;
-    for (int q = t; q < npart; q += kThreads) {
-        s += part[q].sumsq;
-        rc += recomp[q];
-    }
+    for (int q = t; q < np; q += kThreads) s += part[q].sumsq;
+    for (int q = t; q < npart; q += kThreads) rc += recomp[q];
     s_sum[t] = s;
     s_rec[t] = rc;
     __syncthreads();
@@ -1020,6 +1366,24 @@ static int gemv_cols_per_wave(int64_t) {
     return (v == 2 || v == 4) ? v : 1;
 }
 
+// The fused path is taken for matrices of at most kFusedMaxRows rows unless
+// MIID_FUSED=0; MIID_FUSED_NP (2, 4 or 8) overrides the columns per wave.
+static bool fused_enabled() {
+    const char* e = std::getenv("MIID_FUSED");
+    return !(e && e[0] == '0');
+}
+
+static int fused_np(int64_t n) {
+    const char* e = std::getenv("MIID_FUSED_NP");
+    if (e) {
+        const int v = std::atoi(e);
+        if (v == 1 || v == 2 || v == 4) return v;
+    }
+    for (int v = 1; v <= 4; v *= 2)
+        if (n <= (int64_t)256 * 32 * v) return v;  // one workgroup per CU
+    return 4;
+}
+
 int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan* P) {
     if (M < 1) return -2;
     if (N < 1) return -3;
@@ -1042,6 +1406,15 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
     P->cpw = gemv_cols_per_wave(P->m);
     P->npart = (int)((P->n + 4 * P->cpw - 1) / (4 * P->cpw));
     P->NA = (int)((P->ldw + kRowsPerChunk - 1) / kRowsPerChunk);
+    P->fnp = fused_np(P->n);
+    P->fnpart = (int)((P->n + 32 * P->fnp - 1) / (32 * P->fnp));
+    {
+        // 16-byte row groups per lane of a 16-lane column group
+        const int64_t ng = P->ldw * (int64_t)P->esz / 16;  // 16-byte groups in a column
+        const int64_t per_lane = (ng + 15) / 16;
+        P->fgl = per_lane <= 5 ? 5 : (per_lane <= 9 ? 9 : 0);
+    }
+    P->fused = P->ldw <= kFusedMaxRows && P->fgl > 0 && P->nb <= kFusedMaxNb && fused_enabled();
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o2 = off;
@@ -1056,11 +1429,11 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
     P->onuref = take((size_t)P->n * 8);
     P->oR = take((size_t)P->kmax * P->n * P->esz);
     P->osel = take((size_t)P->n * 4);
-    P->opart = take((size_t)P->npart * sizeof(ColPartial));
+    P->opart = take((size_t)std::max(P->npart, 16 * P->fnpart) * sizeof(ColPartial));
     P->opartA = take((size_t)P->NA * kPartAStride * 8);
     P->oR11 = take((size_t)P->kmax * P->kmax * 8);
     P->ostate = take(sizeof(DevState));
-    P->orec = take((size_t)P->npart * 4);
+    P->orec = take((size_t)std::max(P->npart, 8 * P->fnpart) * 4);
     // resident path: every workgroup holds ceil(n / grid) columns in LDS
     P->res_ok = false;
     P->res_rpl = P->m <= 320 ? 5 : (P->m <= 576 ? 9 : (P->m <= 1024 ? 16 : 0));
@@ -1136,6 +1509,51 @@ static hipError_t launch_resident(const IdPlan& P, T* S, T* R, int32_t* J, int32
     }
 }
 
+template <typename T, int NP, int GL>
+static hipError_t launch_fused_k(const IdPlan& P, int pr, hipStream_t stream, T* S, T* V, T* F, ColPartial* pin,
+                                 ColPartial* pout, int npin, DevState* st, int32_t* J, T* R, double* nu,
+                                 double* nuref, int32_t* sel, int32_t* recomp, int j, int i, double tol) {
+    static bool attr = false;
+    const size_t shmem = (size_t)P.ldw * kFusedMaxNb * P.esz;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_step_fused<T, NP, GL>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    MIID_LAUNCH(pr, (k_step_fused<T, NP, GL>), dim3(P.fnpart), dim3(kFusedThreads), shmem, stream, S, P.ldw, P.m,
+                P.n, V, F, P.nb, pin, pout, npin, st, J, R, nu, nuref, sel, recomp, j, i, (int)P.tol, P.eps, tol);
+    return hipGetLastError();
+}
+
+template <typename T, int NP>
+static hipError_t launch_fused_np(const IdPlan& P, int pr, hipStream_t stream, T* S, T* V, T* F, ColPartial* pin,
+                                  ColPartial* pout, int npin, DevState* st, int32_t* J, T* R, double* nu,
+                                  double* nuref, int32_t* sel, int32_t* recomp, int j, int i, double tol) {
+    if (P.fgl == 5)
+        return launch_fused_k<T, NP, 5>(P, pr, stream, S, V, F, pin, pout, npin, st, J, R, nu, nuref, sel, recomp, j,
+                                        i, tol);
+    return launch_fused_k<T, NP, 9>(P, pr, stream, S, V, F, pin, pout, npin, st, J, R, nu, nuref, sel, recomp, j, i,
+                                    tol);
+}
+
+template <typename T>
+static hipError_t launch_fused(const IdPlan& P, int pr, hipStream_t stream, T* S, T* V, T* F, ColPartial* pin,
+                               ColPartial* pout, int npin, DevState* st, int32_t* J, T* R, double* nu, double* nuref,
+                               int32_t* sel, int32_t* recomp, int j, int i, double tol) {
+    switch (P.fnp) {
+        case 4:
+            return launch_fused_np<T, 4>(P, pr, stream, S, V, F, pin, pout, npin, st, J, R, nu, nuref, sel, recomp,
+                                         j, i, tol);
+        case 2:
+            return launch_fused_np<T, 2>(P, pr, stream, S, V, F, pin, pout, npin, st, J, R, nu, nuref, sel, recomp,
+                                         j, i, tol);
+        default:
+            return launch_fused_np<T, 1>(P, pr, stream, S, V, F, pin, pout, npin, st, J, R, nu, nuref, sel, recomp,
+                                         j, i, tol);
+    }
+}
+
 template <typename T>
 int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t ldz, double* R11out, int64_t ldr, T* C,
            int64_t ldc, miid_info* info, unsigned char* ws, hipStream_t stream, bool staged, const T* Csrc,
@@ -1188,6 +1606,7 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
     int32_t host_stop = 0;
     ColPartial* fin_part = part;
     int fin_npart = P.npart;
+    int fin_alt = 0;
     bool resident_done = false;
     if (staged && P.res_ok && resident_enabled()) {
         hipError_t e = launch_resident<T>(P, S, R, J, sel, ws, st, stream);
@@ -1199,7 +1618,39 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
             (void)hipGetLastError();  // not co-resident: take the blocked path
         }
     }
-    if (!resident_done) {
+    if (!resident_done && P.fused) {
+    // the norm pass writes 8 fnpart partials (four-wave workgroups of NP
+    // columns per wave) into buffer 0; the steps write fnpart
+    fin_npart = P.fnpart;
+    fin_alt = 8 * P.fnpart;
+    hipLaunchKernelGGL(k_norms<T>, dim3(8 * P.fnpart), dim3(kThreads), 0, stream, S, ldw, n, P.fnp, nu, nuref, sel,
+                       part, recomp);
+    for (int j = 0; j < P.kmax; ++j) {
+        const int jb = (j / nb) * nb;
+        const int i = j - jb;
+        ColPartial* pin = part + (j & 1) * fin_alt;
+        ColPartial* pout = part + ((j + 1) & 1) * fin_alt;
+        const int npin = j == 0 ? 8 * P.fnpart : P.fnpart;
+        const int pr = prof_take(MIID_K_STEP, j, m - j, n - j);
+        MIID_HIP(launch_fused<T>(P, pr, stream, S, V, F, pin, pout, npin, st, J, R, nu, nuref, sel, recomp, j, i,
+                                 tol));
+        if (i == nb - 1 && j + 1 < P.kmax) {
+            const int64_t r0 = j + 1;
+            const int64_t rbase = r0 & ~(int64_t)63;
+            dim3 grid((unsigned)((ldw - rbase + 63) / 64), (unsigned)((n + 63) / 64));
+            const int pt = prof_take(MIID_K_TRAIL, j / nb, m - r0, n);
+            MIID_LAUNCH(pt, k_trail<T>, grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
+        }
+        if (P.tol && (j % 8 == 7) && j + 1 < P.kmax) {
+            MIID_HIP(hipMemcpyAsync(&host_stop, &st->stop, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+            MIID_HIP(hipStreamSynchronize(stream));
+            if (host_stop) {
+                ksteps = j + 1;
+                break;
+            }
+        }
+    }
+    } else if (!resident_done) {
     hipLaunchKernelGGL(k_norms<T>, dim3(P.npart), dim3(kThreads), 0, stream, S, ldw, n, P.cpw, nu, nuref, sel, part,
                        recomp);
     for (int j = 0; j < P.kmax; ++j) {
@@ -1264,7 +1715,7 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
         hipLaunchKernelGGL(k_gather_c<T>, grid, dim3(256), 0, stream, Csrc, ldcsrc, (int)P.trans, crows, J, st, ksteps,
                            C, ldc);
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, stream, st, fin_part, fin_npart, recomp, J, P.kmax,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, stream, st, fin_part, fin_npart, fin_alt, 8 * P.fnpart, recomp, J, P.kmax,
                        ksteps, (int)P.tol, P.eps, (int)P.trans, info);
     MIID_HIP(hipGetLastError());
     return 0;

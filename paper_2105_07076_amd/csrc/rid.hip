@@ -119,14 +119,15 @@ __global__ void __launch_bounds__(kSkThreads) k_sketch(const float* __restrict__
     }
     // output element r of lane l: Y[row = tile row + l % 16][col = wave col + 4 (l / 16) + r]
 #pragma unroll
+    // (a predicate, not a break: a data-dependent exit from the unrolled loop
+    // would put acc in scratch memory)
     for (int t = 0; t < kSkMTB; ++t) {
-        if (t >= mtb) break;
         const int64_t row = (int64_t)(mt0 + t) * 16 + lane % 16;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t c = (int64_t)blockIdx.x * kSkCols + wave * 16 + 4 * (lane / 16) + r;
-            if (c < n && row < ldw) S[row + c * ldw] = acc[t][r];
-            if (Yout && c < n && row < l) Yout[row + c * ldy] = acc[t][r];
+            if (t < mtb && c < n && row < ldw) S[row + c * ldw] = acc[t][r];
+            if (t < mtb && Yout && c < n && row < l) Yout[row + c * ldy] = acc[t][r];
         }
     }
 }

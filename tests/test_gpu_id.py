@@ -29,6 +29,14 @@ def kappa_tol(ref, dtype, floor):
     return max(floor, 8.0 * UW[dtype] * kap)
 
 
+@pytest.fixture(params=["fused", "blocked"])
+def path(request, monkeypatch):
+    """Matrices of at most 1024 rows take the fused one-launch-per-step
+    kernel; MIID_FUSED=0 forces the two-launch blocked path on them."""
+    monkeypatch.setenv("MIID_FUSED", "1" if request.param == "fused" else "0")
+    return request.param
+
+
 def _miid():
     import paper_2105_07076_amd as miid
     miid.load()
@@ -60,7 +68,7 @@ def _check_id(A_np, k, dtype, nb=0, exact_pivots=True, tol=None, refine=True):
     return r, ref, ties
 
 
-def test_cfg1_fp64():
+def test_cfg1_fp64(path):
     A, k = idgen.cfg1()
     r, ref, _ = _check_id(A, k, torch.float64)
     e_gpu = oracle.error(A, to_np(r.J), to_np(r.Z))
@@ -71,7 +79,7 @@ def test_cfg1_fp64():
 
 
 @pytest.mark.parametrize("nb", [1, 5, 32, 64])
-def test_cfg1_panel_widths(nb):
+def test_cfg1_panel_widths(nb, path):
     A, k = idgen.cfg1()
     _check_id(A, k, torch.float64, nb=nb)
 
@@ -79,7 +87,7 @@ def test_cfg1_panel_widths(nb):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("m,n,k,nb", [(37, 101, 9, 4), (128, 128, 40, 16), (200, 1000, 64, 32),
                                       (300, 700, 100, 64), (65, 4099, 30, 8)])
-def test_planted(dtype, m, n, k, nb):
+def test_planted(dtype, m, n, k, nb, path):
     A, planted, U, perm = idgen.planted_id(100 + m, m, n, k, r=0.9)
     r, ref, _ = _check_id(A, k, dtype, nb=nb)
     assert list(to_np(r.J)) == list(planted)
@@ -90,13 +98,13 @@ def test_planted(dtype, m, n, k, nb):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (1, 9, 1), (2, 3, 2), (63, 64, 20), (64, 64, 64),
                                    (65, 130, 33), (257, 511, 70), (129, 2000, 128)])
-def test_random_shapes(dtype, m, n, k):
+def test_random_shapes(dtype, m, n, k, path):
     g = idgen.rng(7 * m + n)
     A = g.standard_normal((m, n)) * (0.97 ** np.arange(n))[None, :]
     _check_id(A, k, dtype, exact_pivots=False, tol=1e-11 if dtype == torch.float64 else 2e-4)
 
 
-def test_dual_tall_matrix():
+def test_dual_tall_matrix(path):
     g = idgen.rng(9)
     A = g.standard_normal((300, 120)) @ np.diag(0.93 ** np.arange(120))
     r, ref, _ = _check_id(A, 40, torch.float64)
@@ -111,7 +119,7 @@ def test_full_rank():
     assert oracle.error(A, to_np(r.J), to_np(r.Z)) <= 1e-12 * np.linalg.norm(A)
 
 
-def test_rank_deficient_stops():
+def test_rank_deficient_stops(path):
     miid = _miid()
     A = idgen.diag_case(np.array([5.0, 0.0, 3.0, 0.0, 2.0, 0.0]), 10)
     A[:, 7] = 2.0 * A[:, 0]
@@ -121,7 +129,7 @@ def test_rank_deficient_stops():
     assert list(to_np(r.J)) == [7, 2, 4]
 
 
-def test_nonfinite_input():
+def test_nonfinite_input(path):
     miid = _miid()
     A = np.ones((20, 30))
     A[3, 4] = np.nan
@@ -130,7 +138,7 @@ def test_nonfinite_input():
     assert r.status & 2
 
 
-def test_tolerance_mode():
+def test_tolerance_mode(path):
     miid = _miid()
     A, _ = idgen.cfg1()
     a = np.linalg.norm(A)
@@ -156,7 +164,7 @@ def test_deterministic_repeat():
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_cfg2_reduced(dtype):
+def test_cfg2_reduced(dtype, path):
     A, k = idgen.cfg2(m=1024, n=4096)
     _check_id(A, k, dtype, exact_pivots=(dtype == torch.float64))
 

@@ -107,8 +107,12 @@ def test_rid_unaligned_lda():
     assert rel(to_np(r.Y).astype(np.float64), Y64) <= SKETCH_TOL[1]
 
 
-def test_rid_cfg2_reduced():
-    """cfg2 construction at 1024 x 4096, k = 256, l = k + 10."""
+@pytest.mark.parametrize("fused", ["1", "0"])
+def test_rid_cfg2_reduced(fused, monkeypatch):
+    """cfg2 construction at 1024 x 4096, k = 256, l = k + 10, through the
+    fused one-launch-per-step CPQR (default for the sketch) and the blocked
+    two-launch one."""
+    monkeypatch.setenv("MIID_FUSED", fused)
     A, k = idgen.cfg2(m=1024, n=4096)
     _check(A, k + 10, k, 1, e2e_tol=1e-5)
 
