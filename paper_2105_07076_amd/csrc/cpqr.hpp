@@ -28,7 +28,8 @@ struct IdPlan {
     // resident path (few rows): rows per lane, grid, columns per workgroup
     bool res_ok;
     int res_rpl, res_grid, res_cpb;
-    size_t oS, oV, oF, ou, onu, onuref, oR, osel, opart, opartA, oR11, ostate, orec, total;
+    int kpad;  // kmax rounded up to the triangular solve's diagonal block
+    size_t oS, oV, oF, ou, onu, onuref, oR, osel, opart, opartA, oR11, oDinv, ostate, orec, total;
     size_t oPart2, oPartF, oSlots, oBar;
 };
 

@@ -913,133 +913,144 @@ __global__ void __launch_bounds__(kThreads) k_trail(T* __restrict__ S, int64_t l
 }
 
 // ---------------------------------------------------------------------------
-// a9: R11 (FP64, pivot order) gathered from the rows of R.
+// a9: R11 (FP64, pivot order, kpad x kpad column-major, kpad = kmax rounded up
+// to the diagonal block) gathered from the rows of R; the identity pads it
+// beyond the K rows/columns that exist.
 // ---------------------------------------------------------------------------
+constexpr int kTB = 32;  // diagonal block of the triangular solve
+
 template <typename T>
-__global__ void k_gather_r11(const T* __restrict__ R, int64_t n, const int32_t* __restrict__ J, int kmax,
+__global__ void k_gather_r11(const T* __restrict__ R, int64_t n, const int32_t* __restrict__ J, int kmax, int kpad,
                              const DevState* __restrict__ st, int ksteps, double* __restrict__ R11s,
                              double* __restrict__ R11out, int64_t ldr) {
     const int kout = st->stop ? st->k_out : ksteps;
-    const int64_t total = (int64_t)kmax * kmax;
+    const int64_t total = (int64_t)kpad * kpad;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int a = (int)(e % kmax), b = (int)(e / kmax);
+        const int a = (int)(e % kpad), b = (int)(e / kpad);
         double val;
         if (a < kout && b < kout)
             val = a <= b ? (double)R[(int64_t)a * n + J[b]] : 0.0;
         else
             val = a == b ? 1.0 : 0.0;
         R11s[e] = val;
-        if (R11out) R11out[a + (int64_t)b * ldr] = (a < kout && b < kout) ? val : 0.0;
+        if (R11out && a < kmax && b < kmax) R11out[a + (int64_t)b * ldr] = (a < kout && b < kout) ? val : 0.0;
     }
 }
 
-// Blocked back substitution R11 x = b for NCOL right-hand sides held in LDS
-// (work[K][NCOL], overwritten by x).  Row blocks of BS = 256 / NCOL rows are
-// processed bottom-up: the BS x BS diagonal block is staged in LDS and solved
-// by thread (a, c) = (row in block, column); then every row above the block
-// subtracts the block's contribution (thread per row, NCOL columns, R11 read
-// column-wise from global memory with independent loads).
-template <int NCOL>
-__device__ void lds_backsolve(double* work, double* sD, const double* __restrict__ R11s, int kmax, int K) {
-    constexpr int BS = kThreads / NCOL;
-    const int tid = threadIdx.x;
-    const int c = tid % NCOL, a = tid / NCOL;
-    const int nblk = (K + BS - 1) / BS;
-    for (int b = nblk - 1; b >= 0; --b) {
-        const int r0 = b * BS;
-        const int bs = min(BS, K - r0);
-        for (int e = tid; e < BS * BS; e += kThreads) {
-            const int ra = e % BS, cb = e / BS;
-            sD[ra * (BS + 1) + cb] = (ra < bs && cb < bs && ra <= cb) ? R11s[(r0 + ra) + (int64_t)(r0 + cb) * kmax] : 0.0;
+// Inverses of the kTB x kTB diagonal blocks of R11 (upper triangular), one
+// workgroup per block: thread t solves D x = e_t by back substitution, so
+// column t of D^{-1} is exact up to the rounding of that substitution.
+__global__ void __launch_bounds__(kTB) k_trsm_dinv(const double* __restrict__ R11s, int kpad,
+                                                   double* __restrict__ Dinv) {
+    __shared__ double sD[kTB][kTB + 1];
+    __shared__ double sx[kTB][kTB + 1];  // sx[row][t]
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int64_t r0 = (int64_t)b * kTB;
+    for (int c = 0; c < kTB; ++c) sD[t][c] = R11s[(r0 + t) + (r0 + c) * kpad];
+    __syncthreads();
+    for (int r = kTB - 1; r >= 0; --r) {
+        double x = 0.0;
+        if (r <= t) {
+            double acc = (r == t) ? 1.0 : 0.0;
+            for (int c = r + 1; c <= t; ++c) acc -= sD[r][c] * sx[c][t];
+            x = acc / sD[r][r];
         }
-        __syncthreads();
-        for (int i = bs - 1; i >= 0; --i) {
-            if (a == i) work[(r0 + i) * NCOL + c] /= sD[i * (BS + 1) + i];
-            __syncthreads();
-            if (a < i) work[(r0 + a) * NCOL + c] -= sD[a * (BS + 1) + i] * work[(r0 + i) * NCOL + c];
-        }
-        __syncthreads();
-        for (int q = tid; q < r0; q += kThreads) {
-            double acc[NCOL], rq[BS];
-#pragma unroll
-            for (int t = 0; t < BS; ++t) rq[t] = t < bs ? R11s[q + (int64_t)(r0 + t) * kmax] : 0.0;
-#pragma unroll
-            for (int cc = 0; cc < NCOL; ++cc) acc[cc] = work[q * NCOL + cc];
-#pragma unroll
-            for (int t = 0; t < BS; ++t) {
-                if (t < bs) {
-#pragma unroll
-                    for (int cc = 0; cc < NCOL; ++cc) acc[cc] -= rq[t] * work[(r0 + t) * NCOL + cc];
-                }
-            }
-#pragma unroll
-            for (int cc = 0; cc < NCOL; ++cc) work[q * NCOL + cc] = acc[cc];
-        }
-        __syncthreads();
+        sx[r][t] = x;
     }
+    for (int r = 0; r < kTB; ++r) Dinv[(int64_t)b * kTB * kTB + r + (int64_t)t * kTB] = sx[r][t];
 }
 
-// Z[:, cols] = R11^{-1} R[:, cols] in FP64 with one refinement step
-// (residual R[:, cols] - R11 x in FP64, one more solve);
-// Z[:, J[c]] = e_c exactly; rows >= k_out are zero.
-template <typename T, int NCOL>
-__global__ void __launch_bounds__(kThreads, 2) k_trsm(const T* __restrict__ R, int64_t n,
-                                                   const double* __restrict__ R11s, int kmax,
-                                                   const DevState* __restrict__ st, int ksteps,
-                                                   const int32_t* __restrict__ sel, T* __restrict__ Z, int64_t ldz,
-                                                   int refine) {
-    constexpr int BS = kThreads / NCOL;
+// Z[:, cols] = R11^{-1} R[:, cols] in FP64 for NC columns per workgroup, by
+// block back substitution with the inverted diagonal blocks: the columns'
+// right-hand sides stay in LDS (kpad x NC); for row block b (bottom up)
+//   T = X_b - sum_{c > b} R11[b, c] X_c,   X_b = D_b^{-1} T.
+// The refinement sweep (one step of iterative refinement, residual in FP64)
+// runs the same recursion on the residual and overwrites X in place:
+//   X_b += D_b^{-1} (B_b - sum_{c >= b} R11[b, c] X_c)
+// where the X_c (c > b) are already refined -- in exact arithmetic the same
+// correction as solving R11 d = B - R11 X and adding d.
+// Both products run on the FP64 matrix cores (v_mfma_f64_16x16x4): wave w
+// owns the 16 x 16 tile (rows 16 (w % 2), columns 16 (w / 2)) of the
+// kTB x NC block; A operand lane l = R11[row l % 16][k l / 16] (from L2),
+// B operand lane l = X[k l / 16][col l % 16] (LDS), output element e of
+// lane l = row l / 16 + 4 e, column l % 16.
+// Z[:, J[c]] = e_c exactly; rows >= K are zero.
+template <typename T, int NC>
+__global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, int64_t n,
+                                                     const double* __restrict__ R11s, int kpad,
+                                                     const double* __restrict__ Dinv,
+                                                     const DevState* __restrict__ st, int ksteps,
+                                                     const int32_t* __restrict__ sel, T* __restrict__ Z,
+                                                     int64_t ldz, int kmax, int refine) {
+    constexpr int NT = 8 * NC;
+    constexpr int NCP = NC + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* z = reinterpret_cast<double*>(smem_raw);  // [kmax][NCOL]
-    double* work = z + (int64_t)kmax * NCOL;          // [kmax][NCOL]
-    __shared__ double sD[BS * (BS + 1)];
+    double* sX = reinterpret_cast<double*>(smem_raw);  // [kpad][NCP]
+    __shared__ double sT[kTB][NCP];
     const int K = st->stop ? st->k_out : ksteps;
-    const int64_t c0 = (int64_t)blockIdx.x * NCOL;
+    const int nbk = (K + kTB - 1) / kTB;
+    const int kend = nbk * kTB;
     const int tid = threadIdx.x;
-    for (int e = tid; e < K * NCOL; e += kThreads) {
-        const int q = e / NCOL, c = e % NCOL;
-        const int64_t col = c0 + c;
-        work[e] = col < n ? (double)R[(int64_t)q * n + col] : 0.0;
+    const int wave = tid / kWave, lane = tid % kWave;
+    const int tr = 16 * (wave % 2), tc = 16 * (wave / 2);
+    const int l16 = lane % 16, lq = lane / 16;
+    const int64_t c0 = (int64_t)blockIdx.x * NC;
+    const int64_t col = c0 + tc + l16;  // this lane's output column
+    for (int e = tid; e < kend * NC; e += NT) {
+        const int q = e / NC, c = e % NC;
+        sX[q * NCP + c] = (q < K && c0 + c < n) ? (double)R[(int64_t)q * n + c0 + c] : 0.0;
     }
     __syncthreads();
-    lds_backsolve<NCOL>(work, sD, R11s, kmax, K);
-    for (int e = tid; e < K * NCOL; e += kThreads) z[e] = work[e];
-    if (refine) {
-        __syncthreads();
-        for (int q = tid; q < K; q += kThreads) {
-            double acc[NCOL];
+    for (int sweep = 0; sweep < (refine ? 2 : 1); ++sweep) {
+        for (int b = nbk - 1; b >= 0; --b) {
+            const int r0 = b * kTB;
+            d4_t acc;
 #pragma unroll
-            for (int cc = 0; cc < NCOL; ++cc) {
-                const int64_t col = c0 + cc;
-                acc[cc] = col < n ? (double)R[(int64_t)q * n + col] : 0.0;
+            for (int e = 0; e < 4; ++e) {
+                const int row = r0 + tr + lq + 4 * e;
+                if (sweep == 0)
+                    acc[e] = sX[row * NCP + tc + l16];
+                else
+                    acc[e] = (row < K && col < n) ? (double)R[(int64_t)row * n + col] : 0.0;
             }
-            // start at the wave's first row so that the loads of one t are
-            // contiguous over the wave (R11s is zero below the diagonal)
+            const int kstart = sweep == 0 ? r0 + kTB : r0;
+            const double* ap = R11s + (r0 + tr + l16) + (int64_t)(kstart + lq) * kpad;
 #pragma unroll 4
-            for (int t = q & ~(kWave - 1); t < K; ++t) {
-                const double rq = R11s[q + (int64_t)t * kmax];
-#pragma unroll
-                for (int cc = 0; cc < NCOL; ++cc) acc[cc] -= rq * z[t * NCOL + cc];
+            for (int k0 = kstart; k0 < kend; k0 += 4, ap += 4 * (int64_t)kpad) {
+                const double av = -*ap;
+                const double xv = sX[(k0 + lq) * NCP + tc + l16];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xv, acc, 0, 0, 0);
             }
 #pragma unroll
-            for (int cc = 0; cc < NCOL; ++cc) work[q * NCOL + cc] = acc[cc];
+            for (int e = 0; e < 4; ++e) sT[tr + lq + 4 * e][tc + l16] = acc[e];
+            __syncthreads();
+            const double* Db = Dinv + (int64_t)b * kTB * kTB;
+            d4_t out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k0 = 0; k0 < kTB; k0 += 4) {
+                const double av = Db[(tr + l16) + (k0 + lq) * kTB];
+                const double xv = sT[k0 + lq][tc + l16];
+                out = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xv, out, 0, 0, 0);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                double* xp = &sX[(r0 + tr + lq + 4 * e) * NCP + tc + l16];
+                *xp = sweep == 0 ? out[e] : *xp + out[e];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        lds_backsolve<NCOL>(work, sD, R11s, kmax, K);
-        for (int e = tid; e < K * NCOL; e += kThreads) z[e] += work[e];
     }
-    __syncthreads();
-    for (int e = tid; e < kmax * NCOL; e += kThreads) {
+    for (int e = tid; e < kmax * NC; e += NT) {
         const int q = e % kmax, cc = e / kmax;
-        const int64_t cl = c0 + cc;
-        if (cl >= n) continue;
-        const int s = sel[cl];
+        const int64_t c = c0 + cc;
+        if (c >= n) continue;
+        const int s = sel[c];
         double val;
         if (s >= 0 && s < K)
             val = (q == s) ? 1.0 : 0.0;
         else
-            val = q < K ? z[q * NCOL + cc] : 0.0;
-        Z[q + cl * ldz] = (T)val;
+            val = q < K ? sX[q * NCP + cc] : 0.0;
+        Z[q + c * ldz] = (T)val;
     }
 }
 
@@ -1431,7 +1442,9 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
     P->osel = take((size_t)P->n * 4);
     P->opart = take((size_t)std::max(P->npart, 16 * P->fnpart) * sizeof(ColPartial));
     P->opartA = take((size_t)P->NA * kPartAStride * 8);
-    P->oR11 = take((size_t)P->kmax * P->kmax * 8);
+    P->kpad = (int)align_up((size_t)P->kmax, kTB);
+    P->oR11 = take((size_t)P->kpad * P->kpad * 8);
+    P->oDinv = take((size_t)P->kpad * kTB * 8);
     P->ostate = take(sizeof(DevState));
     P->orec = take((size_t)std::max(P->npart, 8 * P->fnpart) * 4);
     // resident path: every workgroup holds ceil(n / grid) columns in LDS
@@ -1517,7 +1530,8 @@ static hipError_t launch_fused_k(const IdPlan& P, int pr, hipStream_t stream, T*
     const size_t shmem = (size_t)P.ldw * kFusedMaxNb * P.esz;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)k_step_fused<T, NP, GL>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kFusedMaxRows * kFusedMaxNb * (int)sizeof(T));
         if (e != hipSuccess) return e;
         attr = true;
     }
@@ -1576,9 +1590,14 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
 
     static bool attr_done = false;
     if (!attr_done) {
-        // dynamic LDS above 64 KB: the reflector (k_gemv) and the solve tiles (k_trsm)
-        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
-        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+        // dynamic LDS above 64 KB: the right-hand sides of the solve
+        // (the largest kpad of each variant: 256, 512, 1024 rows of NC + 1 doubles)
+        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     256 * 65 * 8));
+        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     512 * 33 * 8));
+        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     1024 * 17 * 8));
         attr_done = true;
     }
 
@@ -1694,19 +1713,25 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
     MIID_HIP(hipGetLastError());
     // a9: triangular solve
     {
-        const int64_t total = (int64_t)P.kmax * P.kmax;
+        double* Dinv = reinterpret_cast<double*>(ws + P.oDinv);
+        const int64_t total = (int64_t)P.kpad * P.kpad;
         const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_gather_r11<T>, dim3(blocks), dim3(256), 0, stream, R, n, J, P.kmax, st, ksteps, R11s,
-                           R11out, ldr);
+        hipLaunchKernelGGL(k_gather_r11<T>, dim3(blocks), dim3(256), 0, stream, R, n, J, P.kmax, P.kpad, st, ksteps,
+                           R11s, R11out, ldr);
+        hipLaunchKernelGGL(k_trsm_dinv, dim3((unsigned)(P.kpad / kTB)), dim3(kTB), 0, stream, R11s, P.kpad, Dinv);
         const int pr = prof_take(MIID_K_TRSM, 0, P.kmax, n);
-        if (P.kmax <= 512) {
-            const size_t lds = (size_t)2 * P.kmax * 16 * 8;
-            MIID_LAUNCH(pr, (k_trsm<T, 16>), dim3((unsigned)((n + 15) / 16)), dim3(kThreads), lds, stream, R, n,
-                               R11s, P.kmax, st, ksteps, sel, Z, ldz, (int)P.refine);
+        if (P.kpad <= 256) {
+            MIID_LAUNCH(pr, (k_trsm_blk<T, 64>), dim3((unsigned)((n + 63) / 64)), dim3(8 * 64),
+                        (size_t)P.kpad * 65 * 8, stream, R, n, R11s, P.kpad, Dinv, st, ksteps, sel, Z, ldz, P.kmax,
+                        (int)P.refine);
+        } else if (P.kpad <= 512) {
+            MIID_LAUNCH(pr, (k_trsm_blk<T, 32>), dim3((unsigned)((n + 31) / 32)), dim3(8 * 32),
+                        (size_t)P.kpad * 33 * 8, stream, R, n, R11s, P.kpad, Dinv, st, ksteps, sel, Z, ldz, P.kmax,
+                        (int)P.refine);
         } else {
-            const size_t lds = (size_t)2 * P.kmax * 8 * 8;
-            MIID_LAUNCH(pr, (k_trsm<T, 8>), dim3((unsigned)((n + 7) / 8)), dim3(kThreads), lds, stream, R, n, R11s,
-                               P.kmax, st, ksteps, sel, Z, ldz, (int)P.refine);
+            MIID_LAUNCH(pr, (k_trsm_blk<T, 16>), dim3((unsigned)((n + 15) / 16)), dim3(8 * 16),
+                        (size_t)P.kpad * 17 * 8, stream, R, n, R11s, P.kpad, Dinv, st, ksteps, sel, Z, ldz, P.kmax,
+                        (int)P.refine);
         }
     }
     // a10: C, info
