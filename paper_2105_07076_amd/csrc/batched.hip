@@ -7,14 +7,20 @@
 //
 // Design: one workgroup works on one block at a time and takes the next block
 // from an atomic queue over the blocks sorted by decreasing m * n (longest
-// first), so uneven sizes balance across the chip.  The block is copied into
-// the workgroup's slab of the workspace and factored with unblocked
-// Householder steps: every step applies the reflector to each remaining column
-// and recomputes that column's residual norm exactly (FP64 accumulation) in
-// the same pass -- at eps = 1e-6 in FP32 the downdated norms would have lost
-// all their digits anyway.  R stays in the slab's first k rows (no column
-// swaps); the k x k triangle is staged in LDS in FP64 for the solve.
+// first), so uneven sizes balance across the chip.  Each Householder step
+// applies the reflector to every remaining column and recomputes that
+// column's residual norm exactly (FP64 accumulation) in the same pass -- at
+// eps = 1e-6 in FP32 downdated norms would have lost all their digits.  The
+// working copy W of the block stays in LDS when it fits; otherwise it lives
+// in a per-workgroup scratch and every pass streams it through two LDS column
+// tiles (the next tile's loads in flight while the current one is updated,
+// the updated one written back behind it).  A column is handled by a 16-lane
+// group (lane l16 takes rows l16 + 16 t; DPP row sums).  R stays in W's
+// first k rows and is copied row by row into Z's storage (no column swaps);
+// the k x k triangle is staged in LDS in FP64 for the solve, which then
+// overwrites Z in place.
 #include <algorithm>
+#include <cmath>
 #include <climits>
 
 #include "common.hpp"
@@ -23,13 +29,15 @@
 
 namespace miid {
 
-constexpr int kBThreads = 1024;
+constexpr int kBThreads = 512;
 constexpr int kBWaves = kBThreads / kWave;
+// dynamic LDS (V, then the block or its column tiles): what the 160 KB of a
+// CU leave beside the kernel's static arrays
+constexpr int bdyn_bytes(int) { return 148 * 1024; }
+constexpr int kBTileBytes = 32 * 1024;  // largest streamed column tile
 constexpr int kBMaxM = 256;
 constexpr int kBMaxN = 1024;
 constexpr int kBMaxK = 64;
-constexpr int kBRows = kBMaxM / kWave;  // rows per lane
-constexpr int kBLdsBytes = 88 * 1024;   // LDS for a whole block when it fits
 constexpr uint32_t kBlockUnsupported = 16u;
 
 // Sort block indices by decreasing m * n (ties by index) into order[]:
@@ -77,11 +85,38 @@ __global__ void k_zero_queue(int32_t* __restrict__ queue) {
     if (threadIdx.x == 0) *queue = 0;
 }
 
-template <typename T>
-struct BLds {
-    static constexpr int elems = kBLdsBytes / (int)sizeof(T);
-};
+// Block-wide (value, index) argmax and sum: wave results through LDS, read
+// back in wave order (identical in every thread).
+__device__ __forceinline__ void block_argmax_sum(ArgMax& best, double& sum, ArgMax* w_best, double* w_sum) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    best = wave_argmax_dpp(best);
+    sum = wave_sum_dpp(sum);
+    if (lane == 0) {
+        w_best[wave] = best;
+        w_sum[wave] = sum;
+    }
+    lds_barrier();
+    best = w_best[0];
+    sum = w_sum[0];
+    for (int w = 1; w < kBWaves; ++w) {
+        if (argmax_better(w_best[w].v, w_best[w].i, best.v, best.i)) best = w_best[w];
+        sum += w_sum[w];
+    }
+    lds_barrier();
+}
 
+__device__ __forceinline__ double block_sum(double v, double* w_sum) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    v = wave_sum_dpp(v);
+    if (lane == 0) w_sum[wave] = v;
+    lds_barrier();
+    double t = 0.0;
+    for (int w = 0; w < kBWaves; ++w) t += w_sum[w];
+    lds_barrier();
+    return t;
+}
+
+// Persistent kernel: one block at a time per workgroup (8 waves, one per CU).
 template <typename T>
 __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, const int64_t* __restrict__ a_off,
                                                        const int32_t* __restrict__ mv, const int32_t* __restrict__ nv,
@@ -90,19 +125,25 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
                                                        T* __restrict__ Z, const int64_t* __restrict__ z_off,
                                                        miid_info* __restrict__ info,
                                                        const int32_t* __restrict__ order, int32_t* __restrict__ queue,
-                                                       T* __restrict__ slabs, int64_t slab_elems) {
-    constexpr int kBLdsElems = BLds<T>::elems;
-    __shared__ __align__(16) T sW[kBLdsElems];   // the block when it fits
-    __shared__ double sR[kBMaxK * (kBMaxK + 1)];
-    __shared__ double nu[kBMaxN];
-    __shared__ T sv[kBMaxM];
-    __shared__ double w_best[kBWaves], w_sum[kBWaves];
-    __shared__ int32_t w_idx[kBWaves];
-    __shared__ int32_t s_blk;
+                                                       T* __restrict__ Wscr) {
+    constexpr int kDyn = bdyn_bytes((int)sizeof(T)) / (int)sizeof(T);
+    constexpr int kTileMax = kBTileBytes / (int)sizeof(T);
+    constexpr int kStage = kTileMax / kBThreads;  // staged elements per thread
+    constexpr int kRT = kBMaxM / 16;              // rows per lane of a column group
+    constexpr int kGroups = kBWaves * 4;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    __shared__ double snu[kBMaxN];
+    __shared__ double s_v[kBMaxM];  // the reflector (v_j = 1, zero above j)
+    __shared__ ArgMax w_best[kBWaves];
+    __shared__ double w_sum[kBWaves];
     __shared__ int32_t s_sel[kBMaxK];
+    __shared__ int32_t s_blk;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
-    T* slab = slabs + (int64_t)blockIdx.x * slab_elems;
+    const int l16 = lane & 15, grp = lane >> 4;
+    const int cgroup = wave * 4 + grp;  // 16-lane column group
+    T* Wb = Wscr + (int64_t)blockIdx.x * kBMaxM * kBMaxN;  // W when it does not fit in LDS
 
     for (;;) {
         if (tid == 0) s_blk = atomicAdd(queue, 1);
@@ -118,32 +159,101 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
             continue;
         }
         const T* Ab = A + a_off[b];
-        T* W = ((int64_t)m * n <= kBLdsElems) ? sW : slab;  // flat pointer: LDS or global
-        for (int64_t e = tid; e < (int64_t)m * n; e += kBThreads) W[e] = Ab[e];
-        __syncthreads();
-        // exact column norms (FP64 accumulation) and ||A_b||_F
-        double fro = 0.0;
-        for (int c = wave; c < n; c += kBWaves) {
-            double s = 0.0;
+        T* Zb = Z + z_off[b];
+        const bool resident = m * n <= kDyn;
+        const int TC = resident ? n : min(n, min(kDyn / 2, kTileMax) / m);
+        const int nt = (n + TC - 1) / TC;
+        T* buf0 = lds;
+        T* buf1 = lds + (resident ? 0 : TC * m);
+        if (resident) {
+            for (int e0 = 0; e0 < m * n; e0 += kStage * kBThreads) {
+                T x[kStage];
 #pragma unroll
-            for (int t = 0; t < kBRows; ++t) {
-                const int r = lane + kWave * t;
-                if (r < m) {
-                    const double x = (double)W[(int64_t)c * m + r];
-                    s += x * x;
+                for (int i = 0; i < kStage; ++i) {
+                    const int e = e0 + tid + i * kBThreads;
+                    x[i] = e < m * n ? Ab[e] : T(0);
+                }
+#pragma unroll
+                for (int i = 0; i < kStage; ++i) {
+                    const int e = e0 + tid + i * kBThreads;
+                    if (e < m * n) lds[e] = x[i];
                 }
             }
-            s = wave_sum(s);
-            if (lane == 0) nu[c] = sqrt(s);
-            fro += s;
+            __syncthreads();
         }
-        if (lane == 0) w_sum[wave] = fro;
-        __syncthreads();
-        double a2 = 0.0;
-        for (int w = 0; w < kBWaves; ++w) a2 += w_sum[w];
+
+        // one pass over W: fn(l, column in LDS) for every column; a
+        // streamed block's tiles come from src (A on the first pass, the
+        // scratch afterwards) and go back to the scratch when write is set
+        auto pass = [&](const T* src, bool write, auto&& fn) {
+            if (resident) {
+                for (int l = cgroup; l < n; l += kGroups) fn(l, buf0 + l * m);
+                lds_barrier();
+                return;
+            }
+            T x[kStage];
+            auto load = [&](int t) {
+                const int cnt = min(TC, n - t * TC) * m;
+                const T* s0 = src + (int64_t)t * TC * m;
+#pragma unroll
+                for (int i = 0; i < kStage; ++i) {
+                    const int e = tid + i * kBThreads;
+                    x[i] = e < cnt ? s0[e] : T(0);
+                }
+            };
+            auto store = [&](int t) {
+                const int cnt = min(TC, n - t * TC) * m;
+                T* dst = (t & 1) ? buf1 : buf0;
+#pragma unroll
+                for (int i = 0; i < kStage; ++i) {
+                    const int e = tid + i * kBThreads;
+                    if (e < cnt) dst[e] = x[i];
+                }
+            };
+            load(0);
+            store(0);
+            lds_barrier();
+            for (int t = 0; t < nt; ++t) {
+                if (t + 1 < nt) load(t + 1);
+                const int c0 = t * TC, c1 = min(n, c0 + TC);
+                T* cur = (t & 1) ? buf1 : buf0;
+                for (int l = c0 + cgroup; l < c1; l += kGroups) fn(l, cur + (l - c0) * m);
+                lds_barrier();
+                if (write) {
+                    const int cnt = (c1 - c0) * m;
+                    T* d0 = Wb + (int64_t)c0 * m;
+                    for (int e = tid; e < cnt; e += kBThreads) d0[e] = cur[e];
+                }
+                if (t + 1 < nt) store(t + 1);
+                lds_barrier();
+            }
+        };
+
+        // exact column norms (FP64) and ||A_b||_F; a streamed block is copied
+        // to the scratch on the way
+        double fro = 0.0;
+        pass(Ab, !resident, [&](int l, T* col) {
+            double ss = 0.0;
+#pragma unroll
+            for (int t = 0; t < kRT; ++t) {
+                const int r = l16 + 16 * t;
+                if (r < m) {
+                    const double x = (double)col[r];
+                    ss += x * x;
+                }
+            }
+            ss = row16_sum(ss);
+            if (l16 == 0) {
+                snu[l] = sqrt(ss);
+                fro += ss;
+            }
+        });
+        const double a2 = block_sum(fro, w_sum);
         const double a_norm = sqrt(a2);
         const double stop_abs = eps * a_norm;
+        // W (the scratch writes of the copy) complete before it is read
         __syncthreads();
+        const T* W = resident ? buf0 : Wb;
 
         int k = 0;
         uint32_t status = 0;
@@ -151,32 +261,18 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
         const bool nonfinite = !(a_norm <= 1.0e300);
         if (nonfinite) status |= MIID_NONFINITE;
         while (!nonfinite) {
-            // pivot: largest residual norm among the alive columns (one per thread)
+            // pivot: largest residual norm among the alive columns
             ArgMax best{-1.0, INT32_MAX};
             double ss = 0.0;
-            for (int c = tid; c < n; c += kBThreads) {
-                const double v = nu[c];
+            for (int l = tid; l < n; l += kBThreads) {
+                const double v = snu[l];
                 if (v >= 0.0) {
-                    if (argmax_better(v, c, best.v, best.i)) best = {v, c};
+                    if (argmax_better(v, l, best.v, best.i)) best = {v, l};
                     ss += v * v;
                 }
             }
-            best = wave_argmax(best);
-            ss = wave_sum(ss);
-            if (lane == 0) {
-                w_best[wave] = best.v;
-                w_idx[wave] = best.i;
-                w_sum[wave] = ss;
-            }
-            __syncthreads();
-            best = ArgMax{w_best[0], w_idx[0]};
-            ss = w_sum[0];
-            for (int w = 1; w < kBWaves; ++w) {
-                if (argmax_better(w_best[w], w_idx[w], best.v, best.i)) best = {w_best[w], w_idx[w]};
-                ss += w_sum[w];
-            }
+            block_argmax_sum(best, ss, w_best, w_sum);
             resid = sqrt(ss);
-            __syncthreads();
             if (resid <= stop_abs) break;
             if (k >= kb) {
                 status |= MIID_KMAX_HIT;
@@ -188,113 +284,108 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
             }
             const int p = best.i;
             const int j = k;
-            // Householder reflector of W[j:, p]
-            T* wp = W + (int64_t)p * m;
-            if (wave == 0) {
-                double xs = 0.0;
-#pragma unroll
-                for (int t = 0; t < kBRows; ++t) {
-                    const int r = lane + kWave * t;
-                    if (r > j && r < m) {
-                        const double x = (double)wp[r];
-                        xs += x * x;
-                    }
-                }
-                xs = wave_sum(xs);
-                if (lane == 0) w_sum[0] = xs;
+            // Householder reflector of W[j:, p] (one thread per row)
+            const double x = (tid < m && tid >= j) ? (double)W[tid + (int64_t)p * m] : 0.0;
+            const double s0 = block_sum(tid > j && tid < m ? x * x : 0.0, w_sum);
+            if (tid == j) s_v[kBMaxM - 1] = x;  // x0 (row j) parked in the last slot
+            lds_barrier();
+            const double x0 = tid == j ? x : s_v[kBMaxM - 1];
+            lds_barrier();
+            const double alpha = sqrt(x0 * x0 + s0);
+            if (!(alpha > 0.0)) {
+                status |= MIID_RANK_DEFICIENT;
+                break;
             }
-            __syncthreads();
-            const double x0 = (double)wp[j];
-            const double alpha = sqrt(x0 * x0 + w_sum[0]);
             const double beta = x0 >= 0.0 ? -alpha : alpha;
             const double tau = (beta - x0) / beta;
             const double scale = 1.0 / (x0 - beta);
-            for (int r = tid; r < m; r += kBThreads)
-                sv[r] = r < j ? T(0) : (r == j ? T(1) : (T)((double)wp[r] * scale));
-            __syncthreads();
+            if (tid < kBMaxM) s_v[tid] = (tid < j || tid >= m) ? 0.0 : (tid == j ? 1.0 : (double)(T)(x * scale));
             if (tid == 0) {
-                wp[j] = (T)beta;
-                nu[p] = -1.0;
                 s_sel[j] = p;
+                snu[p] = -1.0;
+                Zb[j + (int64_t)p * kb] = (T)beta;
             }
-            double vr[kBRows];
+            lds_barrier();
+            // apply H = I - tau v v^T to the alive columns, row j of R, exact
+            // new norms of rows j+1..m-1
+            pass(W, !resident, [&](int l, T* col) {
+                if (!(snu[l] >= 0.0)) return;  // dead column (uniform over the group)
+                double xr[kRT];
+                double d = 0.0;
 #pragma unroll
-            for (int t = 0; t < kBRows; ++t) {
-                const int r = lane + kWave * t;
-                vr[t] = r < m ? (double)sv[r] : 0.0;
-            }
-            // apply H = I - tau v v^T to the other alive columns, two at a
-            // time per wave, and recompute their residual norms exactly
-            for (int c0 = wave * 2; c0 < n; c0 += 2 * kBWaves) {
-                int cc[2];
-                bool act[2];
-                double x[2][kBRows], d[2];
+                for (int t = 0; t < kRT; ++t) {
+                    const int r = l16 + 16 * t;
+                    xr[t] = (r >= j && r < m) ? (double)col[r] : 0.0;
+                    d += xr[t] * s_v[r < kBMaxM ? r : 0];
+                }
+                d = tau * row16_sum(d);
+                double s2 = 0.0;
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    cc[u] = c0 + u;
-                    act[u] = cc[u] < n && cc[u] != p && nu[cc[u]] >= 0.0;
-                    d[u] = 0.0;
-#pragma unroll
-                    for (int t = 0; t < kBRows; ++t) {
-                        const int r = lane + kWave * t;
-                        x[u][t] = (act[u] && r >= j && r < m) ? (double)W[(int64_t)cc[u] * m + r] : 0.0;
-                        d[u] += x[u][t] * vr[t];
+                for (int t = 0; t < kRT; ++t) {
+                    const int r = l16 + 16 * t;
+                    if (r >= j && r < m) {
+                        const T y = (T)(xr[t] - d * s_v[r]);
+                        col[r] = y;
+                        if (r == j) Zb[j + (int64_t)l * kb] = y;
+                        if (r > j) s2 += (double)y * (double)y;
                     }
                 }
-                d[0] = tau * wave_sum(d[0]);
-                d[1] = tau * wave_sum(d[1]);
-                double s2[2] = {0.0, 0.0};
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    if (!act[u]) continue;
-#pragma unroll
-                    for (int t = 0; t < kBRows; ++t) {
-                        const int r = lane + kWave * t;
-                        if (r >= j && r < m) {
-                            const T y = (T)(x[u][t] - d[u] * vr[t]);
-                            W[(int64_t)cc[u] * m + r] = y;
-                            if (r > j) s2[u] += (double)y * (double)y;
-                        }
-                    }
-                }
-                s2[0] = wave_sum(s2[0]);
-                s2[1] = wave_sum(s2[1]);
-                if (lane == 0) {
-                    if (act[0]) nu[cc[0]] = sqrt(s2[0]);
-                    if (act[1]) nu[cc[1]] = sqrt(s2[1]);
-                }
-            }
+                s2 = row16_sum(s2);
+                if (l16 == 0) snu[l] = sqrt(s2);
+            });
             ++k;
-            __syncthreads();
+            __syncthreads();  // R rows and the scratch writes of step j are complete
         }
 
-        // triangular solve: Z[:, c] = R11^{-1} R[:, c] in FP64, Z[:, J[i]] = e_i
+        // triangular solve: Z[:, l] = R11^{-1} R[:, l] in FP64, Z[:, J[i]] = e_i
+        double* sR = reinterpret_cast<double*>(smem_raw);  // reuses the dynamic LDS: k x (kBMaxK + 1)
+        __syncthreads();
         for (int e = tid; e < k * k; e += kBThreads) {
             const int a = e % k, c = e / k;
-            sR[a * (kBMaxK + 1) + c] = a <= c ? (double)W[(int64_t)s_sel[c] * m + a] : 0.0;
+            sR[a * (kBMaxK + 1) + c] = a <= c ? (double)Zb[a + (int64_t)s_sel[c] * kb] : 0.0;
         }
         __syncthreads();
-        T* Zb = Z + z_off[b];
         int32_t* Jb = J + j_off[b];
         for (int i = tid; i < kb; i += kBThreads) Jb[i] = i < k ? s_sel[i] : -1;
-        // one wave per column, lane i holds z_i (k <= 64): right-looking
-        // substitution, z_t broadcast by a shuffle
-        for (int c = wave; c < n; c += kBWaves) {
-            T* zc = Zb + (int64_t)c * kb;
-            if (nu[c] < 0.0) {
-                int sidx = 0;
+        // four lanes per column (a quad), lane c of the quad holds z_q for
+        // q = 4 i + c: back substitution with the solved z_t broadcast from
+        // its owner inside the quad (DPP quad permutes)
+        for (int l0 = tid / 4; l0 < n; l0 += kBThreads / 4) {
+            const int l = l0;
+            const int c = tid % 4;
+            T* zc = Zb + (int64_t)l * kb;
+            const bool dead = snu[l] < 0.0;
+            double z[kBMaxK / 4];
+#pragma unroll
+            for (int i = 0; i < kBMaxK / 4; ++i) {
+                const int qq = 4 * i + c;
+                z[i] = (!dead && qq < k) ? (double)zc[qq] : 0.0;
+            }
+#pragma unroll
+            for (int i = kBMaxK / 4 - 1; i >= 0; --i) {
+#pragma unroll
+                for (int r = 3; r >= 0; --r) {
+                    const int t = 4 * i + r;
+                    if (t >= k) continue;  // uniform
+                    double zt = z[i] / sR[t * (kBMaxK + 1) + t];
+                    zt = r == 0 ? dpp_f64<0x00>(zt) : (r == 1 ? dpp_f64<0x55>(zt) : (r == 2 ? dpp_f64<0xAA>(zt) : dpp_f64<0xFF>(zt)));
+                    if (c == r) z[i] = zt;
+#pragma unroll
+                    for (int i2 = 0; i2 <= i; ++i2) {
+                        const int qq = 4 * i2 + c;
+                        if (qq < t) z[i2] -= sR[qq * (kBMaxK + 1) + t] * zt;
+                    }
+                }
+            }
+            int sidx = -1;
+            if (dead)
                 for (int i = 0; i < k; ++i)
-                    if (s_sel[i] == c) sidx = i;
-                if (lane < kb) zc[lane] = (T)(lane == sidx ? 1.0 : 0.0);
-                continue;
+                    if (s_sel[i] == l) sidx = i;
+#pragma unroll
+            for (int i = 0; i < kBMaxK / 4; ++i) {
+                const int qq = 4 * i + c;
+                if (qq < kb) zc[qq] = dead ? (T)(qq == sidx ? 1.0 : 0.0) : (T)(qq < k ? z[i] : 0.0);
             }
-            double z = lane < k ? (double)W[(int64_t)c * m + lane] : 0.0;
-            for (int t = k - 1; t >= 0; --t) {
-                const double zt = __shfl(z, t, kWave) / sR[t * (kBMaxK + 1) + t];
-                if (lane == t) z = zt;
-                if (lane < t) z -= sR[lane * (kBMaxK + 1) + t] * zt;
-            }
-            if (lane < kb) zc[lane] = (T)(lane < k ? z : 0.0);
         }
         if (tid == 0) info[b] = miid_info{k, status, a_norm, resid, 0, k};
         __syncthreads();
@@ -308,10 +399,10 @@ using namespace miid;
 namespace {
 struct BPlan {
     int grid;
-    size_t oOrder, oQueue, oSlab, total;
-    int64_t slab_elems;
+    size_t oOrder, oQueue, oW, total;
 };
 
+// One workgroup per CU (8 waves; LDS: the block or two column tiles of it).
 BPlan batched_plan(int32_t nblk, size_t esz) {
     BPlan P;
     int dev = 0, cus = 256;
@@ -320,14 +411,13 @@ BPlan batched_plan(int32_t nblk, size_t esz) {
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
     }
     P.grid = std::max(1, std::min(nblk, cus));
-    P.slab_elems = (int64_t)kBMaxM * kBMaxN;
     size_t off = 0;
     P.oOrder = off;
     off = align_up(off + (size_t)std::max(nblk, 1) * 4, 256);
     P.oQueue = off;
     off = align_up(off + 4, 256);
-    P.oSlab = off;
-    off = align_up(off + (size_t)P.grid * P.slab_elems * esz, 256);
+    P.oW = off;
+    off = align_up(off + (size_t)P.grid * kBMaxM * kBMaxN * esz, 256);
     P.total = off;
     return P;
 }
@@ -371,14 +461,27 @@ int id_batched(int32_t nblk, const void* A, const int64_t* a_off, const int32_t*
         hipLaunchKernelGGL(k_iota, dim3(64), dim3(256), 0, s, order, nblk, queue);
     }
     const int pr = prof_take(MIID_K_BATCHED, 0, nblk, 0);
+    const size_t shmem = (size_t)bdyn_bytes((int)esz);
     if (dtype == MIID_F64) {
-        MIID_LAUNCH(pr, k_batched<double>, dim3(P.grid), dim3(kBThreads), 0, s, (const double*)A, a_off, m, n,
-                           nblk, eps, kmax, J, j_off, (double*)Z, z_off, info, order, queue,
-                           reinterpret_cast<double*>(w + P.oSlab), P.slab_elems);
+        static bool attr64 = false;
+        if (!attr64) {
+            MIID_HIP(hipFuncSetAttribute((const void*)k_batched<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         bdyn_bytes(8)));
+            attr64 = true;
+        }
+        MIID_LAUNCH(pr, k_batched<double>, dim3(P.grid), dim3(kBThreads), shmem, s, (const double*)A, a_off, m, n,
+                    nblk, eps, kmax, J, j_off, (double*)Z, z_off, info, order, queue,
+                    reinterpret_cast<double*>(w + P.oW));
     } else {
-        MIID_LAUNCH(pr, k_batched<float>, dim3(P.grid), dim3(kBThreads), 0, s, (const float*)A, a_off, m, n, nblk,
-                           eps, kmax, J, j_off, (float*)Z, z_off, info, order, queue,
-                           reinterpret_cast<float*>(w + P.oSlab), P.slab_elems);
+        static bool attr32 = false;
+        if (!attr32) {
+            MIID_HIP(hipFuncSetAttribute((const void*)k_batched<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         bdyn_bytes(4)));
+            attr32 = true;
+        }
+        MIID_LAUNCH(pr, k_batched<float>, dim3(P.grid), dim3(kBThreads), shmem, s, (const float*)A, a_off, m, n,
+                    nblk, eps, kmax, J, j_off, (float*)Z, z_off, info, order, queue,
+                    reinterpret_cast<float*>(w + P.oW));
     }
     MIID_HIP(hipGetLastError());
     return 0;
