@@ -235,7 +235,20 @@ def main() -> int:
             kms = sum(r.ms for r in kb) / len(kb)
             extra["batched_kernel_ms"] = round(kms, 4)
             extra["batched_GBps_blocks"] = round(blocks.A.size * 4 / (kms * 1e-3) / 1e9, 1)
-        log(f"[bench] batched {ms_b:.3f} ms = {extra['batched_ids_per_s']:.0f} IDs/s")
+        # the same launch replayed from a captured HIP graph
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            miid_api.batched_raw(Ab, blocks.a_off, blocks.m, blocks.n, 1e-6, 64, out=out_b)
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        extra["batched_graph_ms"] = round((t1 - t0) * 1000.0 / args.steps, 4)
+        log(f"[bench] batched {ms_b:.3f} ms = {extra['batched_ids_per_s']:.0f} IDs/s "
+            f"(graph replay {extra['batched_graph_ms']} ms)")
 
     if "bwd" in only:
         # differentiable ID: forward (FP32 ID, k = 128) + adjoint on 2048 x 8192
