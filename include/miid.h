@@ -53,6 +53,24 @@ typedef enum { MIID_F32 = 0, MIID_F64 = 1 } miid_dtype;
 /* option flags */
 #define MIID_NO_REFINE 1u      /* skip the refinement step of the triangular solve */
 
+/* Tuning hints, 4-bit fields of miid_opts.flags (0 = library default).  They
+ * change launch shapes only, never the arithmetic's definition; the
+ * autotuner of the Python package picks them by timing.
+ *  CPW   id_cpqr/rid: columns per wave of the two-launch blocked path's
+ *        F-GEMV (1, 2 or 4)
+ *  NP    id_cpqr/rid: column passes per wave of the one-launch fused path
+ *        for short matrices (1, 2 or 4)
+ *  PATH  id_cpqr/rid: 1 = blocked two-launch path, 2 = fused path (taken
+ *        only where eligible: at most 576 rows in FP32 / 288 in FP64,
+ *        panels of at most 32)
+ *  TILE  id_batched: streamed column tile of a block that does not fit in
+ *        LDS, in units of 8 KiB (1..4)                                      */
+#define MIID_HINT_CPW_SHIFT 8
+#define MIID_HINT_NP_SHIFT 12
+#define MIID_HINT_PATH_SHIFT 16
+#define MIID_HINT_TILE_SHIFT 20
+#define MIID_HINT(field_shift, value) (((uint32_t)(value) & 15u) << (field_shift))
+
 typedef struct {
     int32_t k;      /* > 0: fixed rank.  0: tolerance mode: the smallest k with
                        ||R22||_F <= eps * ||A||_F (estimated from the downdated
@@ -60,7 +78,7 @@ typedef struct {
     int32_t kmax;   /* tolerance mode cap (ignored when k > 0); rows of Z/J */
     double eps;     /* relative tolerance for tolerance mode             */
     int32_t nb;     /* panel width of the blocked QR, 0 = library default */
-    uint32_t flags; /* MIID_NO_REFINE                                    */
+    uint32_t flags; /* MIID_NO_REFINE | MIID_HINT(...) fields            */
 } miid_opts;
 
 typedef struct {
@@ -165,11 +183,13 @@ int rid_sketch_cpqr(const float *A, int64_t m, int64_t n, int64_t lda,
  *
  *  A      (2)  packed blocks, dtype
  *  a_off, m, n (3-5) device int64 / int32 / int32 arrays of length nblk
- *  J      (9)  packed int32: block b owns kmax_b entries at j_off[b]
- *  Z      (11) packed dtype: block b owns a kmax_b x n[b] column-major
+ *  opts   (7)  host: eps, kmax and flags (MIID_HINT(MIID_HINT_TILE_SHIFT, t));
+ *              k and nb are ignored
+ *  J      (8)  packed int32: block b owns kmax_b entries at j_off[b]
+ *  Z      (10) packed dtype: block b owns a kmax_b x n[b] column-major
  *              matrix (leading dimension kmax_b) at z_off[b]; rows >= k_out
  *              are zero
- *  info   (13) nblk miid_info entries
+ *  info   (12) nblk miid_info entries
  * Limits: 1 <= m[b] <= 256, m[b] <= n[b] <= 1024, 1 <= kmax <= 64.  A block
  * outside them is skipped with k_out = 0 and status MIID_BLOCK_UNSUPPORTED;
  * the others are unaffected (likewise a block holding a NaN only gets its
@@ -178,7 +198,7 @@ int rid_sketch_cpqr(const float *A, int64_t m, int64_t n, int64_t lda,
  * ---------------------------------------------------------------------- */
 size_t miid_batched_workspace(int32_t nblk, miid_dtype dtype);
 int id_batched(int32_t nblk, const void *A, const int64_t *a_off, const int32_t *m,
-               const int32_t *n, miid_dtype dtype, double eps, int32_t kmax,
+               const int32_t *n, miid_dtype dtype, const miid_opts *opts,
                int32_t *J, const int64_t *j_off, void *Z, const int64_t *z_off,
                miid_info *info, void *ws, size_t ws_bytes, void *stream);
 

@@ -10,5 +10,6 @@ memory and the stream).
 """
 from ._abi import MiidError, load  # noqa: F401
 from .api import IDResult, BatchedResult, id, rid, batched, id_backward, IDFunction  # noqa: F401
+from . import autotune  # noqa: F401
 
-__all__ = ["IDResult", "id", "rid", "batched", "id_backward", "IDFunction", "MiidError", "load"]
+__all__ = ["IDResult", "id", "rid", "batched", "id_backward", "IDFunction", "MiidError", "load", "autotune"]

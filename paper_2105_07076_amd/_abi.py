@@ -34,6 +34,18 @@ EXPORTED = [
 ]
 
 
+# tuning-hint fields of miid_opts.flags (4 bits each, 0 = library default)
+MIID_HINT_CPW_SHIFT = 8
+MIID_HINT_NP_SHIFT = 12
+MIID_HINT_PATH_SHIFT = 16
+MIID_HINT_TILE_SHIFT = 20
+
+
+def hint(shift: int, value: int) -> int:
+    """One tuning-hint field of miid_opts.flags."""
+    return (int(value) & 15) << shift
+
+
 class MiidOpts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("kmax", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("nb", ctypes.c_int32), ("flags", ctypes.c_uint32)]
@@ -80,7 +92,7 @@ def load(path: str = LIB_PATH):
         lib.miid_batched_workspace.restype = SZ
         lib.miid_batched_workspace.argtypes = [I32, ctypes.c_int]
         lib.id_batched.restype = ctypes.c_int
-        lib.id_batched.argtypes = [I32, P, P, P, P, ctypes.c_int, ctypes.c_double, I32, P, P, P, P, P, P, SZ, P]
+        lib.id_batched.argtypes = [I32, P, P, P, P, ctypes.c_int, ctypes.POINTER(MiidOpts), P, P, P, P, P, P, SZ, P]
     if hasattr(lib, "id_backward"):
         lib.miid_backward_workspace.restype = SZ
         lib.miid_backward_workspace.argtypes = [I64, I64, I32, ctypes.c_int]

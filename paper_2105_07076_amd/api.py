@@ -84,7 +84,7 @@ def _read_info(info_dev: torch.Tensor) -> _abi.MiidInfo:
     return _abi.MiidInfo.from_buffer_copy(host)
 
 
-def _opts(k, eps, kmax, nb, refine) -> _abi.MiidOpts:
+def _opts(k, eps, kmax, nb, refine, hints: int = 0) -> _abi.MiidOpts:
     o = _abi.MiidOpts()
     if (k is None) == (eps is None):
         raise ValueError("give exactly one of k or eps")
@@ -92,15 +92,16 @@ def _opts(k, eps, kmax, nb, refine) -> _abi.MiidOpts:
     o.kmax = int(kmax) if kmax is not None else 0
     o.eps = float(eps) if eps is not None else 0.0
     o.nb = int(nb)
-    o.flags = 0 if refine else _abi.MIID_NO_REFINE
+    o.flags = (0 if refine else _abi.MIID_NO_REFINE) | int(hints)
     return o
 
 
 def id_raw(A: torch.Tensor, k: int | None = None, eps: float | None = None, kmax: int | None = None,
            nb: int = 0, refine: bool = True, want_C: bool = True, want_R11: bool = False,
-           out: dict | None = None):
+           out: dict | None = None, hints: int = 0):
     """Enqueue id_cpqr without synchronising.  Returns a dict of device
-    tensors (J, Z, C, R11, info) sized for kmax; ``out`` reuses buffers."""
+    tensors (J, Z, C, R11, info) sized for kmax; ``out`` reuses buffers;
+    ``hints`` are MIID_HINT fields (see :mod:`.autotune`)."""
     lib = _abi.load()
     if A.dtype not in _DT or not A.is_cuda:
         raise TypeError("A must be a float32/float64 CUDA tensor")
@@ -110,7 +111,7 @@ def id_raw(A: torch.Tensor, k: int | None = None, eps: float | None = None, kmax
     if kmax is None:
         kmax = min(M, N) if k is None else k
     kk = k if k is not None else kmax
-    opts = _opts(k, eps, kmax, nb, refine)
+    opts = _opts(k, eps, kmax, nb, refine, hints)
     dt = _DT[A.dtype]
     ws_bytes = lib.miid_id_workspace(M, N, dt, ctypes.byref(opts))
     if ws_bytes == 0:
@@ -145,18 +146,21 @@ def _finish(out: dict, Y=None) -> IDResult:
 
 
 def id(A: torch.Tensor, k: int | None = None, eps: float | None = None, kmax: int | None = None,
-       nb: int = 0, refine: bool = True, want_C: bool = True, want_R11: bool = False) -> IDResult:
+       nb: int = 0, refine: bool = True, want_C: bool = True, want_R11: bool = False,
+       hints: int = 0) -> IDResult:
     """Deterministic ID of A (m x n, float32/float64, on the GPU).
 
     Fixed rank ``k``, or tolerance mode ``eps`` (relative, on ||R22||_F) with
-    cap ``kmax``.  m > n gives the dual ID of A^T (``transposed``)."""
-    out = id_raw(A, k=k, eps=eps, kmax=kmax, nb=nb, refine=refine, want_C=want_C, want_R11=want_R11)
+    cap ``kmax``.  m > n gives the dual ID of A^T (``transposed``).  ``nb``
+    and ``hints`` set launch shapes only (see :mod:`.autotune`)."""
+    out = id_raw(A, k=k, eps=eps, kmax=kmax, nb=nb, refine=refine, want_C=want_C, want_R11=want_R11,
+                 hints=hints)
     return _finish(out)
 
 
 def rid_raw(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: float | None = None,
             kmax: int | None = None, mode: int = 1, nb: int = 0, refine: bool = True, want_C: bool = True,
-            want_Y: bool = False, want_R11: bool = False, out: dict | None = None):
+            want_Y: bool = False, want_R11: bool = False, out: dict | None = None, hints: int = 0):
     """Enqueue rid_sketch_cpqr without synchronising (see :func:`rid`)."""
     lib = _abi.load()
     if A.dtype != torch.float32 or not A.is_cuda:
@@ -172,7 +176,7 @@ def rid_raw(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: flo
     if kmax is None:
         kmax = l if k is None else k
     kk = k if k is not None else kmax
-    opts = _opts(k, eps, kmax, nb, refine)
+    opts = _opts(k, eps, kmax, nb, refine, hints)
     ws_bytes = lib.miid_rid_workspace(m, n, l, ctypes.byref(opts))
     if ws_bytes == 0:
         _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_rid_workspace")
@@ -198,7 +202,7 @@ def rid_raw(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: flo
 
 def rid(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: float | None = None,
         kmax: int | None = None, mode: int = 1, nb: int = 0, refine: bool = True, want_C: bool = True,
-        want_Y: bool = False, want_R11: bool = False) -> IDResult:
+        want_Y: bool = False, want_R11: bool = False, hints: int = 0) -> IDResult:
     """Randomized ID of A (m x n float32, m <= n) with the Gaussian row sketch
     Y = omega A computed on the matrix cores.
 
@@ -207,7 +211,7 @@ def rid(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: float |
     passes), 0 rounds it once.  J and T come from the CPQR of Y; C = A[:, J].
     ``a_norm``/``r22_norm`` in the result refer to Y."""
     out = rid_raw(A, omega, k=k, eps=eps, kmax=kmax, mode=mode, nb=nb, refine=refine, want_C=want_C,
-                  want_Y=want_Y, want_R11=want_R11)
+                  want_Y=want_Y, want_R11=want_R11, hints=hints)
     return _finish(out, Y=out["Y"])
 
 
@@ -235,7 +239,8 @@ class BatchedResult:
         return Jh, Zh
 
 
-def batched_raw(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, out: dict | None = None):
+def batched_raw(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, out: dict | None = None,
+                hints: int = 0):
     """Enqueue id_batched without synchronising.  ``A`` is the packed blocks
     (1-D float32/float64 CUDA tensor), ``a_off``/``m``/``n`` host sequences."""
     import numpy as np
@@ -264,19 +269,21 @@ def batched_raw(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, out: d
     dt = _DT[A.dtype]
     ws_bytes = lib.miid_batched_workspace(out["nblk"], dt)
     ws = _WS.get("batched", ws_bytes, dev)
+    opts = _abi.MiidOpts()
+    opts.k, opts.kmax, opts.eps, opts.nb, opts.flags = 0, int(kmax), float(eps), 0, int(hints)
     rc = lib.id_batched(out["nblk"], _ptr(A), _ptr(out["a_off"]), _ptr(out["m"]), _ptr(out["n"]), dt,
-                        float(eps), int(kmax), _ptr(out["J"]), _ptr(out["j_off"]), _ptr(out["Z"]),
+                        ctypes.byref(opts), _ptr(out["J"]), _ptr(out["j_off"]), _ptr(out["Z"]),
                         _ptr(out["z_off"]), _ptr(out["info"]), _ptr(ws), ws_bytes, _stream())
     _abi.check(rc, "id_batched")
     return out
 
 
-def batched(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64) -> BatchedResult:
+def batched(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, hints: int = 0) -> BatchedResult:
     """Tolerance-mode IDs of many independent blocks in one launch: block b is
     m[b] x n[b] (column-major) at A[a_off[b]:]; its rank is the smallest k with
     ||R22||_F <= eps ||A_b||_F, at most min(m_b, n_b, kmax)."""
     import numpy as np
-    out = batched_raw(A, a_off, m, n, eps, kmax)
+    out = batched_raw(A, a_off, m, n, eps, kmax, hints=hints)
     raw = out["info"].cpu().numpy().tobytes()
     sz = ctypes.sizeof(_abi.MiidInfo)
     infos = [_abi.MiidInfo.from_buffer_copy(raw[i * sz:(i + 1) * sz]) for i in range(out["nblk"])]

@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
                                                        T* __restrict__ Z, const int64_t* __restrict__ z_off,
                                                        miid_info* __restrict__ info,
                                                        const int32_t* __restrict__ order, int32_t* __restrict__ queue,
-                                                       T* __restrict__ Wscr) {
+                                                       T* __restrict__ Wscr, int tile_bytes) {
     constexpr int kDyn = bdyn_bytes((int)sizeof(T)) / (int)sizeof(T);
     constexpr int kTileMax = kBTileBytes / (int)sizeof(T);
     constexpr int kStage = kTileMax / kBThreads;  // staged elements per thread
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
         const T* Ab = A + a_off[b];
         T* Zb = Z + z_off[b];
         const bool resident = m * n <= kDyn;
-        const int TC = resident ? n : min(n, min(kDyn / 2, kTileMax) / m);
+        const int TC = resident ? n : max(1, min(n, min(kDyn / 2, min(kTileMax, tile_bytes / (int)sizeof(T))) / m));
         const int nt = (n + TC - 1) / TC;
         T* buf0 = lds;
         T* buf1 = lds + (resident ? 0 : TC * m);
@@ -431,7 +431,7 @@ size_t miid_batched_workspace(int32_t nblk, miid_dtype dtype) {
 }
 
 int id_batched(int32_t nblk, const void* A, const int64_t* a_off, const int32_t* m, const int32_t* n,
-               miid_dtype dtype, double eps, int32_t kmax, int32_t* J, const int64_t* j_off, void* Z,
+               miid_dtype dtype, const miid_opts* opts, int32_t* J, const int64_t* j_off, void* Z,
                const int64_t* z_off, miid_info* info, void* ws, size_t ws_bytes, void* stream) {
     if (nblk < 1) return -1;
     if (!A) return -2;
@@ -439,14 +439,17 @@ int id_batched(int32_t nblk, const void* A, const int64_t* a_off, const int32_t*
     if (!m) return -4;
     if (!n) return -5;
     if (dtype != MIID_F32 && dtype != MIID_F64) return -6;
-    if (!(eps >= 0.0)) return -7;
-    if (kmax < 1 || kmax > kBMaxK) return -8;
-    if (!J) return -9;
-    if (!j_off) return -10;
-    if (!Z) return -11;
-    if (!z_off) return -12;
-    if (!info) return -13;
-    if (!ws) return -14;
+    if (!opts || !(opts->eps >= 0.0) || opts->kmax < 1 || opts->kmax > kBMaxK) return -7;
+    if (!J) return -8;
+    if (!j_off) return -9;
+    if (!Z) return -10;
+    if (!z_off) return -11;
+    if (!info) return -12;
+    if (!ws) return -13;
+    const double eps = opts->eps;
+    const int32_t kmax = opts->kmax;
+    const int tile_hint = (int)((opts->flags >> MIID_HINT_TILE_SHIFT) & 15u);
+    const int tile_bytes = (tile_hint >= 1 && tile_hint <= 4) ? tile_hint * 8 * 1024 : kBTileBytes;
     const size_t esz = dtype == MIID_F64 ? 8 : 4;
     const BPlan P = batched_plan(nblk, esz);
     if (ws_bytes < P.total) return MIID_E_WORKSPACE;
@@ -471,7 +474,7 @@ int id_batched(int32_t nblk, const void* A, const int64_t* a_off, const int32_t*
         }
         MIID_LAUNCH(pr, k_batched<double>, dim3(P.grid), dim3(kBThreads), shmem, s, (const double*)A, a_off, m, n,
                     nblk, eps, kmax, J, j_off, (double*)Z, z_off, info, order, queue,
-                    reinterpret_cast<double*>(w + P.oW));
+                    reinterpret_cast<double*>(w + P.oW), tile_bytes);
     } else {
         static bool attr32 = false;
         if (!attr32) {
@@ -481,7 +484,7 @@ int id_batched(int32_t nblk, const void* A, const int64_t* a_off, const int32_t*
         }
         MIID_LAUNCH(pr, k_batched<float>, dim3(P.grid), dim3(kBThreads), shmem, s, (const float*)A, a_off, m, n,
                     nblk, eps, kmax, J, j_off, (float*)Z, z_off, info, order, queue,
-                    reinterpret_cast<float*>(w + P.oW));
+                    reinterpret_cast<float*>(w + P.oW), tile_bytes);
     }
     MIID_HIP(hipGetLastError());
     return 0;

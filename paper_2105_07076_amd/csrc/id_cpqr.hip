@@ -1368,23 +1368,30 @@ __global__ void __launch_bounds__(kThreads) k_cpqr_resident(const T* __restrict_
 // host side
 // ---------------------------------------------------------------------------
 
-// Columns per wave of the F-GEMV (1, 2 or 4).  One column per wave measured
-// fastest both for 4096-row matrices and for 266-row sketches;
-// MIID_GEMV_CPW overrides it for tuning.
-static int gemv_cols_per_wave(int64_t) {
+// Columns per wave of the F-GEMV (1, 2 or 4): the CPW hint, else
+// MIID_GEMV_CPW, else one (measured fastest for 4096-row matrices).
+static int gemv_cols_per_wave(uint32_t flags) {
+    const int h = (int)((flags >> MIID_HINT_CPW_SHIFT) & 15u);
+    if (h == 1 || h == 2 || h == 4) return h;
     const char* e = std::getenv("MIID_GEMV_CPW");
     const int v = e ? std::atoi(e) : 1;
     return (v == 2 || v == 4) ? v : 1;
 }
 
-// The fused path is taken for matrices of at most kFusedMaxRows rows unless
-// MIID_FUSED=0; MIID_FUSED_NP (2, 4 or 8) overrides the columns per wave.
-static bool fused_enabled() {
+// The fused path is taken where eligible unless the PATH hint asks for the
+// blocked one (or, without a hint, MIID_FUSED=0); the NP hint, else
+// MIID_FUSED_NP, else one workgroup per CU sets the column passes per wave.
+static bool fused_enabled(uint32_t flags) {
+    const int h = (int)((flags >> MIID_HINT_PATH_SHIFT) & 15u);
+    if (h == 1) return false;
+    if (h == 2) return true;
     const char* e = std::getenv("MIID_FUSED");
     return !(e && e[0] == '0');
 }
 
-static int fused_np(int64_t n) {
+static int fused_np(int64_t n, uint32_t flags) {
+    const int h = (int)((flags >> MIID_HINT_NP_SHIFT) & 15u);
+    if (h == 1 || h == 2 || h == 4) return h;
     const char* e = std::getenv("MIID_FUSED_NP");
     if (e) {
         const int v = std::atoi(e);
@@ -1414,10 +1421,10 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
     P->esz = dtype == MIID_F64 ? 8 : 4;
     P->ldw = (int64_t)align_up((size_t)P->m, 64);
     if ((size_t)P->ldw * P->esz > kMaxVecLds) return MIID_E_UNSUPPORTED;
-    P->cpw = gemv_cols_per_wave(P->m);
+    P->cpw = gemv_cols_per_wave(o->flags);
     P->npart = (int)((P->n + 4 * P->cpw - 1) / (4 * P->cpw));
     P->NA = (int)((P->ldw + kRowsPerChunk - 1) / kRowsPerChunk);
-    P->fnp = fused_np(P->n);
+    P->fnp = fused_np(P->n, o->flags);
     P->fnpart = (int)((P->n + 32 * P->fnp - 1) / (32 * P->fnp));
     {
         // 16-byte row groups per lane of a 16-lane column group
@@ -1425,7 +1432,7 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
         const int64_t per_lane = (ng + 15) / 16;
         P->fgl = per_lane <= 5 ? 5 : (per_lane <= 9 ? 9 : 0);
     }
-    P->fused = P->ldw <= kFusedMaxRows && P->fgl > 0 && P->nb <= kFusedMaxNb && fused_enabled();
+    P->fused = P->ldw <= kFusedMaxRows && P->fgl > 0 && P->nb <= kFusedMaxNb && fused_enabled(o->flags);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o2 = off;

@@ -92,9 +92,15 @@ def test_argument_validation_before_any_device_work():
                                1, None, 1, dummy, dummy, 1 << 30, None) == _abi.MIID_E_UNSUPPORTED
     assert lib.rid_sketch_cpqr(dummy, 10, 20, 10, dummy, 8, 8, 2, ctypes.byref(o), dummy, dummy, 4, None, 1, None,
                                1, None, 1, dummy, dummy, 1 << 30, None) == -8
-    # batched: kmax out of range -> -8
-    assert lib.id_batched(4, dummy, dummy, dummy, dummy, 0, 1e-6, 65, dummy, dummy, dummy, dummy, dummy, dummy,
-                          1 << 30, None) == -8
+    # batched: kmax out of range in the options -> -7
+    ob = _abi.MiidOpts()
+    ob.k, ob.kmax, ob.eps, ob.nb, ob.flags = 0, 65, 1e-6, 0, 0
+    assert lib.id_batched(4, dummy, dummy, dummy, dummy, 0, ctypes.byref(ob), dummy, dummy, dummy, dummy, dummy,
+                          dummy, 1 << 30, None) == -7
+    ob.kmax = 16
+    ob.eps = -1.0
+    assert lib.id_batched(4, dummy, dummy, dummy, dummy, 0, ctypes.byref(ob), dummy, dummy, dummy, dummy, dummy,
+                          dummy, 1 << 30, None) == -7
     # backward: k > m -> -7
     assert lib.id_backward(dummy, 10, 20, 10, 0, dummy, 11, dummy, 11, dummy, 11, None, 1, None, 1, dummy, 10,
                            dummy, 1 << 30, None) == -7
