@@ -34,7 +34,7 @@ constexpr int kBWaves = kBThreads / kWave;
 // dynamic LDS (V, then the block or its column tiles): what the 160 KB of a
 // CU leave beside the kernel's static arrays
 constexpr int bdyn_bytes(int) { return 148 * 1024; }
-constexpr int kBTileBytes = 32 * 1024;  // largest streamed column tile
+constexpr int kBTileBytes = 72 * 1024;  // default streamed column tile (at most half the dynamic LDS)
 constexpr int kBMaxM = 256;
 constexpr int kBMaxN = 1024;
 constexpr int kBMaxK = 64;
@@ -117,6 +117,8 @@ __device__ __forceinline__ double block_sum(double v, double* w_sum) {
 }
 
 // Persistent kernel: one block at a time per workgroup (8 waves, one per CU).
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
 template <typename T>
 __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, const int64_t* __restrict__ a_off,
                                                        const int32_t* __restrict__ mv, const int32_t* __restrict__ nv,
@@ -127,8 +129,6 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
                                                        const int32_t* __restrict__ order, int32_t* __restrict__ queue,
                                                        T* __restrict__ Wscr, int tile_bytes) {
     constexpr int kDyn = bdyn_bytes((int)sizeof(T)) / (int)sizeof(T);
-    constexpr int kTileMax = kBTileBytes / (int)sizeof(T);
-    constexpr int kStage = kTileMax / kBThreads;  // staged elements per thread
     constexpr int kRT = kBMaxM / 16;              // rows per lane of a column group
     constexpr int kGroups = kBWaves * 4;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -161,23 +161,17 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
         const T* Ab = A + a_off[b];
         T* Zb = Z + z_off[b];
         const bool resident = m * n <= kDyn;
-        const int TC = resident ? n : max(1, min(n, min(kDyn / 2, min(kTileMax, tile_bytes / (int)sizeof(T))) / m));
+        const int TC = resident ? n : max(1, min(n, min(kDyn / 2, tile_bytes / (int)sizeof(T)) / m));
         const int nt = (n + TC - 1) / TC;
         T* buf0 = lds;
         T* buf1 = lds + (resident ? 0 : TC * m);
-        if (resident) {
-            for (int e0 = 0; e0 < m * n; e0 += kStage * kBThreads) {
-                T x[kStage];
-#pragma unroll
-                for (int i = 0; i < kStage; ++i) {
-                    const int e = e0 + tid + i * kBThreads;
-                    x[i] = e < m * n ? Ab[e] : T(0);
-                }
-#pragma unroll
-                for (int i = 0; i < kStage; ++i) {
-                    const int e = e0 + tid + i * kBThreads;
-                    if (e < m * n) lds[e] = x[i];
-                }
+        if (resident) {  // the whole block straight into LDS
+            const int cntw = m * n * (int)(sizeof(T) / 4);
+            const uint32_t* s32 = reinterpret_cast<const uint32_t*>(Ab);
+            lds_u32* d32 = (lds_u32*)smem_raw;
+            for (int e0 = 0; e0 < cntw; e0 += kBThreads) {
+                const int e = e0 + tid;
+                if (e < cntw) __builtin_amdgcn_global_load_lds((const void*)(s32 + e), d32 + (e - lane), 4, 0, 0);
             }
             __syncthreads();
         }
@@ -191,30 +185,22 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
                 lds_barrier();
                 return;
             }
-            T x[kStage];
-            auto load = [&](int t) {
-                const int cnt = min(TC, n - t * TC) * m;
-                const T* s0 = src + (int64_t)t * TC * m;
-#pragma unroll
-                for (int i = 0; i < kStage; ++i) {
-                    const int e = tid + i * kBThreads;
-                    x[i] = e < cnt ? s0[e] : T(0);
+            // a tile is a contiguous range of src; it goes straight from
+            // global memory into LDS (global_load_lds: no registers, the
+            // next tile's copy in flight while the current one is updated)
+            auto issue = [&](int t) {
+                const int cntw = min(TC, n - t * TC) * m * (int)(sizeof(T) / 4);
+                const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src + (int64_t)t * TC * m);
+                lds_u32* d32 = (lds_u32*)smem_raw + ((t & 1) ? TC * m * (int)(sizeof(T) / 4) : 0);
+                for (int e0 = 0; e0 < cntw; e0 += kBThreads) {
+                    const int e = e0 + tid;
+                    if (e < cntw) __builtin_amdgcn_global_load_lds((const void*)(s32 + e), d32 + (e - lane), 4, 0, 0);
                 }
             };
-            auto store = [&](int t) {
-                const int cnt = min(TC, n - t * TC) * m;
-                T* dst = (t & 1) ? buf1 : buf0;
-#pragma unroll
-                for (int i = 0; i < kStage; ++i) {
-                    const int e = tid + i * kBThreads;
-                    if (e < cnt) dst[e] = x[i];
-                }
-            };
-            load(0);
-            store(0);
-            lds_barrier();
+            issue(0);
+            __syncthreads();
             for (int t = 0; t < nt; ++t) {
-                if (t + 1 < nt) load(t + 1);
+                if (t + 1 < nt) issue(t + 1);
                 const int c0 = t * TC, c1 = min(n, c0 + TC);
                 T* cur = (t & 1) ? buf1 : buf0;
                 for (int l = c0 + cgroup; l < c1; l += kGroups) fn(l, cur + (l - c0) * m);
@@ -224,8 +210,7 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
                     T* d0 = Wb + (int64_t)c0 * m;
                     for (int e = tid; e < cnt; e += kBThreads) d0[e] = cur[e];
                 }
-                if (t + 1 < nt) store(t + 1);
-                lds_barrier();
+                __syncthreads();  // the next tile has landed; this one is written back
             }
         };
 
@@ -449,7 +434,7 @@ int id_batched(int32_t nblk, const void* A, const int64_t* a_off, const int32_t*
     const double eps = opts->eps;
     const int32_t kmax = opts->kmax;
     const int tile_hint = (int)((opts->flags >> MIID_HINT_TILE_SHIFT) & 15u);
-    const int tile_bytes = (tile_hint >= 1 && tile_hint <= 4) ? tile_hint * 8 * 1024 : kBTileBytes;
+    const int tile_bytes = tile_hint >= 1 ? tile_hint * 8 * 1024 : kBTileBytes;
     const size_t esz = dtype == MIID_F64 ? 8 : 4;
     const BPlan P = batched_plan(nblk, esz);
     if (ws_bytes < P.total) return MIID_E_WORKSPACE;
