@@ -23,16 +23,6 @@ void report_hip_error(int code, const char* what, const char* file, int line);
         }                                                              \
     } while (0)
 
-// Butterfly sum over the 64 lanes of a wave.  Every lane ends with the same
-// value (each stage adds the same two operands on both partners), so the
-// result is identical on all lanes and from run to run.
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
-
 // Workgroup barrier that orders LDS only: global loads and stores issued
 // before it stay in flight (a plain __syncthreads also waits for them).  For
 // kernels whose threads exchange data through LDS alone.
@@ -92,6 +82,19 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
     return t;
 }
 
+// Butterfly sum over the 64 lanes of a wave.  Every lane ends with the same
+// value (each stage adds the same two operands on both partners), so the
+// result is identical on all lanes and from run to run.  Doubles take the
+// DPP form (wave_sum_dpp) instead.  Both need every lane of the wave active.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
+
 // (value, index) pair ordered by larger value, then smaller index.
 struct ArgMax {
     double v;
@@ -135,18 +138,8 @@ __device__ __forceinline__ ArgMax wave_argmax_dpp(ArgMax a) {
     return b;
 }
 
-__device__ __forceinline__ ArgMax wave_argmax(ArgMax a) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        double ov = __shfl_xor(a.v, off, kWave);
-        int32_t oi = __shfl_xor(a.i, off, kWave);
-        if (argmax_better(ov, oi, a.v, a.i)) {
-            a.v = ov;
-            a.i = oi;
-        }
-    }
-    return a;
-}
+// Argmax over the wave (every lane active); wave-uniform result.
+__device__ __forceinline__ ArgMax wave_argmax(ArgMax a) { return wave_argmax_dpp(a); }
 
 // Per-workgroup partial result of a pass over the alive columns: the best
 // residual norm with its column, and the sum of squared residual norms.

@@ -1416,9 +1416,9 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
     P->tol = o->k == 0;
     P->kmax = P->tol ? o->kmax : o->k;
     P->eps = o->eps;
-    // default panel width: 32 in FP64, 16 in FP32 (timed fastest on MI355X
-    // for 4096 x 16384 IDs and 266-row sketches)
-    P->nb = o->nb != 0 ? o->nb : (dtype == MIID_F32 ? 16 : 32);
+    // panel width: the caller's, else 32 (FP32 on the blocked path: 16, set
+    // below once the path is known)
+    P->nb = o->nb != 0 ? o->nb : 32;
     P->refine = !(o->flags & MIID_NO_REFINE);
     if (P->nb > kMaxNb || P->kmax > P->m || P->kmax > kMaxK) return MIID_E_UNSUPPORTED;
     P->esz = dtype == MIID_F64 ? 8 : 4;
@@ -1436,6 +1436,10 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
         P->fgl = per_lane <= 5 ? 5 : (per_lane <= 9 ? 9 : 0);
     }
     P->fused = P->ldw <= kFusedMaxRows && P->fgl > 0 && P->nb <= kFusedMaxNb && fused_enabled(o->flags);
+    // FP32 blocked path: 16 timed fastest for 4096 x 16384 IDs; the fused
+    // path keeps 32 (fewer roundings of the eagerly updated trailing matrix
+    // for the same time)
+    if (o->nb == 0 && dtype == MIID_F32 && !P->fused) P->nb = 16;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o2 = off;
