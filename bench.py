@@ -85,9 +85,9 @@ def time_id(miid_api, lib, A, k, steps, warmup, sample_every=7):
 GEMV_TRAFFIC = {
     "bytes_per_launch": 528.8e6,
     "sources": {
-        "paper_2105_07076_amd/csrc/id_cpqr.hip": "d649bc4789caa2f582b2b0c855b6a2e974a33815d70265f3cf5e165993d6a54a",
-        "paper_2105_07076_amd/csrc/common.hpp": "3667dddd26f0fe4488a3519628c81272cffe7f158460fdb3c2a7882679b4564d",
-        "paper_2105_07076_amd/csrc/cpqr.hpp": "2141e9679dacc130355cf161968e90157a3db20b2c863bb60ddd122adfc1b186",
+        "paper_2105_07076_amd/csrc/id_cpqr.hip": "5d4b8cedf3404c742bc823457358466fc9454a3b5bdfc8bbfbe7e264a5452475",
+        "paper_2105_07076_amd/csrc/common.hpp": "9ee920512e6556ed77256f87fc251b5fe7a2dbd6efc59cff38f69e9222716f13",
+        "paper_2105_07076_amd/csrc/cpqr.hpp": "e002806934b941a7b8c686698d55d3e93423adffd1eefd46e79fcbc23b7204ff",
     },
 }
 
@@ -129,6 +129,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing on the host")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--host-input", action="store_true",
+                    help="build the 4096 x 16384 input with the numpy recipe on the host (no device QR; "
+                         "for counter-collection runs)")
     ap.add_argument("--only", default="all",
                     help="comma list of sections to run: id64,id32,rid,batched,bwd (default all); "
                          "the value is the FP64 ID, so id64 always runs")
@@ -150,7 +153,10 @@ def main() -> int:
     m, n, k = 4096, 16384, 256
     log(f"[bench] generating A {m}x{n} on the GPU")
     s = np.exp(-np.arange(m) / 64.0)
-    A64 = idgen.lowrank_plus_noise_device(args.seed, m, n, s, 1e-8, dtype=torch.float64)
+    if args.host_input:
+        A64 = torch.tensor(idgen.cfg2(seed=args.seed, m=m, n=n)[0], device="cuda").t().contiguous().t()
+    else:
+        A64 = idgen.lowrank_plus_noise_device(args.seed, m, n, s, 1e-8, dtype=torch.float64)
     torch.cuda.synchronize()
 
     log("[bench] FP64 ID")
@@ -253,8 +259,11 @@ def main() -> int:
     if "bwd" in only:
         # differentiable ID: forward (FP32 ID, k = 128) + adjoint on 2048 x 8192
         log("[bench] ID forward + adjoint, 2048 x 8192, k = 128, FP32")
-        A5 = idgen.lowrank_plus_noise_device(5, 2048, 8192, np.exp(-np.arange(2048) / 32.0), 1e-6,
-                                             dtype=torch.float32)
+        if args.host_input:
+            A5 = torch.tensor(idgen.cfg5()[0], dtype=torch.float32, device="cuda").t().contiguous().t()
+        else:
+            A5 = idgen.lowrank_plus_noise_device(5, 2048, 8192, np.exp(-np.arange(2048) / 32.0), 1e-6,
+                                                 dtype=torch.float32)
         g5 = torch.Generator(device="cuda")
         g5.manual_seed(1005)
         gC5 = torch.randn(128, 2048, generator=g5, device="cuda").t()
