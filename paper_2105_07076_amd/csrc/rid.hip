@@ -24,7 +24,6 @@ typedef float f4v_t __attribute__((ext_vector_type(4)));
 
 constexpr int kSkThreads = 256;
 constexpr int kSkCols = 64;   // columns of A (and Y) per workgroup, 16 per wave
-constexpr int kSkMTB = 17;    // 16-row tiles of Y per workgroup (272 rows)
 constexpr int kSkK = 32;      // K per MFMA
 constexpr int kSkLdsRow = kSkK + 8;  // bf16 per LDS row (padding against bank conflicts)
 
@@ -56,72 +55,119 @@ __global__ void k_omega_t(const uint16_t* __restrict__ Om, int l, int64_t m, int
 // k = 8 (l / 16) + e of the A operand, k = 8 (l / 16) + e and column l % 16
 // of the B operand; output element r of lane l is row 4 (l / 16) + r,
 // column l % 16.
-template <bool SPLIT, bool VEC>
+// K advances in chunks of KC (KC / 32 MFMA steps): the Omega chunk
+// (16 MTB rows x KC) is double-buffered in LDS and the next chunk's Omega
+// and A loads are in flight while the current chunk is multiplied, so there
+// is one barrier per chunk.
+template <bool SPLIT, bool VEC, int MTB, int KC>
 __global__ void __launch_bounds__(kSkThreads) k_sketch(const float* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                        const uint16_t* __restrict__ Wt, int64_t mpad, int mt_total,
                                                        float* __restrict__ S, int64_t ldw, float* __restrict__ Yout,
                                                        int64_t ldy, int l) {
-    __shared__ __align__(16) uint16_t sW[kSkMTB * 16 * kSkLdsRow];
+    constexpr int LR = KC + 8;             // bf16 per LDS row (padding against bank conflicts)
+    constexpr int KS = KC / kSkK;          // MFMA steps per chunk
+    constexpr int ROWS = MTB * 16;
+    constexpr int SEG = KC / 8;            // 16-byte segments of a row of the chunk
+    constexpr int NSEG = ROWS * SEG;
+    constexpr int SPT = (NSEG + kSkThreads - 1) / kSkThreads;  // segments staged per thread
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    uint16_t* sW = reinterpret_cast<uint16_t*>(smem_raw);  // [2][ROWS][LR]
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
-    const int mt0 = blockIdx.y * kSkMTB;
-    const int mtb = min(kSkMTB, mt_total - mt0);
+    const int mt0 = blockIdx.y * MTB;
+    const int mtb = min(MTB, mt_total - mt0);
     const int64_t col = (int64_t)blockIdx.x * kSkCols + wave * 16 + lane % 16;  // this lane's A column
     const int kl = 8 * (lane / 16);                                            // this lane's k offset
     const bool colok = col < n;
     const float* ac = A + (colok ? col : 0) * lda;
 
-    f4v_t acc[kSkMTB];
+    f4v_t acc[MTB];
 #pragma unroll
-    for (int t = 0; t < kSkMTB; ++t) acc[t] = f4v_t{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < MTB; ++t) acc[t] = f4v_t{0.f, 0.f, 0.f, 0.f};
 
-    auto load_a = [&](int64_t k0, float* x) {
-        const int64_t kb = k0 + kl;
-        if (VEC && colok && kb + 8 <= m) {
-            const float4 v0 = *reinterpret_cast<const float4*>(ac + kb);
-            const float4 v1 = *reinterpret_cast<const float4*>(ac + kb + 4);
-            x[0] = v0.x; x[1] = v0.y; x[2] = v0.z; x[3] = v0.w;
-            x[4] = v1.x; x[5] = v1.y; x[6] = v1.z; x[7] = v1.w;
-        } else {
+    uint4 stg[SPT];
+    auto load_w = [&](int64_t k0) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) x[e] = (colok && kb + e < m) ? ac[kb + e] : 0.f;
+        for (int i = 0; i < SPT; ++i) {
+            const int seg = tid + kSkThreads * i;
+            const int row = seg / SEG, sg = seg % SEG;
+            const int64_t kk = k0 + 8 * sg;
+            stg[i] = (seg < NSEG && row < 16 * mtb && kk < mpad)
+                         ? *reinterpret_cast<const uint4*>(Wt + (int64_t)(mt0 * 16 + row) * mpad + kk)
+                         : make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+    auto store_w = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < SPT; ++i) {
+            const int seg = tid + kSkThreads * i;
+            const int row = seg / SEG, sg = seg % SEG;
+            if (seg < NSEG) *reinterpret_cast<uint4*>(sW + (buf * ROWS + row) * LR + 8 * sg) = stg[i];
+        }
+    };
+    auto load_a = [&](int64_t k0, float (&x)[KS][8]) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int64_t kb = k0 + kSkK * ks + kl;
+            if (VEC && colok && kb + 8 <= m) {
+                const float4 v0 = *reinterpret_cast<const float4*>(ac + kb);
+                const float4 v1 = *reinterpret_cast<const float4*>(ac + kb + 4);
+                x[ks][0] = v0.x; x[ks][1] = v0.y; x[ks][2] = v0.z; x[ks][3] = v0.w;
+                x[ks][4] = v1.x; x[ks][5] = v1.y; x[ks][6] = v1.z; x[ks][7] = v1.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[ks][e] = (colok && kb + e < m) ? ac[kb + e] : 0.f;
+            }
         }
     };
 
-    float xa[8];
+    float xa[KS][8], xn[KS][8];
+    load_w(0);
     load_a(0, xa);
-    for (int64_t k0 = 0; k0 < mpad; k0 += kSkK) {
-        // stage the Omega tile (mtb * 16 rows x 32 k) in LDS, 16 bytes per thread-chunk
-        for (int e = tid; e < mtb * 16 * 4; e += kSkThreads) {
-            const int row = e / 4, ch = e % 4;
-            const uint4 w = *reinterpret_cast<const uint4*>(Wt + (int64_t)(mt0 * 16 + row) * mpad + k0 + ch * 8);
-            *reinterpret_cast<uint4*>(sW + row * kSkLdsRow + ch * 8) = w;
+    store_w(0);
+    __syncthreads();
+    int cur = 0;
+    for (int64_t k0 = 0; k0 < mpad; k0 += KC) {
+        const bool more = k0 + KC < mpad;
+        if (more) {
+            load_w(k0 + KC);
+            load_a(k0 + KC, xn);
         }
-        // this step's A operand, and the next step's loads in flight
-        bf16x8_t hi, lo;
+        const uint16_t* wb = sW + cur * ROWS * LR;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const __bf16 h = (__bf16)xa[e];
-            hi[e] = h;
-            if (SPLIT) lo[e] = (__bf16)(xa[e] - (float)h);
-        }
-        if (k0 + kSkK < mpad) load_a(k0 + kSkK, xa);
-        __syncthreads();
+        for (int ks = 0; ks < KS; ++ks) {
+            bf16x8_t hi, lo;
 #pragma unroll
-        for (int t = 0; t < kSkMTB; ++t) {
-            if (t < mtb) {
-                const bf16x8_t w = *reinterpret_cast<const bf16x8_t*>(sW + (t * 16 + lane % 16) * kSkLdsRow + kl);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, w, acc[t], 0, 0, 0);
-                if (SPLIT) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, w, acc[t], 0, 0, 0);
+            for (int e = 0; e < 8; ++e) {
+                const __bf16 h = (__bf16)xa[ks][e];
+                hi[e] = h;
+                if (SPLIT) lo[e] = (__bf16)(xa[ks][e] - (float)h);
+            }
+#pragma unroll
+            for (int t = 0; t < MTB; ++t) {
+                if (t < mtb) {
+                    const bf16x8_t w =
+                        *reinterpret_cast<const bf16x8_t*>(wb + (t * 16 + lane % 16) * LR + kSkK * ks + kl);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, w, acc[t], 0, 0, 0);
+                    if (SPLIT) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, w, acc[t], 0, 0, 0);
+                }
             }
         }
+        if (more) {
+            store_w(cur ^ 1);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) xa[ks][e] = xn[ks][e];
+        }
         __syncthreads();
+        cur ^= 1;
     }
     // output element r of lane l: Y[row = tile row + l % 16][col = wave col + 4 (l / 16) + r]
-#pragma unroll
     // (a predicate, not a break: a data-dependent exit from the unrolled loop
     // would put acc in scratch memory)
-    for (int t = 0; t < kSkMTB; ++t) {
+#pragma unroll
+    for (int t = 0; t < MTB; ++t) {
         const int64_t row = (int64_t)(mt0 + t) * 16 + lane % 16;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -130,6 +176,40 @@ __global__ void __launch_bounds__(kSkThreads) k_sketch(const float* __restrict__
             if (t < mtb && Yout && c < n && row < l) Yout[row + c * ldy] = acc[t][r];
         }
     }
+}
+
+// LDS bytes of a k_sketch instantiation (two Omega chunks)
+constexpr size_t sketch_lds(int mtb, int kc) { return (size_t)2 * mtb * 16 * (kc + 8) * 2; }
+
+template <bool SPLIT, bool VEC, int MTB, int KC>
+static hipError_t launch_sketch(int pr, hipStream_t s, int64_t n, int mt_total, const float* A, int64_t lda, int64_t m,
+                                const uint16_t* Wt, int64_t mpad, float* S, int64_t ldw, float* Y, int64_t ldy,
+                                int l) {
+    static bool attr = false;
+    constexpr size_t lds = sketch_lds(MTB, KC);
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_sketch<SPLIT, VEC, MTB, KC>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    dim3 grid((unsigned)((n + kSkCols - 1) / kSkCols), (unsigned)((mt_total + MTB - 1) / MTB));
+    MIID_LAUNCH(pr, (k_sketch<SPLIT, VEC, MTB, KC>), grid, dim3(kSkThreads), lds, s, A, lda, m, n, Wt, mpad,
+                mt_total, S, ldw, Y, ldy, l);
+    return hipGetLastError();
+}
+
+// Tile rows per workgroup: every 16-row tile of Y in one workgroup when
+// l <= 528 (A is then read once), 33 tiles per workgroup row beyond.
+template <bool SPLIT, bool VEC>
+static hipError_t launch_sketch_mt(int pr, hipStream_t s, int64_t n, int mt_total, const float* A, int64_t lda,
+                                   int64_t m, const uint16_t* Wt, int64_t mpad, float* S, int64_t ldw, float* Y,
+                                   int64_t ldy, int l) {
+    if (mt_total <= 9)
+        return launch_sketch<SPLIT, VEC, 9, 128>(pr, s, n, mt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l);
+    if (mt_total <= 17)
+        return launch_sketch<SPLIT, VEC, 17, 128>(pr, s, n, mt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l);
+    return launch_sketch<SPLIT, VEC, 33, 64>(pr, s, n, mt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l);
 }
 
 template <typename T>
@@ -212,24 +292,16 @@ int rid_sketch_cpqr(const float* A, int64_t m, int64_t n, int64_t lda, const uin
         hipLaunchKernelGGL(k_omega_t, grid, dim3(256), 0, s, Omega, l, m, ldo, Wt, R.lpad, R.mpad);
     }
     {
-        dim3 grid((unsigned)((n + kSkCols - 1) / kSkCols), (unsigned)((R.mt_total + kSkMTB - 1) / kSkMTB));
         const bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
         const int pr = prof_take(MIID_K_SKETCH, 0, m, n);
-        if (mode == 1) {
-            if (vec)
-                MIID_LAUNCH(pr, (k_sketch<true, true>), grid, dim3(kSkThreads), 0, s, A, lda, m, n, Wt, R.mpad,
-                                   R.mt_total, S, ldw, Y, ldy, l);
-            else
-                MIID_LAUNCH(pr, (k_sketch<true, false>), grid, dim3(kSkThreads), 0, s, A, lda, m, n, Wt, R.mpad,
-                                   R.mt_total, S, ldw, Y, ldy, l);
-        } else {
-            if (vec)
-                MIID_LAUNCH(pr, (k_sketch<false, true>), grid, dim3(kSkThreads), 0, s, A, lda, m, n, Wt, R.mpad,
-                                   R.mt_total, S, ldw, Y, ldy, l);
-            else
-                MIID_LAUNCH(pr, (k_sketch<false, false>), grid, dim3(kSkThreads), 0, s, A, lda, m, n, Wt, R.mpad,
-                                   R.mt_total, S, ldw, Y, ldy, l);
-        }
+        hipError_t e;
+        if (mode == 1)
+            e = vec ? launch_sketch_mt<true, true>(pr, s, n, R.mt_total, A, lda, m, Wt, R.mpad, S, ldw, Y, ldy, l)
+                    : launch_sketch_mt<true, false>(pr, s, n, R.mt_total, A, lda, m, Wt, R.mpad, S, ldw, Y, ldy, l);
+        else
+            e = vec ? launch_sketch_mt<false, true>(pr, s, n, R.mt_total, A, lda, m, Wt, R.mpad, S, ldw, Y, ldy, l)
+                    : launch_sketch_mt<false, false>(pr, s, n, R.mt_total, A, lda, m, Wt, R.mpad, S, ldw, Y, ldy, l);
+        MIID_HIP(e);
     }
     MIID_HIP(hipGetLastError());
     return run_id<float>(R.id, A, lda, J, Z, ldz, R11, ldr, C, ldc, info, w, s, true, A, lda, m);
