@@ -65,7 +65,8 @@ typedef enum { MIID_F32 = 0, MIID_F64 = 1 } miid_dtype;
  *        panels of at most 32)
  *  TILE  id_batched: streamed column tile of a block that does not fit in
  *        LDS, in units of 8 KiB (1..15, capped at half of the LDS the
- *        kernel uses for blocks; default 72 KiB)                          */
+ *        kernel uses for blocks; default 24 KiB); the LDS left beside the
+ *        two tiles keeps the block's first columns resident              */
 #define MIID_HINT_CPW_SHIFT 8
 #define MIID_HINT_NP_SHIFT 12
 #define MIID_HINT_PATH_SHIFT 16

@@ -112,8 +112,8 @@ def tune_rid(A: torch.Tensor, omega: torch.Tensor, k: int, mode: int = 1, reps: 
 
 
 def batched_candidates():
-    """Streamed column tile sizes of the batched kernel (16 to 72 KiB)."""
-    return [(f"tile={8 * t}KiB", 0, H(_abi.MIID_HINT_TILE_SHIFT, t)) for t in (2, 4, 6, 8, 9)]
+    """Streamed column tile sizes of the batched kernel (8 to 72 KiB)."""
+    return [(f"tile={8 * t}KiB", 0, H(_abi.MIID_HINT_TILE_SHIFT, t)) for t in (1, 2, 3, 4, 6, 9)]
 
 
 def tune_batched(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, reps: int = 3,

@@ -34,7 +34,7 @@ constexpr int kBWaves = kBThreads / kWave;
 // dynamic LDS (V, then the block or its column tiles): what the 160 KB of a
 // CU leave beside the kernel's static arrays
 constexpr int bdyn_bytes(int) { return 148 * 1024; }
-constexpr int kBTileBytes = 72 * 1024;  // default streamed column tile (at most half the dynamic LDS)
+constexpr int kBTileBytes = 24 * 1024;  // default streamed column tile (the rest of LDS keeps columns resident)
 constexpr int kBMaxM = 256;
 constexpr int kBMaxN = 1024;
 constexpr int kBMaxK = 64;
@@ -160,13 +160,18 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
         }
         const T* Ab = A + a_off[b];
         T* Zb = Z + z_off[b];
+        // LDS: the first cres columns stay resident for the whole block; the
+        // other ns columns (if any) stream through two tiles of TC columns
         const bool resident = m * n <= kDyn;
-        const int TC = resident ? n : max(1, min(n, min(kDyn / 2, tile_bytes / (int)sizeof(T)) / m));
-        const int nt = (n + TC - 1) / TC;
-        T* buf0 = lds;
-        T* buf1 = lds + (resident ? 0 : TC * m);
-        if (resident) {  // the whole block straight into LDS
-            const int cntw = m * n * (int)(sizeof(T) / 4);
+        const int TC = resident ? 1 : max(1, min(n, min(kDyn / 2, tile_bytes / (int)sizeof(T)) / m));
+        const int cres = resident ? n : min(n, max(0, (kDyn - 2 * TC * m) / m));
+        const int ns = n - cres;
+        const int nt = (ns + TC - 1) / TC;
+        T* res = lds;
+        T* buf0 = lds + cres * m;
+        T* buf1 = buf0 + TC * m;
+        if (cres > 0) {  // the resident columns straight into LDS
+            const int cntw = cres * m * (int)(sizeof(T) / 4);
             const uint32_t* s32 = reinterpret_cast<const uint32_t*>(Ab);
             lds_u32* d32 = (lds_u32*)smem_raw;
             for (int e0 = 0; e0 < cntw; e0 += kBThreads) {
@@ -176,12 +181,12 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
             __syncthreads();
         }
 
-        // one pass over W: fn(l, column in LDS) for every column; a
-        // streamed block's tiles come from src (A on the first pass, the
+        // one pass over W: fn(l, column in LDS) for every column; the
+        // streamed columns' tiles come from src (A on the first pass, the
         // scratch afterwards) and go back to the scratch when write is set
         auto pass = [&](const T* src, bool write, auto&& fn) {
-            if (resident) {
-                for (int l = cgroup; l < n; l += kGroups) fn(l, buf0 + l * m);
+            for (int l = cgroup; l < cres; l += kGroups) fn(l, res + l * m);
+            if (ns == 0) {
                 lds_barrier();
                 return;
             }
@@ -189,9 +194,10 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
             // global memory into LDS (global_load_lds: no registers, the
             // next tile's copy in flight while the current one is updated)
             auto issue = [&](int t) {
-                const int cntw = min(TC, n - t * TC) * m * (int)(sizeof(T) / 4);
-                const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src + (int64_t)t * TC * m);
-                lds_u32* d32 = (lds_u32*)smem_raw + ((t & 1) ? TC * m * (int)(sizeof(T) / 4) : 0);
+                const int c0 = cres + t * TC;
+                const int cntw = min(TC, n - c0) * m * (int)(sizeof(T) / 4);
+                const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src + (int64_t)c0 * m);
+                lds_u32* d32 = (lds_u32*)smem_raw + (cres + ((t & 1) ? TC : 0)) * m * (int)(sizeof(T) / 4);
                 for (int e0 = 0; e0 < cntw; e0 += kBThreads) {
                     const int e = e0 + tid;
                     if (e < cntw) __builtin_amdgcn_global_load_lds((const void*)(s32 + e), d32 + (e - lane), 4, 0, 0);
@@ -201,7 +207,7 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
             __syncthreads();
             for (int t = 0; t < nt; ++t) {
                 if (t + 1 < nt) issue(t + 1);
-                const int c0 = t * TC, c1 = min(n, c0 + TC);
+                const int c0 = cres + t * TC, c1 = min(n, c0 + TC);
                 T* cur = (t & 1) ? buf1 : buf0;
                 for (int l = c0 + cgroup; l < c1; l += kGroups) fn(l, cur + (l - c0) * m);
                 lds_barrier();
@@ -217,7 +223,7 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
         // exact column norms (FP64) and ||A_b||_F; a streamed block is copied
         // to the scratch on the way
         double fro = 0.0;
-        pass(Ab, !resident, [&](int l, T* col) {
+        pass(Ab, ns > 0, [&](int l, T* col) {
             double ss = 0.0;
 #pragma unroll
             for (int t = 0; t < kRT; ++t) {
@@ -238,7 +244,6 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
         const double stop_abs = eps * a_norm;
         // W (the scratch writes of the copy) complete before it is read
         __syncthreads();
-        const T* W = resident ? buf0 : Wb;
 
         int k = 0;
         uint32_t status = 0;
@@ -270,7 +275,8 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
             const int p = best.i;
             const int j = k;
             // Householder reflector of W[j:, p] (one thread per row)
-            const double x = (tid < m && tid >= j) ? (double)W[tid + (int64_t)p * m] : 0.0;
+            const T* colp = p < cres ? res + p * m : Wb + (int64_t)p * m;
+            const double x = (tid < m && tid >= j) ? (double)colp[tid] : 0.0;
             const double s0 = block_sum(tid > j && tid < m ? x * x : 0.0, w_sum);
             if (tid == j) s_v[kBMaxM - 1] = x;  // x0 (row j) parked in the last slot
             lds_barrier();
@@ -293,7 +299,7 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
             lds_barrier();
             // apply H = I - tau v v^T to the alive columns, row j of R, exact
             // new norms of rows j+1..m-1
-            pass(W, !resident, [&](int l, T* col) {
+            pass(Wb, ns > 0, [&](int l, T* col) {
                 if (!(snu[l] >= 0.0)) return;  // dead column (uniform over the group)
                 double xr[kRT];
                 double d = 0.0;

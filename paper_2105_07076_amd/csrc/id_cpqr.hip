@@ -560,6 +560,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     __shared__ double w_best[kFusedWaves], w_sum[kFusedWaves];
     __shared__ int32_t w_idx[kFusedWaves], w_nf[kFusedWaves], w_nrec[kFusedWaves];
     __shared__ double s_x0;
+    __shared__ double s_fg[kFusedWaves * 4][kFusedMaxNb];  // F[col, 0:i] of a group's recomputed column
 
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
@@ -570,7 +571,13 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     const int64_t j0 = (int64_t)j & ~(int64_t)(VEC - 1);
     const int64_t ngroups = (ldw - j0) / VEC;  // VEC-row groups from j0
 
+    // the previous step's partials first: the loads below are independent of
+    // them and of each other, so one memory round trip covers them all
+    // (npart <= kFusedThreads partials: one per thread)
+    const ColPartial cp0 = tid < npart ? part_in[tid] : ColPartial{-1.0, INT32_MAX, 0, 0.0, 0.0};
+
     // this wave's columns and their per-column data, independent of the pivot
+    // (loaded whatever the column's state; used only for alive columns)
     int64_t col[NP];
     bool in[NP];
     double nuc[NP], nrf[NP], sjc[NP], fq[NP][kFusedMaxNb / 16];
@@ -579,13 +586,12 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
         col[ps] = (int64_t)wg * 32 * NP + (int64_t)wave * 4 * NP + ps * 4 + grp;
         in[ps] = col[ps] < n;
         nuc[ps] = in[ps] ? nu[col[ps]] : -1.0;
-        const bool live = in[ps] && nuc[ps] >= 0.0;
-        nrf[ps] = live ? nuref[col[ps]] : 1.0;
-        sjc[ps] = live ? (double)S[col[ps] * ldw + j] : 0.0;
+        nrf[ps] = in[ps] ? nuref[col[ps]] : 1.0;
+        sjc[ps] = in[ps] ? (double)S[col[ps] * ldw + j] : 0.0;
 #pragma unroll
         for (int s = 0; s < kFusedMaxNb / 16; ++s) {
             const int q = l16 + 16 * s;
-            fq[ps][s] = (live && q < i) ? (double)F[col[ps] * nb + q] : 0.0;
+            fq[ps][s] = (in[ps] && q < i) ? (double)F[col[ps] * nb + q] : 0.0;
         }
     }
     // the first two column chunks and V[:, 0:i] (GL 16-byte groups per
@@ -593,8 +599,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     // pivot is found
     ColChunk<T, GL> buf[2];
 #pragma unroll
-    for (int ps = 0; ps < (NP < 2 ? NP : 2); ++ps)
-        buf[ps].load((in[ps] && nuc[ps] >= 0.0) ? S + col[ps] * ldw + j0 : nullptr, ngroups, l16);
+    for (int ps = 0; ps < (NP < 2 ? NP : 2); ++ps) buf[ps].load(in[ps] ? S + col[ps] * ldw + j0 : nullptr, ngroups, l16);
     const int64_t vtot = (ldw / VEC) * i;
     VT vst[GL];
 #pragma unroll
@@ -607,7 +612,10 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     ArgMax best{-1.0, INT32_MAX};
     double sumsq = 0.0;
     int nf = 0;
-    for (int q = tid; q < npart; q += kFusedThreads) {
+    if (argmax_better(cp0.best, cp0.idx, best.v, best.i)) best = {cp0.best, cp0.idx};
+    sumsq += cp0.sumsq;
+    nf |= cp0.nonfinite;
+    for (int q = tid + kFusedThreads; q < npart; q += kFusedThreads) {
         const ColPartial cp = part_in[q];
         if (argmax_better(cp.best, cp.idx, best.v, best.i)) best = {cp.best, cp.idx};
         sumsq += cp.sumsq;
@@ -719,10 +727,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     for (int ps = 0; ps < NP; ++ps) {
         const bool alive = in[ps] && col[ps] != p && nuc[ps] >= 0.0;
         acc[ps] = alive ? buf[ps & 1].dot(su, ngroups, l16) : 0.0;
-        if (ps + 2 < NP)
-            buf[ps & 1].load((in[ps + 2] && nuc[ps + 2] >= 0.0 && col[ps + 2] != p) ? S + col[ps + 2] * ldw + j0
-                                                                                   : nullptr,
-                             ngroups, l16);
+        if (ps + 2 < NP) buf[ps & 1].load(in[ps + 2] ? S + col[ps + 2] * ldw + j0 : nullptr, ngroups, l16);
     }
     {
         const int q = 4 * wave + grp;
@@ -783,11 +788,18 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
                 nnew = nuc[ps] * sqrt(t);
         }
         if (rec) {
-            // exact norm of the lazily updated column, rows j+1..m-1
+            // exact norm of the lazily updated column, rows j+1..m-1; the
+            // column's F row goes through the group's LDS slot
+            double* fg = s_fg[wave * 4 + grp];
+#pragma unroll
+            for (int s = 0; s < kFusedMaxNb / 16; ++s) {
+                const int q = l16 + 16 * s;
+                if (q < i) fg[q] = fq[ps][s];
+            }
             double s2 = 0.0;
             for (int64_t r = j + 1 + l16; r < m; r += 16) {
                 double x = (double)S[col[ps] * ldw + r] - scale * s_u[r] * f;
-                for (int q = 0; q < i; ++q) x -= (double)sV[r + (int64_t)q * ldw] * (double)F[col[ps] * nb + q];
+                for (int q = 0; q < i; ++q) x -= (double)sV[r + (int64_t)q * ldw] * fg[q];
                 s2 += x * x;
             }
             nnew = sqrt(group16_sum(s2));

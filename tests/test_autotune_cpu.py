@@ -28,7 +28,7 @@ def test_id_candidates():
     # FP64 with 320 rows (ldw 320: 16-byte groups per lane 10 > 9): blocked only
     c3 = autotune.id_candidates(300, 1000, torch.float64)
     assert all(lbl.startswith("blocked") for lbl, _, _ in c3)
-    assert len(autotune.batched_candidates()) == 5
+    assert len(autotune.batched_candidates()) == 6
 
 
 def test_table_roundtrip(tmp_path):
