@@ -10,15 +10,17 @@
 // first), so uneven sizes balance across the chip.  Each Householder step
 // applies the reflector to every remaining column and recomputes that
 // column's residual norm exactly (FP64 accumulation) in the same pass -- at
-// eps = 1e-6 in FP32 downdated norms would have lost all their digits.  The
-// working copy W of the block stays in LDS when it fits; otherwise it lives
-// in a per-workgroup scratch and every pass streams it through two LDS column
-// tiles (the next tile's loads in flight while the current one is updated,
-// the updated one written back behind it).  A column is handled by a 16-lane
-// group (lane l16 takes rows l16 + 16 t; DPP row sums).  R stays in W's
-// first k rows and is copied row by row into Z's storage (no column swaps);
-// the k x k triangle is staged in LDS in FP64 for the solve, which then
-// overwrites Z in place.
+// eps = 1e-6 in FP32 downdated norms would have lost all their digits.  A
+// column is handled by a 16-lane group (lane l16 takes rows l16 + 16 t; DPP
+// row sums), with the rows per lane fitted to m.  The working copy W of the
+// block is spread over the chip: its first columns in registers, the next in
+// LDS, and whatever does not fit in a per-workgroup scratch that every pass
+// streams through two LDS column tiles (the next tile's loads in flight while
+// the current one is updated, the updated one written back behind it).  The
+// pivot column's group forms the reflector, so a step costs two workgroup
+// barriers.  R stays in W's first k rows and is copied row by row into Z's
+// storage (no column swaps); the k x k triangle is staged in LDS in FP64 for
+// the solve, which then overwrites Z in place.
 #include <algorithm>
 #include <cmath>
 #include <climits>
@@ -86,39 +88,340 @@ __global__ void k_zero_queue(int32_t* __restrict__ queue) {
 }
 
 // Block-wide (value, index) argmax and sum: wave results through LDS, read
-// back in wave order (identical in every thread).
-__device__ __forceinline__ void block_argmax_sum(ArgMax& best, double& sum, ArgMax* w_best, double* w_sum) {
+// back in wave order (identical in every thread).  The LDS slots alternate
+// between two sets by call parity, so one barrier suffices: a wave can only
+// reach the call after next once every wave has left this one.
+__device__ __forceinline__ void block_argmax_sum(ArgMax& best, double& sum, ArgMax* w_best, double* w_sum, int par) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     best = wave_argmax_dpp(best);
     sum = wave_sum_dpp(sum);
+    ArgMax* wb = w_best + par * kBWaves;
+    double* ws = w_sum + par * kBWaves;
     if (lane == 0) {
-        w_best[wave] = best;
-        w_sum[wave] = sum;
+        wb[wave] = best;
+        ws[wave] = sum;
     }
     lds_barrier();
-    best = w_best[0];
-    sum = w_sum[0];
+    best = wb[0];
+    sum = ws[0];
     for (int w = 1; w < kBWaves; ++w) {
-        if (argmax_better(w_best[w].v, w_best[w].i, best.v, best.i)) best = w_best[w];
-        sum += w_sum[w];
+        if (argmax_better(wb[w].v, wb[w].i, best.v, best.i)) best = wb[w];
+        sum += ws[w];
     }
-    lds_barrier();
 }
 
-__device__ __forceinline__ double block_sum(double v, double* w_sum) {
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    v = wave_sum_dpp(v);
-    if (lane == 0) w_sum[wave] = v;
-    lds_barrier();
-    double t = 0.0;
-    for (int w = 0; w < kBWaves; ++w) t += w_sum[w];
-    lds_barrier();
-    return t;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+// Columns of a block kept in registers, per 16-lane group: 32 to 48 VGPRs
+// (what the pass leaves free of the 256 a lane has at two waves per SIMD).
+template <typename T, int RT>
+constexpr int breg_cols() {
+    return (RT == 2 ? 32 : (RT == 4 ? 40 : 48)) / (RT * (int)(sizeof(T) / 4));
+}
+
+// The kernel's static LDS, handed to the per-block factorisation.
+struct BShared {
+    double* snu;     // residual norm of every column (-1: chosen)
+    double* s_v;     // the reflector (v_j = 1, zero above j and below m)
+    ArgMax* w_best;  // 2 x kBWaves
+    double* w_sum;   // 2 x kBWaves
+    int32_t* s_sel;  // chosen columns in order
+    double* s_scal;  // tau, 1 if the reflector exists
+};
+
+struct BResult {
+    int k;
+    uint32_t status;
+    double a_norm, resid;
+};
+
+// Pivoted Householder QR of one block, stopped by the tolerance.  A column
+// belongs to the 16-lane group (column mod 32); lane l16 holds rows
+// l16 + 16 t, t < RT (RT = ceil(m / 16) rounded up to 2, 4, 8 or 16).  The
+// first 32 NR columns live in registers, the next cres in LDS, the rest in
+// the workgroup's scratch Wb, streamed through two LDS tiles of TC columns
+// per pass.  Columns in LDS and in the scratch are stored with the row count
+// padded to mp = a multiple of 16 (zeros below row m), so whole slices t are
+// either in the column or not and no per-row bounds are needed.  Each step:
+// argmax of the residual norms (one barrier), the reflector formed by the
+// pivot column's group, a barrier, then one pass that applies it to every
+// alive column, writes row j of R into Zb and recomputes the residual norms
+// exactly (FP64 accumulation).
+template <typename T, int RT>
+__device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __restrict__ Zb, T* __restrict__ Wb,
+                                                int m, int n, int kb, double eps, int tile_bytes,
+                                                unsigned char* smem_raw, BShared sh) {
+    constexpr int NR = breg_cols<T, RT>();
+    constexpr int kDyn = bdyn_bytes((int)sizeof(T)) / (int)sizeof(T);
+    constexpr int kGroups = kBWaves * 4;
+    const int tid = threadIdx.x;
+    const int lane = tid % kWave;
+    int l16 = lane & 15;
+    // opaque to the optimiser: what is derived from it is formed here, per
+    // block, instead of being hoisted out of the persistent loop for every
+    // RT instance and held in registers throughout
+    asm volatile("" : "+v"(l16));
+    const int cgroup = tid / 16;  // 16-lane column group, 0..31
+    T* lds = reinterpret_cast<T*>(smem_raw);
+
+    const int mp = (m + 15) & ~15;
+    const int ntv = mp / 16;  // slices t inside a padded column
+    const int nreg = min(n, kGroups * NR);
+    const int nrest = n - nreg;
+    const bool resident = nrest * mp <= kDyn;
+    const int TC = resident ? 1 : max(1, min(nrest, min(kDyn / 2, tile_bytes / (int)sizeof(T)) / mp));
+    const int cres = resident ? nrest : min(nrest, max(0, (kDyn - 2 * TC * mp) / mp));
+    const int c_str = nreg + cres;  // first streamed column
+    const int ns = n - c_str;
+    const int nt = (ns + TC - 1) / TC;
+    T* buf0 = lds + cres * mp;
+    T* buf1 = buf0 + TC * mp;
+    // home of column l >= nreg: LDS or the scratch
+    auto home = [&](int l) { return l < c_str ? lds + (l - nreg) * mp : Wb + (int64_t)l * mp; };
+
+    T rc[NR][RT];   // register-resident columns cgroup + 32 c (zero below row m)
+    T sv[RT];  // v at this lane's rows (v is rounded to T, so exact)
+
+    // copy the streamed tile t of the scratch into its LDS buffer (no registers)
+    auto issue = [&](int t) {
+        const int c0 = c_str + t * TC;
+        const int cntw = min(TC, n - c0) * mp * (int)(sizeof(T) / 4);
+        const uint32_t* s32 = reinterpret_cast<const uint32_t*>(Wb + (int64_t)c0 * mp);
+        lds_u32* d32 = (lds_u32*)smem_raw + (cres + ((t & 1) ? TC : 0)) * mp * (int)(sizeof(T) / 4);
+        for (int e0 = 0; e0 < cntw; e0 += kBThreads) {
+            const int e = e0 + tid;
+            if (e < cntw) __builtin_amdgcn_global_load_lds((const void*)(s32 + e), d32 + (e - lane), 4, 0, 0);
+        }
+    };
+
+    // ---- first pass: every column from A_b to its home, exact norms --------
+    ArgMax best{-1.0, INT32_MAX};
+    double acc = 0.0;  // this lane's share of the sum over columns
+    auto norm_of = [&](int l, double ss) {
+        ss = row16_sum(ss);
+        if (l16 == 0) {
+            const double nu = sqrt(ss);
+            sh.snu[l] = nu;
+            acc += ss;
+            if (argmax_better(nu, l, best.v, best.i)) best = {nu, l};
+        }
+    };
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        const int l = cgroup + kGroups * c;
+        const bool have = l < nreg;
+        double ss = 0.0;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            const int r = l16 + 16 * t;
+            const T x = (have && r < m) ? Ab[(int64_t)l * m + r] : T(0);
+            rc[c][t] = x;
+            ss += (double)x * (double)x;
+        }
+        if (have) norm_of(l, ss);
+    }
+    for (int l = nreg + cgroup; l < n; l += kGroups) {
+        T* col = home(l);
+        double ss = 0.0;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            if (t < ntv) {
+                const int r = l16 + 16 * t;
+                const T x = r < m ? Ab[(int64_t)l * m + r] : T(0);
+                col[r] = x;
+                ss += (double)x * (double)x;
+            }
+        }
+        norm_of(l, ss);
+    }
+    if (ns > 0) __syncthreads();  // the scratch holds the streamed columns
+
+    int k = 0, par = 0;
+    uint32_t status = 0;
+    double a_norm = 0.0, resid = 0.0, stop_abs = 0.0;
+    for (;;) {
+        double ss = acc;
+        block_argmax_sum(best, ss, sh.w_best, sh.w_sum, par);
+        par ^= 1;
+        if (k == 0) {
+            a_norm = sqrt(ss);
+            stop_abs = eps * a_norm;
+            resid = a_norm;
+            if (!(a_norm <= 1.0e300)) {
+                status |= MIID_NONFINITE;
+                break;
+            }
+        } else {
+            resid = sqrt(ss);
+        }
+        if (resid <= stop_abs) break;
+        if (k >= kb) {
+            status |= MIID_KMAX_HIT;
+            break;
+        }
+        if (!(best.v > 0.0)) {
+            status |= MIID_RANK_DEFICIENT;
+            break;
+        }
+        const int p = best.i;
+        const int j = k;
+        const int jt = j >> 4, jl = j & 15;
+        // ---- the reflector, by the pivot column's group --------------------
+        if (cgroup == p % kGroups) {
+            double x[RT];
+            if (p < nreg) {
+                const int cp = p / kGroups;
+#pragma unroll
+                for (int t = 0; t < RT; ++t) {
+                    T v = rc[0][t];
+#pragma unroll
+                    for (int c = 1; c < NR; ++c) v = c == cp ? rc[c][t] : v;
+                    x[t] = (double)v;
+                }
+            } else {
+                // a streamed column was last written to the scratch by other
+                // lanes: read it at device scope, past this CU's L1
+                const T* col = home(p);
+                const bool dev = p >= c_str;
+#pragma unroll
+                for (int t = 0; t < RT; ++t) {
+                    const int r = l16 + 16 * t;
+                    T v = T(0);
+                    if (t < ntv) v = dev ? __hip_atomic_load(col + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : col[r];
+                    x[t] = (double)v;
+                }
+            }
+            // rows below j only (rows above hold R); zero below row m
+            double x0 = 0.0, s0 = 0.0;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                if (t == jt) {
+                    x0 = l16 == jl ? x[t] : 0.0;
+                    if (l16 > jl) s0 += x[t] * x[t];
+                } else if (t > jt) {
+                    s0 += x[t] * x[t];
+                }
+            }
+            x0 = row16_sum(x0);
+            s0 = row16_sum(s0);
+            const double alpha = sqrt(x0 * x0 + s0);
+            const double beta = x0 >= 0.0 ? -alpha : alpha;
+            const double tau = (beta - x0) / beta;
+            const double scale = 1.0 / (x0 - beta);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                double v = (double)(T)(x[t] * scale);
+                if (t < jt) v = 0.0;
+                if (t == jt) v = l16 < jl ? 0.0 : (l16 == jl ? 1.0 : v);
+                sh.s_v[l16 + 16 * t] = v;
+            }
+            if (l16 == 0) {
+                sh.s_scal[0] = tau;
+                sh.s_scal[1] = alpha > 0.0 ? 1.0 : 0.0;
+                sh.s_sel[j] = p;
+                sh.snu[p] = -1.0;
+                Zb[j + (int64_t)p * kb] = (T)beta;
+            }
+        }
+        if (ns > 0) issue(0);  // the first streamed tile of the pass
+        lds_barrier();
+        if (!(sh.s_scal[1] > 0.0)) {
+            status |= MIID_RANK_DEFICIENT;
+            if (ns > 0) __syncthreads();  // no tile copy left in flight
+            break;
+        }
+        const double tau = sh.s_scal[0];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) sv[t] = (T)sh.s_v[l16 + 16 * t];
+
+        // ---- the pass: H = I - tau v v^T on every alive column -------------
+        best = {-1.0, INT32_MAX};
+        acc = 0.0;
+        auto track = [&](int l, double s2) {
+            s2 = row16_sum(s2);
+            if (l16 == 0) {
+                const double nu = sqrt(s2);
+                sh.snu[l] = nu;
+                acc += nu * nu;
+                if (argmax_better(nu, l, best.v, best.i)) best = {nu, l};
+            }
+        };
+        // s2 over rows > j and the store of row j, from slice t of y
+        auto tail = [&](int t, T y, double& s2, int l, bool alive) {
+            if (t > jt) s2 += (double)y * (double)y;
+            if (t == jt) {
+                if (l16 > jl) s2 += (double)y * (double)y;
+                if (l16 == jl && alive) Zb[j + (int64_t)l * kb] = y;
+            }
+        };
+        // register columns, branch-free (a chosen or missing column gets
+        // tau = 0, which leaves it unchanged)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            const int l = cgroup + kGroups * c;
+            const bool alive = l < nreg && sh.snu[l < nreg ? l : 0] >= 0.0;
+            double d = 0.0;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) d += (double)rc[c][t] * (double)sv[t];
+            // the FP64 copies of the column are formed again below rather
+            // than held across the reduction (register pressure)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) asm volatile("" : "+v"(rc[c][t]));
+            d = row16_sum(d);
+            const double tc = alive ? tau * d : 0.0;
+            double s2 = 0.0;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const T y = (T)((double)rc[c][t] - tc * sv[t]);
+                rc[c][t] = y;
+                tail(t, y, s2, l, alive);
+            }
+            if (alive) track(l, s2);
+        }
+        auto col_step = [&](int l, T* col) {
+            if (!(sh.snu[l] >= 0.0)) return;  // chosen column (uniform over the group)
+            T x[RT];
+            double d = 0.0;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                x[t] = t < ntv ? col[l16 + 16 * t] : T(0);
+                d += (double)x[t] * (double)sv[t];
+            }
+#pragma unroll
+            for (int t = 0; t < RT; ++t) asm volatile("" : "+v"(x[t]));
+            d = tau * row16_sum(d);
+            double s2 = 0.0;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const T y = (T)((double)x[t] - d * (double)sv[t]);
+                if (t < ntv) col[l16 + 16 * t] = y;
+                tail(t, y, s2, l, true);
+            }
+            track(l, s2);
+        };
+        for (int l = nreg + cgroup; l < c_str; l += kGroups) col_step(l, lds + (l - nreg) * mp);
+        if (ns > 0) {
+            // streamed columns: tile t + 1 in flight while tile t is updated,
+            // tile t written back to the scratch behind it
+            __syncthreads();  // tile 0 has landed
+            for (int t = 0; t < nt; ++t) {
+                if (t + 1 < nt) issue(t + 1);
+                const int c0 = c_str + t * TC, c1 = min(n, c0 + TC);
+                T* cur = (t & 1) ? buf1 : buf0;
+                for (int l = c0 + cgroup; l < c1; l += kGroups) col_step(l, cur + (l - c0) * mp);
+                lds_barrier();
+                const int cnt = (c1 - c0) * mp;
+                T* d0 = Wb + (int64_t)c0 * mp;
+                for (int e = tid; e < cnt; e += kBThreads) d0[e] = cur[e];
+                __syncthreads();  // the next tile has landed; this one is written back
+            }
+        }
+        ++k;
+    }
+    return BResult{k, status, a_norm, resid};
 }
 
 // Persistent kernel: one block at a time per workgroup (8 waves, one per CU).
-typedef __attribute__((address_space(3))) uint32_t lds_u32;
-
 template <typename T>
 __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, const int64_t* __restrict__ a_off,
                                                        const int32_t* __restrict__ mv, const int32_t* __restrict__ nv,
@@ -128,22 +431,17 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
                                                        miid_info* __restrict__ info,
                                                        const int32_t* __restrict__ order, int32_t* __restrict__ queue,
                                                        T* __restrict__ Wscr, int tile_bytes) {
-    constexpr int kDyn = bdyn_bytes((int)sizeof(T)) / (int)sizeof(T);
-    constexpr int kRT = kBMaxM / 16;              // rows per lane of a column group
-    constexpr int kGroups = kBWaves * 4;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* lds = reinterpret_cast<T*>(smem_raw);
     __shared__ double snu[kBMaxN];
-    __shared__ double s_v[kBMaxM];  // the reflector (v_j = 1, zero above j)
-    __shared__ ArgMax w_best[kBWaves];
-    __shared__ double w_sum[kBWaves];
+    __shared__ double s_v[kBMaxM];
+    __shared__ ArgMax w_best[2 * kBWaves];
+    __shared__ double w_sum[2 * kBWaves];
     __shared__ int32_t s_sel[kBMaxK];
+    __shared__ double s_scal[2];
     __shared__ int32_t s_blk;
     const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
-    const int l16 = lane & 15, grp = lane >> 4;
-    const int cgroup = wave * 4 + grp;  // 16-lane column group
-    T* Wb = Wscr + (int64_t)blockIdx.x * kBMaxM * kBMaxN;  // W when it does not fit in LDS
+    T* Wb = Wscr + (int64_t)blockIdx.x * kBMaxM * kBMaxN;  // W when it does not fit on chip
+    const BShared sh{snu, s_v, w_best, w_sum, s_sel, s_scal};
 
     for (;;) {
         if (tid == 0) s_blk = atomicAdd(queue, 1);
@@ -160,190 +458,42 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
         }
         const T* Ab = A + a_off[b];
         T* Zb = Z + z_off[b];
-        // LDS: the first cres columns stay resident for the whole block; the
-        // other ns columns (if any) stream through two tiles of TC columns
-        const bool resident = m * n <= kDyn;
-        const int TC = resident ? 1 : max(1, min(n, min(kDyn / 2, tile_bytes / (int)sizeof(T)) / m));
-        const int cres = resident ? n : min(n, max(0, (kDyn - 2 * TC * m) / m));
-        const int ns = n - cres;
-        const int nt = (ns + TC - 1) / TC;
-        T* res = lds;
-        T* buf0 = lds + cres * m;
-        T* buf1 = buf0 + TC * m;
-        if (cres > 0) {  // the resident columns straight into LDS
-            const int cntw = cres * m * (int)(sizeof(T) / 4);
-            const uint32_t* s32 = reinterpret_cast<const uint32_t*>(Ab);
-            lds_u32* d32 = (lds_u32*)smem_raw;
-            for (int e0 = 0; e0 < cntw; e0 += kBThreads) {
-                const int e = e0 + tid;
-                if (e < cntw) __builtin_amdgcn_global_load_lds((const void*)(s32 + e), d32 + (e - lane), 4, 0, 0);
-            }
-            __syncthreads();
-        }
+        BResult res;
+        if (m <= 32)
+            res = factor_block<T, 2>(Ab, Zb, Wb, m, n, kb, eps, tile_bytes, smem_raw, sh);
+        else if (m <= 64)
+            res = factor_block<T, 4>(Ab, Zb, Wb, m, n, kb, eps, tile_bytes, smem_raw, sh);
+        else if (m <= 128)
+            res = factor_block<T, 8>(Ab, Zb, Wb, m, n, kb, eps, tile_bytes, smem_raw, sh);
+        else
+            res = factor_block<T, 16>(Ab, Zb, Wb, m, n, kb, eps, tile_bytes, smem_raw, sh);
+        const int k = res.k;
 
-        // one pass over W: fn(l, column in LDS) for every column; the
-        // streamed columns' tiles come from src (A on the first pass, the
-        // scratch afterwards) and go back to the scratch when write is set
-        auto pass = [&](const T* src, bool write, auto&& fn) {
-            for (int l = cgroup; l < cres; l += kGroups) fn(l, res + l * m);
-            if (ns == 0) {
-                lds_barrier();
-                return;
-            }
-            // a tile is a contiguous range of src; it goes straight from
-            // global memory into LDS (global_load_lds: no registers, the
-            // next tile's copy in flight while the current one is updated)
-            auto issue = [&](int t) {
-                const int c0 = cres + t * TC;
-                const int cntw = min(TC, n - c0) * m * (int)(sizeof(T) / 4);
-                const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src + (int64_t)c0 * m);
-                lds_u32* d32 = (lds_u32*)smem_raw + (cres + ((t & 1) ? TC : 0)) * m * (int)(sizeof(T) / 4);
-                for (int e0 = 0; e0 < cntw; e0 += kBThreads) {
-                    const int e = e0 + tid;
-                    if (e < cntw) __builtin_amdgcn_global_load_lds((const void*)(s32 + e), d32 + (e - lane), 4, 0, 0);
-                }
-            };
-            issue(0);
-            __syncthreads();
-            for (int t = 0; t < nt; ++t) {
-                if (t + 1 < nt) issue(t + 1);
-                const int c0 = cres + t * TC, c1 = min(n, c0 + TC);
-                T* cur = (t & 1) ? buf1 : buf0;
-                for (int l = c0 + cgroup; l < c1; l += kGroups) fn(l, cur + (l - c0) * m);
-                lds_barrier();
-                if (write) {
-                    const int cnt = (c1 - c0) * m;
-                    T* d0 = Wb + (int64_t)c0 * m;
-                    for (int e = tid; e < cnt; e += kBThreads) d0[e] = cur[e];
-                }
-                __syncthreads();  // the next tile has landed; this one is written back
-            }
-        };
-
-        // exact column norms (FP64) and ||A_b||_F; a streamed block is copied
-        // to the scratch on the way
-        double fro = 0.0;
-        pass(Ab, ns > 0, [&](int l, T* col) {
-            double ss = 0.0;
-#pragma unroll
-            for (int t = 0; t < kRT; ++t) {
-                const int r = l16 + 16 * t;
-                if (r < m) {
-                    const double x = (double)col[r];
-                    ss += x * x;
-                }
-            }
-            ss = row16_sum(ss);
-            if (l16 == 0) {
-                snu[l] = sqrt(ss);
-                fro += ss;
-            }
-        });
-        const double a2 = block_sum(fro, w_sum);
-        const double a_norm = sqrt(a2);
-        const double stop_abs = eps * a_norm;
-        // W (the scratch writes of the copy) complete before it is read
+        // triangular solve: Z[:, l] = R11^{-1} R[:, l] in FP64, Z[:, J[i]] = e_i.
+        // The strict upper triangle of R11 goes to sR (zeros elsewhere, up to
+        // k rounded to 4), its diagonal to sD: the updates below then need no
+        // bounds tests.
+        constexpr int kSR = kBMaxK + 1;
+        double* sR = reinterpret_cast<double*>(smem_raw);  // reuses the dynamic LDS
+        double* sD = sR + kBMaxK * kSR;
+        const int kq4 = (k + 3) & ~3;
         __syncthreads();
-
-        int k = 0;
-        uint32_t status = 0;
-        double resid = a_norm;
-        const bool nonfinite = !(a_norm <= 1.0e300);
-        if (nonfinite) status |= MIID_NONFINITE;
-        while (!nonfinite) {
-            // pivot: largest residual norm among the alive columns
-            ArgMax best{-1.0, INT32_MAX};
-            double ss = 0.0;
-            for (int l = tid; l < n; l += kBThreads) {
-                const double v = snu[l];
-                if (v >= 0.0) {
-                    if (argmax_better(v, l, best.v, best.i)) best = {v, l};
-                    ss += v * v;
-                }
-            }
-            block_argmax_sum(best, ss, w_best, w_sum);
-            resid = sqrt(ss);
-            if (resid <= stop_abs) break;
-            if (k >= kb) {
-                status |= MIID_KMAX_HIT;
-                break;
-            }
-            if (!(best.v > 0.0)) {
-                status |= MIID_RANK_DEFICIENT;
-                break;
-            }
-            const int p = best.i;
-            const int j = k;
-            // Householder reflector of W[j:, p] (one thread per row)
-            const T* colp = p < cres ? res + p * m : Wb + (int64_t)p * m;
-            const double x = (tid < m && tid >= j) ? (double)colp[tid] : 0.0;
-            const double s0 = block_sum(tid > j && tid < m ? x * x : 0.0, w_sum);
-            if (tid == j) s_v[kBMaxM - 1] = x;  // x0 (row j) parked in the last slot
-            lds_barrier();
-            const double x0 = tid == j ? x : s_v[kBMaxM - 1];
-            lds_barrier();
-            const double alpha = sqrt(x0 * x0 + s0);
-            if (!(alpha > 0.0)) {
-                status |= MIID_RANK_DEFICIENT;
-                break;
-            }
-            const double beta = x0 >= 0.0 ? -alpha : alpha;
-            const double tau = (beta - x0) / beta;
-            const double scale = 1.0 / (x0 - beta);
-            if (tid < kBMaxM) s_v[tid] = (tid < j || tid >= m) ? 0.0 : (tid == j ? 1.0 : (double)(T)(x * scale));
-            if (tid == 0) {
-                s_sel[j] = p;
-                snu[p] = -1.0;
-                Zb[j + (int64_t)p * kb] = (T)beta;
-            }
-            lds_barrier();
-            // apply H = I - tau v v^T to the alive columns, row j of R, exact
-            // new norms of rows j+1..m-1
-            pass(Wb, ns > 0, [&](int l, T* col) {
-                if (!(snu[l] >= 0.0)) return;  // dead column (uniform over the group)
-                double xr[kRT];
-                double d = 0.0;
-#pragma unroll
-                for (int t = 0; t < kRT; ++t) {
-                    const int r = l16 + 16 * t;
-                    xr[t] = (r >= j && r < m) ? (double)col[r] : 0.0;
-                    d += xr[t] * s_v[r < kBMaxM ? r : 0];
-                }
-                d = tau * row16_sum(d);
-                double s2 = 0.0;
-#pragma unroll
-                for (int t = 0; t < kRT; ++t) {
-                    const int r = l16 + 16 * t;
-                    if (r >= j && r < m) {
-                        const T y = (T)(xr[t] - d * s_v[r]);
-                        col[r] = y;
-                        if (r == j) Zb[j + (int64_t)l * kb] = y;
-                        if (r > j) s2 += (double)y * (double)y;
-                    }
-                }
-                s2 = row16_sum(s2);
-                if (l16 == 0) snu[l] = sqrt(s2);
-            });
-            ++k;
-            __syncthreads();  // R rows and the scratch writes of step j are complete
+        for (int e = tid; e < kq4 * kq4; e += kBThreads) {
+            const int a = e % kq4, c = e / kq4;
+            sR[a * kSR + c] = (a < c && c < k) ? (double)Zb[a + (int64_t)s_sel[c] * kb] : 0.0;
         }
-
-        // triangular solve: Z[:, l] = R11^{-1} R[:, l] in FP64, Z[:, J[i]] = e_i
-        double* sR = reinterpret_cast<double*>(smem_raw);  // reuses the dynamic LDS: k x (kBMaxK + 1)
-        __syncthreads();
-        for (int e = tid; e < k * k; e += kBThreads) {
-            const int a = e % k, c = e / k;
-            sR[a * (kBMaxK + 1) + c] = a <= c ? (double)Zb[a + (int64_t)s_sel[c] * kb] : 0.0;
-        }
+        for (int t = tid; t < k; t += kBThreads) sD[t] = (double)Zb[t + (int64_t)s_sel[t] * kb];
         __syncthreads();
         int32_t* Jb = J + j_off[b];
         for (int i = tid; i < kb; i += kBThreads) Jb[i] = i < k ? s_sel[i] : -1;
         // four lanes per column (a quad), lane c of the quad holds z_q for
         // q = 4 i + c: back substitution with the solved z_t broadcast from
         // its owner inside the quad (DPP quad permutes)
+        int cq = tid % 4;
+        asm volatile("" : "+v"(cq));  // as in factor_block: no hoisting out of the block loop
         for (int l0 = tid / 4; l0 < n; l0 += kBThreads / 4) {
             const int l = l0;
-            const int c = tid % 4;
+            const int c = cq;
             T* zc = Zb + (int64_t)l * kb;
             const bool dead = snu[l] < 0.0;
             double z[kBMaxK / 4];
@@ -354,18 +504,18 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
             }
 #pragma unroll
             for (int i = kBMaxK / 4 - 1; i >= 0; --i) {
+                if (4 * i >= k) continue;  // uniform
 #pragma unroll
                 for (int r = 3; r >= 0; --r) {
                     const int t = 4 * i + r;
                     if (t >= k) continue;  // uniform
-                    double zt = z[i] / sR[t * (kBMaxK + 1) + t];
+                    double zt = z[i] / sD[t];
                     zt = r == 0 ? dpp_f64<0x00>(zt) : (r == 1 ? dpp_f64<0x55>(zt) : (r == 2 ? dpp_f64<0xAA>(zt) : dpp_f64<0xFF>(zt)));
                     if (c == r) z[i] = zt;
+                    // rows q < t take R[q, t] z_t; sR is zero on and below
+                    // the diagonal, so the other rows are left as they are
 #pragma unroll
-                    for (int i2 = 0; i2 <= i; ++i2) {
-                        const int qq = 4 * i2 + c;
-                        if (qq < t) z[i2] -= sR[qq * (kBMaxK + 1) + t] * zt;
-                    }
+                    for (int i2 = 0; i2 <= i; ++i2) z[i2] -= sR[(4 * i2 + c) * kSR + t] * zt;
                 }
             }
             int sidx = -1;
@@ -378,7 +528,7 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
                 if (qq < kb) zc[qq] = dead ? (T)(qq == sidx ? 1.0 : 0.0) : (T)(qq < k ? z[i] : 0.0);
             }
         }
-        if (tid == 0) info[b] = miid_info{k, status, a_norm, resid, 0, k};
+        if (tid == 0) info[b] = miid_info{k, res.status, res.a_norm, res.resid, 0, k};
         __syncthreads();
     }
 }
