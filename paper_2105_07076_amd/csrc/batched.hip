@@ -358,6 +358,7 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
         // tau = 0, which leaves it unchanged)
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
+            if (kGroups * c >= nreg) break;  // uniform: no group has column c
             const int l = cgroup + kGroups * c;
             const bool alive = l < nreg && sh.snu[l < nreg ? l : 0] >= 0.0;
             double d = 0.0;
@@ -378,13 +379,15 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
             }
             if (alive) track(l, s2);
         }
-        auto col_step = [&](int l, T* col) {
+        // a column read from src (LDS) and written to dst (the same LDS
+        // column, or its scratch home for a streamed tile)
+        auto col_step = [&](int l, const T* src, T* dst) {
             if (!(sh.snu[l] >= 0.0)) return;  // chosen column (uniform over the group)
             T x[RT];
             double d = 0.0;
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
-                x[t] = t < ntv ? col[l16 + 16 * t] : T(0);
+                x[t] = t < ntv ? src[l16 + 16 * t] : T(0);
                 d += (double)x[t] * (double)sv[t];
             }
 #pragma unroll
@@ -394,26 +397,25 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 const T y = (T)((double)x[t] - d * (double)sv[t]);
-                if (t < ntv) col[l16 + 16 * t] = y;
+                if (t < ntv) dst[l16 + 16 * t] = y;
                 tail(t, y, s2, l, true);
             }
             track(l, s2);
         };
-        for (int l = nreg + cgroup; l < c_str; l += kGroups) col_step(l, lds + (l - nreg) * mp);
+        for (int l = nreg + cgroup; l < c_str; l += kGroups) {
+            T* col = lds + (l - nreg) * mp;
+            col_step(l, col, col);
+        }
         if (ns > 0) {
-            // streamed columns: tile t + 1 in flight while tile t is updated,
-            // tile t written back to the scratch behind it
+            // streamed columns: tile t + 1 in flight while tile t is updated
+            // and stored straight back to the scratch
             __syncthreads();  // tile 0 has landed
             for (int t = 0; t < nt; ++t) {
                 if (t + 1 < nt) issue(t + 1);
                 const int c0 = c_str + t * TC, c1 = min(n, c0 + TC);
-                T* cur = (t & 1) ? buf1 : buf0;
-                for (int l = c0 + cgroup; l < c1; l += kGroups) col_step(l, cur + (l - c0) * mp);
-                lds_barrier();
-                const int cnt = (c1 - c0) * mp;
-                T* d0 = Wb + (int64_t)c0 * mp;
-                for (int e = tid; e < cnt; e += kBThreads) d0[e] = cur[e];
-                __syncthreads();  // the next tile has landed; this one is written back
+                const T* cur = (t & 1) ? buf1 : buf0;
+                for (int l = c0 + cgroup; l < c1; l += kGroups) col_step(l, cur + (l - c0) * mp, Wb + (int64_t)l * mp);
+                __syncthreads();  // the next tile has landed, this one is stored and no longer read
             }
         }
         ++k;
