@@ -119,6 +119,10 @@ constexpr int breg_cols() {
     return (RT == 2 ? 32 : (RT == 4 ? 40 : 48)) / (RT * (int)(sizeof(T) / 4));
 }
 
+// a * b + c with one rounding, in the working precision
+__device__ __forceinline__ float fma_w(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_w(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // The kernel's static LDS, handed to the per-block factorisation.
 struct BShared {
     double* snu;     // residual norm of every column (-1: chosen)
@@ -268,7 +272,7 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
         const int jt = j >> 4, jl = j & 15;
         // ---- the reflector, by the pivot column's group --------------------
         if (cgroup == p % kGroups) {
-            double x[RT];
+            T x[RT];
             if (p < nreg) {
                 const int cp = p / kGroups;
 #pragma unroll
@@ -276,7 +280,7 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
                     T v = rc[0][t];
 #pragma unroll
                     for (int c = 1; c < NR; ++c) v = c == cp ? rc[c][t] : v;
-                    x[t] = (double)v;
+                    x[t] = v;
                 }
             } else {
                 // a streamed column was last written to the scratch by other
@@ -288,7 +292,7 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
                     const int r = l16 + 16 * t;
                     T v = T(0);
                     if (t < ntv) v = dev ? __hip_atomic_load(col + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : col[r];
-                    x[t] = (double)v;
+                    x[t] = v;
                 }
             }
             // rows below j only (rows above hold R); zero below row m
@@ -296,10 +300,10 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 if (t == jt) {
-                    x0 = l16 == jl ? x[t] : 0.0;
-                    if (l16 > jl) s0 += x[t] * x[t];
+                    x0 = l16 == jl ? (double)x[t] : 0.0;
+                    if (l16 > jl) s0 += (double)x[t] * (double)x[t];
                 } else if (t > jt) {
-                    s0 += x[t] * x[t];
+                    s0 += (double)x[t] * (double)x[t];
                 }
             }
             x0 = row16_sum(x0);
@@ -310,7 +314,7 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
             const double scale = 1.0 / (x0 - beta);
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
-                double v = (double)(T)(x[t] * scale);
+                double v = (double)(T)((double)x[t] * scale);
                 if (t < jt) v = 0.0;
                 if (t == jt) v = l16 < jl ? 0.0 : (l16 == jl ? 1.0 : v);
                 sh.s_v[l16 + 16 * t] = v;
@@ -364,16 +368,14 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
             double d = 0.0;
 #pragma unroll
             for (int t = 0; t < RT; ++t) d += (double)rc[c][t] * (double)sv[t];
-            // the FP64 copies of the column are formed again below rather
-            // than held across the reduction (register pressure)
-#pragma unroll
-            for (int t = 0; t < RT; ++t) asm volatile("" : "+v"(rc[c][t]));
             d = row16_sum(d);
-            const double tc = alive ? tau * d : 0.0;
+            // the update itself in the working precision (the dot product
+            // above and the norm below accumulate in FP64)
+            const T tc = alive ? (T)(tau * d) : T(0);
             double s2 = 0.0;
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
-                const T y = (T)((double)rc[c][t] - tc * sv[t]);
+                const T y = fma_w(-tc, sv[t], rc[c][t]);
                 rc[c][t] = y;
                 tail(t, y, s2, l, alive);
             }
@@ -390,13 +392,11 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
                 x[t] = t < ntv ? src[l16 + 16 * t] : T(0);
                 d += (double)x[t] * (double)sv[t];
             }
-#pragma unroll
-            for (int t = 0; t < RT; ++t) asm volatile("" : "+v"(x[t]));
-            d = tau * row16_sum(d);
+            const T dw = (T)(tau * row16_sum(d));
             double s2 = 0.0;
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
-                const T y = (T)((double)x[t] - d * (double)sv[t]);
+                const T y = fma_w(-dw, sv[t], x[t]);
                 if (t < ntv) dst[l16 + 16 * t] = y;
                 tail(t, y, s2, l, true);
             }
