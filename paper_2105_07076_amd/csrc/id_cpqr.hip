@@ -40,8 +40,6 @@
 namespace miid {
 
 constexpr int kThreads = 256;
-constexpr int kColsPerWave = 4;
-constexpr int kColsPerWG = 16;     // 4 waves x 4 columns
 constexpr int kRowsPerChunk = 256; // rows per workgroup of the pivot-column kernel
 constexpr int kMaxNb = 64;
 constexpr int kPartAStride = kMaxNb + 1;
@@ -50,21 +48,9 @@ constexpr size_t kMaxVecLds = 131072;  // bytes of LDS for the reflector in the 
 
 
 // ---------------------------------------------------------------------------
-// a1: staging.  S (ldw x n, padded rows zero) <- A, or A^T for the dual ID.
+// a1: staging.  S (ldw x n, padded rows zero) <- A (inside the first norm
+// pass, k_norms<T, true>), or A^T for the dual ID.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_stage_copy(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                                                         T* __restrict__ S, int64_t ldw) {
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    for (int c = 0; c < kColsPerWave; ++c) {
-        const int64_t col = (int64_t)blockIdx.x * kColsPerWG + wave * kColsPerWave + c;
-        if (col >= n) break;
-        const T* a = A + col * lda;
-        T* s = S + col * ldw;
-        for (int64_t r = lane; r < ldw; r += kWave) s[r] = r < m ? a[r] : T(0);
-    }
-}
-
 // S[r, c] = A[c, r] (A is n x m with leading dimension lda), 64 x 64 tiles.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_stage_transpose(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n,
@@ -86,9 +72,12 @@ __global__ void __launch_bounds__(kThreads) k_stage_transpose(const T* __restric
 
 // Column norms of S with FP64 accumulation; sel = -1; argmax partials.
 // Workgroup b owns columns [4 cpw b, 4 cpw (b + 1)), wave w the cpw columns
-// starting at 4 cpw b + w cpw (the same partition as k_gemv).
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_norms(const T* __restrict__ S, int64_t ldw, int64_t n, int cpw,
+// starting at 4 cpw b + w cpw (the same partition as k_gemv).  With STAGE
+// the columns come from A (m x n, leading dimension lda) and are written to
+// S on the way (a1 and the first norms in one pass over A).
+template <typename T, bool STAGE>
+__global__ void __launch_bounds__(kThreads) k_norms(const T* __restrict__ A, int64_t lda, int64_t m,
+                                                    T* __restrict__ S, int64_t ldw, int64_t n, int cpw,
                                                     double* __restrict__ nu, double* __restrict__ nuref,
                                                     int32_t* __restrict__ sel, ColPartial* __restrict__ part,
                                                     int32_t* __restrict__ recomp) {
@@ -101,11 +90,48 @@ __global__ void __launch_bounds__(kThreads) k_norms(const T* __restrict__ S, int
     for (int c = 0; c < cpw; ++c) {
         const int64_t col = ((int64_t)blockIdx.x * 4 + wave) * cpw + c;
         if (col >= n) break;
-        const T* s = S + col * ldw;
         double acc = 0.0;
-        for (int64_t r = lane; r < ldw; r += kWave) {
-            const double x = (double)s[r];
-            acc += x * x;
+        if (STAGE) {
+            // A's columns need not be 16-byte aligned: element loads, four
+            // in flight per lane
+            const T* a = A + col * lda;
+            T* sc = S + col * ldw;
+            int64_t r = lane;
+            for (; r + 3 * kWave < ldw; r += 4 * kWave) {
+                T x[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[q] = r + q * kWave < m ? a[r + q * kWave] : T(0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    sc[r + q * kWave] = x[q];
+                    acc += (double)x[q] * (double)x[q];
+                }
+            }
+            for (; r < ldw; r += kWave) {
+                const T x = r < m ? a[r] : T(0);
+                sc[r] = x;
+                acc += (double)x * (double)x;
+            }
+        }
+        // 16-byte loads, four in flight per lane (ldw is a multiple of 64)
+        using VT = typename Vec16<T>::type;
+        constexpr int VEC = Vec16<T>::n;
+        const VT* s = reinterpret_cast<const VT*>(S + col * ldw);
+        const int64_t ng = STAGE ? 0 : ldw / VEC;
+        int64_t g = lane;
+        for (; g + 3 * kWave < ng; g += 4 * kWave) {
+            VT v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = s[g + q * kWave];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc += (double)get(v[q], e) * (double)get(v[q], e);
+        }
+        for (; g < ng; g += kWave) {
+            const VT v = s[g];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc += (double)get(v, e) * (double)get(v, e);
         }
         acc = wave_sum(acc);
         const double v = sqrt(acc);
@@ -865,7 +891,7 @@ __device__ __forceinline__ f4_t mfma16x16x4(float a, float b, f4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <typename T>
+template <typename T, int W>
 __global__ void __launch_bounds__(kThreads) k_trail(T* __restrict__ S, int64_t ldw, int64_t n,
                                                     const T* __restrict__ V, const T* __restrict__ F, int nb, int w,
                                                     int64_t r0, const DevState* __restrict__ st) {
@@ -892,23 +918,50 @@ __global__ void __launch_bounds__(kThreads) k_trail(T* __restrict__ S, int64_t l
                 acc[bc][br][e] = col < n ? S[row + col * ldw] : T(0);
             }
         }
-    for (int k0 = 0; k0 < w; k0 += 4) {
-        const int q = k0 + lg;
-        T a[2], b[2];
+    if (W > 0) {
+        // the whole panel's F and V operands in flight at once, then the
+        // W / 4 MFMA steps
+        constexpr int KS = W > 0 ? W / 4 : 1;
+        T a[KS][2], b[KS][2];
 #pragma unroll
-        for (int bc = 0; bc < 2; ++bc) {
-            const int64_t col = cbase + wc + bc * 16 + l16;
-            a[bc] = (q < w && col < n) ? F[col * nb + q] : T(0);
+        for (int ks = 0; ks < KS; ++ks) {
+            const int q = 4 * ks + lg;
+#pragma unroll
+            for (int bc = 0; bc < 2; ++bc) {
+                const int64_t col = cbase + wc + bc * 16 + l16;
+                a[ks][bc] = col < n ? F[col * nb + q] : T(0);
+            }
+#pragma unroll
+            for (int br = 0; br < 2; ++br) {
+                const int64_t row = rbase + wr + br * 16 + l16;
+                b[ks][br] = -V[row + (int64_t)q * ldw];
+            }
         }
 #pragma unroll
-        for (int br = 0; br < 2; ++br) {
-            const int64_t row = rbase + wr + br * 16 + l16;
-            b[br] = q < w ? -V[row + (int64_t)q * ldw] : T(0);
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+                for (int br = 0; br < 2; ++br) acc[bc][br] = mfma16x16x4(a[ks][bc], b[ks][br], acc[bc][br]);
+    } else {
+        for (int k0 = 0; k0 < w; k0 += 4) {
+            const int q = k0 + lg;
+            T a[2], b[2];
+#pragma unroll
+            for (int bc = 0; bc < 2; ++bc) {
+                const int64_t col = cbase + wc + bc * 16 + l16;
+                a[bc] = (q < w && col < n) ? F[col * nb + q] : T(0);
+            }
+#pragma unroll
+            for (int br = 0; br < 2; ++br) {
+                const int64_t row = rbase + wr + br * 16 + l16;
+                b[br] = q < w ? -V[row + (int64_t)q * ldw] : T(0);
+            }
+#pragma unroll
+            for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+                for (int br = 0; br < 2; ++br) acc[bc][br] = mfma16x16x4(a[bc], b[br], acc[bc][br]);
         }
-#pragma unroll
-        for (int bc = 0; bc < 2; ++bc)
-#pragma unroll
-            for (int br = 0; br < 2; ++br) acc[bc][br] = mfma16x16x4(a[bc], b[br], acc[bc][br]);
     }
 #pragma unroll
     for (int bc = 0; bc < 2; ++bc)
@@ -1641,10 +1694,17 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
     } else if (P.trans) {
         dim3 grid((unsigned)((ldw + 63) / 64), (unsigned)((n + 63) / 64));
         hipLaunchKernelGGL(k_stage_transpose<T>, grid, dim3(kThreads), 0, stream, A, lda, m, n, S, ldw);
-    } else {
-        hipLaunchKernelGGL(k_stage_copy<T>, dim3((unsigned)((n + kColsPerWG - 1) / kColsPerWG)), dim3(kThreads), 0,
-                           stream, A, lda, m, n, S, ldw);
     }
+    // a1 for a plain A happens inside the first norm pass
+    const bool stage_in_norms = !staged && !P.trans;
+    auto launch_norms = [&](int grid, int cpw) {
+        if (stage_in_norms)
+            hipLaunchKernelGGL((k_norms<T, true>), dim3(grid), dim3(kThreads), 0, stream, A, lda, m, S, ldw, n, cpw, nu,
+                               nuref, sel, part, recomp);
+        else
+            hipLaunchKernelGGL((k_norms<T, false>), dim3(grid), dim3(kThreads), 0, stream, (const T*)nullptr,
+                               (int64_t)0, m, S, ldw, n, cpw, nu, nuref, sel, part, recomp);
+    };
 
     const double tol = sizeof(T) == 8 ? sqrt(2.220446049250313e-16) : sqrt(1.1920928955078125e-07);
     int ksteps = P.kmax;
@@ -1668,8 +1728,7 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
     // columns per wave) into buffer 0; the steps write fnpart
     fin_npart = P.fnpart;
     fin_alt = 8 * P.fnpart;
-    hipLaunchKernelGGL(k_norms<T>, dim3(8 * P.fnpart), dim3(kThreads), 0, stream, S, ldw, n, P.fnp, nu, nuref, sel,
-                       part, recomp);
+    launch_norms(8 * P.fnpart, P.fnp);
     for (int j = 0; j < P.kmax; ++j) {
         const int jb = (j / nb) * nb;
         const int i = j - jb;
@@ -1684,7 +1743,12 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
             const int64_t rbase = r0 & ~(int64_t)63;
             dim3 grid((unsigned)((ldw - rbase + 63) / 64), (unsigned)((n + 63) / 64));
             const int pt = prof_take(MIID_K_TRAIL, j / nb, m - r0, n);
-            MIID_LAUNCH(pt, k_trail<T>, grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
+            if (nb == 32)
+                MIID_LAUNCH(pt, (k_trail<T, 32>), grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
+            else if (nb == 16)
+                MIID_LAUNCH(pt, (k_trail<T, 16>), grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
+            else
+                MIID_LAUNCH(pt, (k_trail<T, 0>), grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
         }
         if (P.tol && (j % 8 == 7) && j + 1 < P.kmax) {
             MIID_HIP(hipMemcpyAsync(&host_stop, &st->stop, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
@@ -1696,8 +1760,7 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
         }
     }
     } else if (!resident_done) {
-    hipLaunchKernelGGL(k_norms<T>, dim3(P.npart), dim3(kThreads), 0, stream, S, ldw, n, P.cpw, nu, nuref, sel, part,
-                       recomp);
+    launch_norms(P.npart, P.cpw);
     for (int j = 0; j < P.kmax; ++j) {
         const int jb = (j / nb) * nb;
         const int i = j - jb;
@@ -1724,7 +1787,12 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
             const int64_t rbase = r0 & ~(int64_t)63;
             dim3 grid((unsigned)((ldw - rbase + 63) / 64), (unsigned)((n + 63) / 64));
             pr = prof_take(MIID_K_TRAIL, j / nb, m - r0, n);
-            MIID_LAUNCH(pr, k_trail<T>, grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
+            if (nb == 32)
+                MIID_LAUNCH(pr, (k_trail<T, 32>), grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
+            else if (nb == 16)
+                MIID_LAUNCH(pr, (k_trail<T, 16>), grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
+            else
+                MIID_LAUNCH(pr, (k_trail<T, 0>), grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
         }
         if (P.tol && (j % 8 == 7) && j + 1 < P.kmax) {
             MIID_HIP(hipMemcpyAsync(&host_stop, &st->stop, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
