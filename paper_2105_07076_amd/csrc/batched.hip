@@ -224,19 +224,35 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
         }
         if (have) norm_of(l, ss);
     }
-    for (int l = nreg + cgroup; l < n; l += kGroups) {
-        T* col = home(l);
-        double ss = 0.0;
+    // the other columns CB at a time per group, all their loads in flight
+    // before the first is stored
+    constexpr int CB = RT >= 16 ? 2 : (RT >= 8 ? 4 : 8);
+    for (int l0 = nreg + cgroup; l0 < n; l0 += kGroups * CB) {
+        T xv[CB][RT];
 #pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            if (t < ntv) {
+        for (int cb = 0; cb < CB; ++cb) {
+            const int l = l0 + kGroups * cb;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
                 const int r = l16 + 16 * t;
-                const T x = r < m ? Ab[(int64_t)l * m + r] : T(0);
-                col[r] = x;
-                ss += (double)x * (double)x;
+                xv[cb][t] = (l < n && t < ntv && r < m) ? Ab[(int64_t)l * m + r] : T(0);
             }
         }
-        norm_of(l, ss);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int l = l0 + kGroups * cb;
+            if (l >= n) break;  // uniform over the group
+            T* col = home(l);
+            double ss = 0.0;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                if (t < ntv) {
+                    col[l16 + 16 * t] = xv[cb][t];
+                    ss += (double)xv[cb][t] * (double)xv[cb][t];
+                }
+            }
+            norm_of(l, ss);
+        }
     }
     if (ns > 0) __syncthreads();  // the scratch holds the streamed columns
 
