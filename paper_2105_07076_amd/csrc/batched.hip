@@ -17,8 +17,9 @@
 // LDS, and whatever does not fit in a per-workgroup scratch that every pass
 // streams through two LDS column tiles (the next tile's loads in flight while
 // the current one is updated, the updated one written back behind it).  The
-// pivot column's group forms the reflector, so a step costs two workgroup
-// barriers.  R stays in W's first k rows and is copied row by row into Z's
+// waves stage their best columns at the end of a pass and every lane forms
+// the next reflector itself, so a step costs two workgroup barriers and no
+// serial section.  R stays in W's first k rows and is copied row by row into Z's
 // storage (no column swaps); the k x k triangle is staged in LDS in FP64 for
 // the solve, which then overwrites Z in place.
 #include <algorithm>
@@ -33,9 +34,10 @@ namespace miid {
 
 constexpr int kBThreads = 512;
 constexpr int kBWaves = kBThreads / kWave;
-// dynamic LDS (V, then the block or its column tiles): what the 160 KB of a
-// CU leave beside the kernel's static arrays
-constexpr int bdyn_bytes(int) { return 148 * 1024; }
+// dynamic LDS (the block's LDS columns and tiles, later the triangle of the
+// solve): what the 160 KB of a CU leave beside the kernel's static arrays
+// (residual norms, the waves' staged columns, a few scalars)
+constexpr int bdyn_bytes(int esz) { return 160 * 1024 - 9 * 1024 - 8 * 256 * esz; }
 constexpr int kBTileBytes = 24 * 1024;  // default streamed column tile (the rest of LDS keeps columns resident)
 constexpr int kBMaxM = 256;
 constexpr int kBMaxN = 1024;
@@ -87,36 +89,15 @@ __global__ void k_zero_queue(int32_t* __restrict__ queue) {
     if (threadIdx.x == 0) *queue = 0;
 }
 
-// Block-wide (value, index) argmax and sum: wave results through LDS, read
-// back in wave order (identical in every thread).  The LDS slots alternate
-// between two sets by call parity, so one barrier suffices: a wave can only
-// reach the call after next once every wave has left this one.
-__device__ __forceinline__ void block_argmax_sum(ArgMax& best, double& sum, ArgMax* w_best, double* w_sum, int par) {
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    best = wave_argmax_dpp(best);
-    sum = wave_sum_dpp(sum);
-    ArgMax* wb = w_best + par * kBWaves;
-    double* ws = w_sum + par * kBWaves;
-    if (lane == 0) {
-        wb[wave] = best;
-        ws[wave] = sum;
-    }
-    lds_barrier();
-    best = wb[0];
-    sum = ws[0];
-    for (int w = 1; w < kBWaves; ++w) {
-        if (argmax_better(wb[w].v, wb[w].i, best.v, best.i)) best = wb[w];
-        sum += ws[w];
-    }
-}
-
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
-// Columns of a block kept in registers, per 16-lane group: 32 to 48 VGPRs
-// (what the pass leaves free of the 256 a lane has at two waves per SIMD).
+// Columns of a block kept in registers, per 16-lane group: what the pass
+// leaves free of the 256 VGPRs a lane has at two waves per SIMD (FP64
+// columns take twice the registers and the pass's FP64 state more too).
 template <typename T, int RT>
 constexpr int breg_cols() {
-    return (RT == 2 ? 32 : (RT == 4 ? 40 : 48)) / (RT * (int)(sizeof(T) / 4));
+    return sizeof(T) == 4 ? (RT == 2 ? 32 : (RT == 4 ? 40 : 48)) / RT
+                          : (RT == 16 ? 0 : 16 / (2 * RT));
 }
 
 // a * b + c with one rounding, in the working precision
@@ -124,13 +105,13 @@ __device__ __forceinline__ float fma_w(float a, float b, float c) { return __bui
 __device__ __forceinline__ double fma_w(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // The kernel's static LDS, handed to the per-block factorisation.
+template <typename T>
 struct BShared {
     double* snu;     // residual norm of every column (-1: chosen)
-    double* s_v;     // the reflector (v_j = 1, zero above j and below m)
-    ArgMax* w_best;  // 2 x kBWaves
-    double* w_sum;   // 2 x kBWaves
+    ArgMax* w_best;  // per wave
+    double* w_sum;   // per wave
+    T* w_col;        // per wave its best column (kBMaxM rows)
     int32_t* s_sel;  // chosen columns in order
-    double* s_scal;  // tau, 1 if the reflector exists
 };
 
 struct BResult {
@@ -146,20 +127,27 @@ struct BResult {
 // the workgroup's scratch Wb, streamed through two LDS tiles of TC columns
 // per pass.  Columns in LDS and in the scratch are stored with the row count
 // padded to mp = a multiple of 16 (zeros below row m), so whole slices t are
-// either in the column or not and no per-row bounds are needed.  Each step:
-// argmax of the residual norms (one barrier), the reflector formed by the
-// pivot column's group, a barrier, then one pass that applies it to every
-// alive column, writes row j of R into Zb and recomputes the residual norms
-// exactly (FP64 accumulation).
+// either in the column or not and no per-row bounds are needed.
+//
+// A step: at the end of the previous pass each wave stages its best column
+// (and its residual norm and sum) in LDS; after one barrier every lane picks
+// the pivot from the eight wave entries and forms the reflector itself from
+// the staged column -- alpha is the pivot's residual norm from the pass (its
+// rows j.. are what the reflector annihilates), so only x0 = x[j] is read --
+// and after a second barrier (the staging area is reused) the pass applies
+// H = I - tau v v^T to every alive column, writes row j of R into Zb and
+// recomputes the residual norms exactly (FP64 accumulation of the stored
+// values).
 template <typename T, int RT>
 __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __restrict__ Zb, T* __restrict__ Wb,
                                                 int m, int n, int kb, double eps, int tile_bytes,
-                                                unsigned char* smem_raw, BShared sh) {
+                                                unsigned char* smem_raw, BShared<T> sh) {
     constexpr int NR = breg_cols<T, RT>();
     constexpr int kDyn = bdyn_bytes((int)sizeof(T)) / (int)sizeof(T);
     constexpr int kGroups = kBWaves * 4;
     const int tid = threadIdx.x;
     const int lane = tid % kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
     int l16 = lane & 15;
     // opaque to the optimiser: what is derived from it is formed here, per
     // block, instead of being hoisted out of the persistent loop for every
@@ -183,8 +171,73 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
     // home of column l >= nreg: LDS or the scratch
     auto home = [&](int l) { return l < c_str ? lds + (l - nreg) * mp : Wb + (int64_t)l * mp; };
 
-    T rc[NR][RT];   // register-resident columns cgroup + 32 c (zero below row m)
-    T sv[RT];  // v at this lane's rows (v is rounded to T, so exact)
+    T rc[NR > 0 ? NR : 1][RT];  // register-resident columns cgroup + 32 c (zero below row m)
+    T sv[RT];      // v at this lane's rows (v is rounded to T, so exact)
+    ArgMax gb{-1.0, INT32_MAX};  // the group's best (the same in its 16 lanes)
+    double acc = 0.0;            // the group's sum (the same in its 16 lanes)
+
+    // a column's new residual norm: the group's best and sum, branch-free
+    auto consider = [&](int l, double nu, double add) {
+        acc += add;
+        const bool bt = argmax_better(nu, l, gb.v, gb.i);
+        gb.v = bt ? nu : gb.v;
+        gb.i = bt ? l : gb.i;
+    };
+    // the wave's best of its four groups (row leaders, fixed order), staged
+    // with its column; a streamed column is read back from the scratch
+    // (written there by other lanes: device scope, past this CU's L1)
+    auto publish = [&]() {
+        ArgMax wbst{-1.0, INT32_MAX};
+        double wsum = 0.0;
+        int wrow = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t bits = __builtin_bit_cast(int64_t, gb.v);
+            const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffff), 16 * r);
+            const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), 16 * r);
+            const double v = __builtin_bit_cast(double, ((int64_t)hi << 32) | (uint32_t)lo);
+            const int32_t i = __builtin_amdgcn_readlane(gb.i, 16 * r);
+            const int64_t abits = __builtin_bit_cast(int64_t, acc);
+            const int alo = __builtin_amdgcn_readlane((int)(abits & 0xffffffff), 16 * r);
+            const int ahi = __builtin_amdgcn_readlane((int)(abits >> 32), 16 * r);
+            wsum += __builtin_bit_cast(double, ((int64_t)ahi << 32) | (uint32_t)alo);
+            if (argmax_better(v, i, wbst.v, wbst.i)) {
+                wbst = {v, i};
+                wrow = r;
+            }
+        }
+        const int q = wbst.i;  // wave-uniform
+        if ((lane >> 4) == wrow && wbst.v >= 0.0) {
+            T* slot = sh.w_col + wave * kBMaxM;
+            if (q < nreg) {
+                // one uniform branch per register column (a select chain
+                // over c would be turned into an indexed, memory-held array)
+                const int cq = q / kGroups;
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    if (c == cq) {
+#pragma unroll
+                        for (int t = 0; t < RT; ++t) slot[l16 + 16 * t] = rc[c][t];
+                    }
+                }
+            } else if (q < c_str) {
+                const T* col = lds + (q - nreg) * mp;
+#pragma unroll
+                for (int t = 0; t < RT; ++t) slot[l16 + 16 * t] = t < ntv ? col[l16 + 16 * t] : T(0);
+            } else {
+                const T* col = Wb + (int64_t)q * mp;
+#pragma unroll
+                for (int t = 0; t < RT; ++t) {
+                    const int r = l16 + 16 * t;
+                    slot[r] = t < ntv ? __hip_atomic_load(col + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : T(0);
+                }
+            }
+        }
+        if (lane == 0) {
+            sh.w_best[wave] = wbst;
+            sh.w_sum[wave] = wsum;
+        }
+    };
 
     // copy the streamed tile t of the scratch into its LDS buffer (no registers)
     auto issue = [&](int t) {
@@ -199,16 +252,11 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
     };
 
     // ---- first pass: every column from A_b to its home, exact norms --------
-    ArgMax best{-1.0, INT32_MAX};
-    double acc = 0.0;  // this lane's share of the sum over columns
-    auto norm_of = [&](int l, double ss) {
+    auto first_norm = [&](int l, double ss) {
         ss = row16_sum(ss);
-        if (l16 == 0) {
-            const double nu = sqrt(ss);
-            sh.snu[l] = nu;
-            acc += ss;
-            if (argmax_better(nu, l, best.v, best.i)) best = {nu, l};
-        }
+        const double nu = sqrt(ss);
+        if (l16 == 0) sh.snu[l] = nu;
+        consider(l, nu, ss);
     };
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
@@ -222,7 +270,7 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
             rc[c][t] = x;
             ss += (double)x * (double)x;
         }
-        if (have) norm_of(l, ss);
+        if (have) first_norm(l, ss);
     }
     // the other columns CB at a time per group, all their loads in flight
     // before the first is stored
@@ -251,18 +299,40 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
                     ss += (double)xv[cb][t] * (double)xv[cb][t];
                 }
             }
-            norm_of(l, ss);
+            first_norm(l, ss);
         }
     }
-    if (ns > 0) __syncthreads();  // the scratch holds the streamed columns
+    if (ns > 0) {
+        __syncthreads();  // the scratch holds the streamed columns
+        issue(0);         // the first tile of the first step's pass
+    }
+    publish();
 
-    int k = 0, par = 0;
+    int k = 0;
     uint32_t status = 0;
     double a_norm = 0.0, resid = 0.0, stop_abs = 0.0;
     for (;;) {
-        double ss = acc;
-        block_argmax_sum(best, ss, sh.w_best, sh.w_sum, par);
-        par ^= 1;
+        lds_barrier();
+        // ---- the pivot: best of the eight wave entries ----------------------
+        ArgMax e[kBWaves];
+        double sm[kBWaves];
+#pragma unroll
+        for (int w = 0; w < kBWaves; ++w) {
+            e[w] = sh.w_best[w];
+            sm[w] = sh.w_sum[w];
+        }
+        ArgMax best = e[0];
+        double ss = sm[0];
+        int bw = 0;
+#pragma unroll
+        for (int w = 1; w < kBWaves; ++w) {
+            if (argmax_better(e[w].v, e[w].i, best.v, best.i)) {
+                best = e[w];
+                bw = w;
+            }
+            ss += sm[w];
+        }
+        const T* pc = sh.w_col + bw * kBMaxM;  // the pivot column
         if (k == 0) {
             a_norm = sqrt(ss);
             stop_abs = eps * a_norm;
@@ -286,86 +356,29 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
         const int p = best.i;
         const int j = k;
         const int jt = j >> 4, jl = j & 15;
-        // ---- the reflector, by the pivot column's group --------------------
-        if (cgroup == p % kGroups) {
-            T x[RT];
-            if (p < nreg) {
-                const int cp = p / kGroups;
+        // ---- the reflector, in every lane ------------------------------------
+        const double alpha = best.v;
+        const double x0 = (double)pc[j];
+        const double beta = x0 >= 0.0 ? -alpha : alpha;
+        const double tau = (beta - x0) / beta;
+        const double scale = 1.0 / (x0 - beta);
 #pragma unroll
-                for (int t = 0; t < RT; ++t) {
-                    T v = rc[0][t];
-#pragma unroll
-                    for (int c = 1; c < NR; ++c) v = c == cp ? rc[c][t] : v;
-                    x[t] = v;
-                }
-            } else {
-                // a streamed column was last written to the scratch by other
-                // lanes: read it at device scope, past this CU's L1
-                const T* col = home(p);
-                const bool dev = p >= c_str;
-#pragma unroll
-                for (int t = 0; t < RT; ++t) {
-                    const int r = l16 + 16 * t;
-                    T v = T(0);
-                    if (t < ntv) v = dev ? __hip_atomic_load(col + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : col[r];
-                    x[t] = v;
-                }
-            }
-            // rows below j only (rows above hold R); zero below row m
-            double x0 = 0.0, s0 = 0.0;
-#pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                if (t == jt) {
-                    x0 = l16 == jl ? (double)x[t] : 0.0;
-                    if (l16 > jl) s0 += (double)x[t] * (double)x[t];
-                } else if (t > jt) {
-                    s0 += (double)x[t] * (double)x[t];
-                }
-            }
-            x0 = row16_sum(x0);
-            s0 = row16_sum(s0);
-            const double alpha = sqrt(x0 * x0 + s0);
-            const double beta = x0 >= 0.0 ? -alpha : alpha;
-            const double tau = (beta - x0) / beta;
-            const double scale = 1.0 / (x0 - beta);
-#pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                double v = (double)(T)((double)x[t] * scale);
-                if (t < jt) v = 0.0;
-                if (t == jt) v = l16 < jl ? 0.0 : (l16 == jl ? 1.0 : v);
-                sh.s_v[l16 + 16 * t] = v;
-            }
-            if (l16 == 0) {
-                sh.s_scal[0] = tau;
-                sh.s_scal[1] = alpha > 0.0 ? 1.0 : 0.0;
-                sh.s_sel[j] = p;
-                sh.snu[p] = -1.0;
-                Zb[j + (int64_t)p * kb] = (T)beta;
-            }
+        for (int t = 0; t < RT; ++t) {
+            T v = (T)((double)pc[l16 + 16 * t] * scale);
+            if (t < jt) v = T(0);
+            if (t == jt) v = l16 < jl ? T(0) : (l16 == jl ? T(1) : v);
+            sv[t] = v;
         }
-        if (ns > 0) issue(0);  // the first streamed tile of the pass
-        lds_barrier();
-        if (!(sh.s_scal[1] > 0.0)) {
-            status |= MIID_RANK_DEFICIENT;
-            if (ns > 0) __syncthreads();  // no tile copy left in flight
-            break;
+        if (tid == 0) {
+            sh.s_sel[j] = p;
+            sh.snu[p] = -1.0;
+            Zb[j + (int64_t)p * kb] = (T)beta;
         }
-        const double tau = sh.s_scal[0];
-#pragma unroll
-        for (int t = 0; t < RT; ++t) sv[t] = (T)sh.s_v[l16 + 16 * t];
+        lds_barrier();  // the staged entries are read before the pass restages them
 
         // ---- the pass: H = I - tau v v^T on every alive column -------------
-        best = {-1.0, INT32_MAX};
+        gb = {-1.0, INT32_MAX};
         acc = 0.0;
-        auto track = [&](int l, double s2) {
-            s2 = row16_sum(s2);
-            if (l16 == 0) {
-                const double nu = sqrt(s2);
-                sh.snu[l] = nu;
-                acc += nu * nu;
-                if (argmax_better(nu, l, best.v, best.i)) best = {nu, l};
-            }
-        };
         // s2 over rows > j and the store of row j, from slice t of y
         auto tail = [&](int t, T y, double& s2, int l, bool alive) {
             if (t > jt) s2 += (double)y * (double)y;
@@ -373,6 +386,12 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
                 if (l16 > jl) s2 += (double)y * (double)y;
                 if (l16 == jl && alive) Zb[j + (int64_t)l * kb] = y;
             }
+        };
+        auto track = [&](int l, double s2) {
+            s2 = row16_sum(s2);
+            const double nu = sqrt(s2);
+            if (l16 == 0) sh.snu[l] = nu;
+            consider(l, nu, nu * nu);
         };
         // register columns, branch-free (a chosen or missing column gets
         // tau = 0, which leaves it unchanged)
@@ -412,9 +431,9 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
             double s2 = 0.0;
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
-                const T y = fma_w(-dw, sv[t], x[t]);
-                if (t < ntv) dst[l16 + 16 * t] = y;
-                tail(t, y, s2, l, true);
+                x[t] = fma_w(-dw, sv[t], x[t]);
+                if (t < ntv) dst[l16 + 16 * t] = x[t];
+                tail(t, x[t], s2, l, true);
             }
             track(l, s2);
         };
@@ -433,9 +452,12 @@ __device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __r
                 for (int l = c0 + cgroup; l < c1; l += kGroups) col_step(l, cur + (l - c0) * mp, Wb + (int64_t)l * mp);
                 __syncthreads();  // the next tile has landed, this one is stored and no longer read
             }
+            issue(0);  // the first tile of the next step's pass
         }
         ++k;
+        publish();
     }
+    if (ns > 0) __syncthreads();  // no tile copy left in flight
     return BResult{k, status, a_norm, resid};
 }
 
@@ -451,15 +473,14 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
                                                        T* __restrict__ Wscr, int tile_bytes) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double snu[kBMaxN];
-    __shared__ double s_v[kBMaxM];
-    __shared__ ArgMax w_best[2 * kBWaves];
-    __shared__ double w_sum[2 * kBWaves];
+    __shared__ ArgMax w_best[kBWaves];
+    __shared__ double w_sum[kBWaves];
+    __shared__ T w_col[kBWaves * kBMaxM];
     __shared__ int32_t s_sel[kBMaxK];
-    __shared__ double s_scal[2];
     __shared__ int32_t s_blk;
     const int tid = threadIdx.x;
     T* Wb = Wscr + (int64_t)blockIdx.x * kBMaxM * kBMaxN;  // W when it does not fit on chip
-    const BShared sh{snu, s_v, w_best, w_sum, s_sel, s_scal};
+    const BShared<T> sh{snu, w_best, w_sum, w_col, s_sel};
 
     for (;;) {
         if (tid == 0) s_blk = atomicAdd(queue, 1);
