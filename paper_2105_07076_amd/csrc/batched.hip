@@ -510,18 +510,18 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
 
         // triangular solve: Z[:, l] = R11^{-1} R[:, l] in FP64, Z[:, J[i]] = e_i.
         // The strict upper triangle of R11 goes to sR (zeros elsewhere, up to
-        // k rounded to 4), its diagonal to sD: the updates below then need no
-        // bounds tests.
+        // k rounded to 4), the reciprocals of its diagonal to sDi: the updates
+        // below then need no bounds tests and no divisions.
         constexpr int kSR = kBMaxK + 1;
         double* sR = reinterpret_cast<double*>(smem_raw);  // reuses the dynamic LDS
-        double* sD = sR + kBMaxK * kSR;
+        double* sDi = sR + kBMaxK * kSR;  // reciprocals of the diagonal
         const int kq4 = (k + 3) & ~3;
         __syncthreads();
         for (int e = tid; e < kq4 * kq4; e += kBThreads) {
             const int a = e % kq4, c = e / kq4;
             sR[a * kSR + c] = (a < c && c < k) ? (double)Zb[a + (int64_t)s_sel[c] * kb] : 0.0;
         }
-        for (int t = tid; t < k; t += kBThreads) sD[t] = (double)Zb[t + (int64_t)s_sel[t] * kb];
+        for (int t = tid; t < k; t += kBThreads) sDi[t] = 1.0 / (double)Zb[t + (int64_t)s_sel[t] * kb];
         __syncthreads();
         int32_t* Jb = J + j_off[b];
         for (int i = tid; i < kb; i += kBThreads) Jb[i] = i < k ? s_sel[i] : -1;
@@ -548,7 +548,7 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
                 for (int r = 3; r >= 0; --r) {
                     const int t = 4 * i + r;
                     if (t >= k) continue;  // uniform
-                    double zt = z[i] / sD[t];
+                    double zt = z[i] * sDi[t];
                     zt = r == 0 ? dpp_f64<0x00>(zt) : (r == 1 ? dpp_f64<0x55>(zt) : (r == 2 ? dpp_f64<0xAA>(zt) : dpp_f64<0xFF>(zt)));
                     if (c == r) z[i] = zt;
                     // rows q < t take R[q, t] z_t; sR is zero on and below

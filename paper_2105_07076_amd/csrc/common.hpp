@@ -141,6 +141,32 @@ __device__ __forceinline__ ArgMax wave_argmax_dpp(ArgMax a) {
 // Argmax over the wave (every lane active); wave-uniform result.
 __device__ __forceinline__ ArgMax wave_argmax(ArgMax a) { return wave_argmax_dpp(a); }
 
+// Fold W per-wave (value, index, sum, flag) entries from LDS: every load is
+// issued before the first comparison, then the fixed-order fold (the same
+// result in every thread).
+template <int W>
+__device__ __forceinline__ void fold_waves(const double* bv, const int32_t* bi, const double* bs, const int32_t* bf,
+                                           ArgMax& best, double& sum, int& flag) {
+    double v[W], s[W];
+    int32_t id[W], f[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        v[w] = bv[w];
+        id[w] = bi[w];
+        s[w] = bs[w];
+        f[w] = bf[w];
+    }
+    best = ArgMax{v[0], id[0]};
+    sum = s[0];
+    flag = f[0];
+#pragma unroll
+    for (int w = 1; w < W; ++w) {
+        if (argmax_better(v[w], id[w], best.v, best.i)) best = ArgMax{v[w], id[w]};
+        sum += s[w];
+        flag |= f[w];
+    }
+}
+
 // Per-workgroup partial result of a pass over the alive columns: the best
 // residual norm with its column, and the sum of squared residual norms.
 struct ColPartial {

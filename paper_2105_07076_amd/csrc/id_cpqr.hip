@@ -229,14 +229,7 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
         w_nf[wave] = nf;
     }
     __syncthreads();
-    best = ArgMax{w_best[0], w_idx[0]};
-    sumsq = w_sum[0];
-    nf = w_nf[0];
-    for (int w = 1; w < 4; ++w) {
-        if (argmax_better(w_best[w], w_idx[w], best.v, best.i)) best = {w_best[w], w_idx[w]};
-        sumsq += w_sum[w];
-        nf |= w_nf[w];
-    }
+    fold_waves<4>(w_best, w_idx, w_sum, w_nf, best, sumsq, nf);
 
     const double a_norm = (j == 0) ? sqrt(sumsq) : st->a_norm;
     uint32_t status = 0;
@@ -658,14 +651,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
         w_nf[wave] = nf;
     }
     lds_barrier();
-    best = ArgMax{w_best[0], w_idx[0]};
-    sumsq = w_sum[0];
-    nf = w_nf[0];
-    for (int w = 1; w < kFusedWaves; ++w) {
-        if (argmax_better(w_best[w], w_idx[w], best.v, best.i)) best = {w_best[w], w_idx[w]};
-        sumsq += w_sum[w];
-        nf |= w_nf[w];
-    }
+    fold_waves<kFusedWaves>(w_best, w_idx, w_sum, w_nf, best, sumsq, nf);
     const double a_norm = (j == 0) ? sqrt(sumsq) : a_prev;
     {
         uint32_t status = 0;
