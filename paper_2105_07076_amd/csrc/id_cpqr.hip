@@ -1047,9 +1047,20 @@ __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, in
     const int l16 = lane % 16, lq = lane / 16;
     const int64_t c0 = (int64_t)blockIdx.x * NC;
     const int64_t col = c0 + tc + l16;  // this lane's output column
-    for (int e = tid; e < kend * NC; e += NT) {
-        const int q = e / NC, c = e % NC;
-        sX[q * NCP + c] = (q < K && c0 + c < n) ? (double)R[(int64_t)q * n + c0 + c] : 0.0;
+    // the right-hand sides into LDS, eight loads per thread in flight
+    for (int e0 = tid; e0 < kend * NC; e0 += 8 * NT) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * NT;
+            const int q = e / NC, c = e % NC;
+            v[u] = (e < kend * NC && q < K && c0 + c < n) ? (double)R[(int64_t)q * n + c0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * NT;
+            if (e < kend * NC) sX[(e / NC) * NCP + e % NC] = v[u];
+        }
     }
     __syncthreads();
     for (int sweep = 0; sweep < (refine ? 2 : 1); ++sweep) {
@@ -1064,13 +1075,19 @@ __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, in
                 else
                     acc[e] = (row < K && col < n) ? (double)R[(int64_t)row * n + col] : 0.0;
             }
+            // one kTB-deep slice of R11 at a time (kend - kstart is a
+            // multiple of kTB): its eight operand loads are all in flight
+            // before the first product waits on them
             const int kstart = sweep == 0 ? r0 + kTB : r0;
-            const double* ap = R11s + (r0 + tr + l16) + (int64_t)(kstart + lq) * kpad;
-#pragma unroll 4
-            for (int k0 = kstart; k0 < kend; k0 += 4, ap += 4 * (int64_t)kpad) {
-                const double av = -*ap;
-                const double xv = sX[(k0 + lq) * NCP + tc + l16];
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xv, acc, 0, 0, 0);
+            const double* ap = R11s + (r0 + tr + l16) + (int64_t)lq * kpad;
+            for (int k0 = kstart; k0 < kend; k0 += kTB) {
+                double av[kTB / 4], xv[kTB / 4];
+#pragma unroll
+                for (int q = 0; q < kTB / 4; ++q) av[q] = ap[(int64_t)(k0 + 4 * q) * kpad];
+#pragma unroll
+                for (int q = 0; q < kTB / 4; ++q) xv[q] = sX[(k0 + 4 * q + lq) * NCP + tc + l16];
+#pragma unroll
+                for (int q = 0; q < kTB / 4; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[q], xv[q], acc, 0, 0, 0);
             }
 #pragma unroll
             for (int e = 0; e < 4; ++e) sT[tr + lq + 4 * e][tc + l16] = acc[e];
@@ -1091,11 +1108,16 @@ __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, in
             __syncthreads();
         }
     }
+    // Z, column by column of the workgroup's NC: the columns' selection
+    // marks first (one load per column), then the stores
+    __shared__ int32_t s_sel[NC];
+    for (int cc = tid; cc < NC; cc += NT) s_sel[cc] = c0 + cc < n ? sel[c0 + cc] : -1;
+    __syncthreads();
     for (int e = tid; e < kmax * NC; e += NT) {
         const int q = e % kmax, cc = e / kmax;
         const int64_t c = c0 + cc;
         if (c >= n) continue;
-        const int s = sel[c];
+        const int s = s_sel[cc];
         double val;
         if (s >= 0 && s < K)
             val = (q == s) ? 1.0 : 0.0;
