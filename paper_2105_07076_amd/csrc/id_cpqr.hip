@@ -997,12 +997,17 @@ __global__ void __launch_bounds__(kTB) k_trsm_dinv(const double* __restrict__ R1
     __shared__ double sx[kTB][kTB + 1];  // sx[row][t]
     const int b = blockIdx.x, t = threadIdx.x;
     const int64_t r0 = (int64_t)b * kTB;
-    for (int c = 0; c < kTB; ++c) sD[t][c] = R11s[(r0 + t) + (r0 + c) * kpad];
+    double d[kTB];
+#pragma unroll
+    for (int c = 0; c < kTB; ++c) d[c] = R11s[(r0 + t) + (r0 + c) * kpad];  // all loads in flight
+#pragma unroll
+    for (int c = 0; c < kTB; ++c) sD[t][c] = d[c];
     __syncthreads();
     for (int r = kTB - 1; r >= 0; --r) {
         double x = 0.0;
         if (r <= t) {
             double acc = (r == t) ? 1.0 : 0.0;
+#pragma unroll 8
             for (int c = r + 1; c <= t; ++c) acc -= sD[r][c] * sx[c][t];
             x = acc / sD[r][r];
         }
@@ -1154,7 +1159,9 @@ __global__ void k_finalize(const DevState* __restrict__ st, const ColPartial* __
     const int np = (part_alt > 0 && Kd == 0) ? npart0 : npart;
     double s = 0.0;
     int rc = 0;
+#pragma unroll 8
     for (int q = t; q < np; q += kThreads) s += part[q].sumsq;
+#pragma unroll 8
     for (int q = t; q < npart; q += kThreads) rc += recomp[q];
     s_sum[t] = s;
     s_rec[t] = rc;
