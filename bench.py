@@ -85,8 +85,8 @@ def time_id(miid_api, lib, A, k, steps, warmup, sample_every=7):
 GEMV_TRAFFIC = {
     "bytes_per_launch": 528.8e6,
     "sources": {
-        "paper_2105_07076_amd/csrc/id_cpqr.hip": "5d4b8cedf3404c742bc823457358466fc9454a3b5bdfc8bbfbe7e264a5452475",
-        "paper_2105_07076_amd/csrc/common.hpp": "9ee920512e6556ed77256f87fc251b5fe7a2dbd6efc59cff38f69e9222716f13",
+        "paper_2105_07076_amd/csrc/id_cpqr.hip": "2d3c3be20f8925f74e84eacc11c31c52caadaa687a737fb9038c6774bf1b0799",
+        "paper_2105_07076_amd/csrc/common.hpp": "0aced8b4e3ec60eb1f1d6948e61f743d682b1df65ec1c89db52c999f2a38ebe4",
         "paper_2105_07076_amd/csrc/cpqr.hpp": "e002806934b941a7b8c686698d55d3e93423adffd1eefd46e79fcbc23b7204ff",
     },
 }

@@ -44,50 +44,43 @@ constexpr int kBMaxN = 1024;
 constexpr int kBMaxK = 64;
 constexpr uint32_t kBlockUnsupported = 16u;
 
-// Sort block indices by decreasing m * n (ties by index) into order[]:
-// bitonic sort of (size, index) keys in LDS by one workgroup.
+// Order the blocks by decreasing size for the queue (longest first): a
+// counting sort of one workgroup on the coarse key m n / 256 (1024 buckets
+// cover every admissible block; the order inside a bucket is whatever the
+// LDS atomics give -- it only affects which workgroup takes a block, not its
+// result).  Also zeroes the queue.
+constexpr int kLptBuckets = 1024;
+
 __global__ void __launch_bounds__(1024) k_lpt_order(const int32_t* __restrict__ m, const int32_t* __restrict__ n,
-                                                    int32_t nblk, int32_t* __restrict__ order) {
-    __shared__ uint64_t key[8192];
-    int P = 1;
-    while (P < nblk) P <<= 1;
-    for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        if (i < nblk) {
-            const uint64_t sz = (uint64_t)(int64_t)m[i] * (uint64_t)(int64_t)n[i];
-            // larger size first: sort ascending on (~size, index)
-            key[i] = ((~sz & 0xFFFFFFFFull) << 32) | (uint64_t)(uint32_t)i;
-        } else {
-            key[i] = ~0ull;
-        }
-    }
+                                                    int32_t nblk, int32_t* __restrict__ order,
+                                                    int32_t* __restrict__ queue) {
+    __shared__ int32_t cnt[kLptBuckets];
+    __shared__ int32_t scan[kLptBuckets];
+    const int tid = threadIdx.x;
+    auto bucket = [&](int i) {
+        const int64_t sz = (int64_t)max(m[i], 0) * (int64_t)max(n[i], 0);
+        return kLptBuckets - 1 - (int)min<int64_t>(sz >> 8, kLptBuckets - 1);  // larger first
+    };
+    for (int b = tid; b < kLptBuckets; b += blockDim.x) cnt[b] = 0;
     __syncthreads();
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int i = threadIdx.x; i < P; i += blockDim.x) {
-                const int ixj = i ^ jj;
-                if (ixj > i) {
-                    const bool up = (i & k) == 0;
-                    const uint64_t a = key[i], b = key[ixj];
-                    if ((a > b) == up) {
-                        key[i] = b;
-                        key[ixj] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    for (int i = tid; i < nblk; i += blockDim.x) atomicAdd(&cnt[bucket(i)], 1);
+    __syncthreads();
+    // exclusive prefix sum over the buckets (one per thread, Hillis-Steele)
+    const int v = tid < kLptBuckets ? cnt[tid] : 0;
+    if (tid < kLptBuckets) scan[tid] = v;
+    __syncthreads();
+    for (int d = 1; d < kLptBuckets; d <<= 1) {
+        const int t = (tid < kLptBuckets && tid >= d) ? scan[tid - d] : 0;
+        __syncthreads();
+        if (tid < kLptBuckets) scan[tid] += t;
+        __syncthreads();
     }
-    for (int i = threadIdx.x; i < nblk; i += blockDim.x) order[i] = (int32_t)(key[i] & 0xFFFFFFFFull);
+    if (tid < kLptBuckets) cnt[tid] = scan[tid] - v;  // start of the bucket
+    __syncthreads();
+    for (int i = tid; i < nblk; i += blockDim.x) order[atomicAdd(&cnt[bucket(i)], 1)] = i;
+    if (tid == 0) *queue = 0;
 }
 
-__global__ void k_iota(int32_t* __restrict__ order, int32_t nblk, int32_t* __restrict__ queue) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nblk; i += gridDim.x * blockDim.x) order[i] = i;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0;
-}
-
-__global__ void k_zero_queue(int32_t* __restrict__ queue) {
-    if (threadIdx.x == 0) *queue = 0;
-}
 
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
@@ -637,12 +630,7 @@ int id_batched(int32_t nblk, const void* A, const int64_t* a_off, const int32_t*
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
     int32_t* order = reinterpret_cast<int32_t*>(w + P.oOrder);
     int32_t* queue = reinterpret_cast<int32_t*>(w + P.oQueue);
-    if (nblk <= 8192) {
-        hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), 0, s, m, n, nblk, order);
-        hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, s, queue);
-    } else {
-        hipLaunchKernelGGL(k_iota, dim3(64), dim3(256), 0, s, order, nblk, queue);
-    }
+    hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), 0, s, m, n, nblk, order, queue);
     const int pr = prof_take(MIID_K_BATCHED, 0, nblk, 0);
     const size_t shmem = (size_t)bdyn_bytes((int)esz);
     if (dtype == MIID_F64) {
