@@ -200,6 +200,18 @@ struct Vec16<float> {
     static constexpr int n = 4;
 };
 
+// 16-byte load marked nontemporal (not kept in the caches on its way in)
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double2 load_nt(const double2* p) {
+    const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+    return double2(v.x, v.y);
+}
+__device__ __forceinline__ float4 load_nt(const float4* p) {
+    const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+    return float4(v.x, v.y, v.z, v.w);
+}
+
 __device__ __forceinline__ double get(const double2& v, int e) { return e == 0 ? v.x : v.y; }
 __device__ __forceinline__ double get(const float4& v, int e) {
     return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
