@@ -184,8 +184,9 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
                                                         int npart, double* __restrict__ partA,
                                                         DevState* __restrict__ st, int32_t* __restrict__ J, int j,
                                                         int i, int tol_mode, double eps) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double s_F[kMaxNb];
-    __shared__ double s_red[4][kPartAStride];
+    __shared__ double s_red[kThreads / 32][kPartAStride];
     __shared__ double w_best[4], w_sum[4];
     __shared__ int32_t w_idx[4], w_nf[4];
     const int tid = threadIdx.x;
@@ -194,31 +195,36 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
     const bool active = r >= j && r < m;
     const int stop_in = st->stop;
 
-    // row r of the panel's reflectors does not depend on the pivot: load first
-    double vr[kMaxNb];
-#pragma unroll
-    for (int q = 0; q < kMaxNb; ++q) vr[q] = (active && q < i) ? (double)V[r + (int64_t)q * ldw] : 0.0;
-
     // a2: pivot = argmax of the per-workgroup column partials (same order in
-    // every workgroup, no atomics)
+    // every workgroup, no atomics).  The first kPU per thread are all issued
+    // before anything else, so one memory round trip covers them.
     ArgMax best{-1.0, INT32_MAX};
     double sumsq = 0.0;
     int nf = 0;
-    // all partial loads of a thread are issued before any is consumed
-    constexpr int kPU = 8;
-    for (int q0 = tid; q0 < npart; q0 += kPU * kThreads) {
-        ColPartial cp[kPU];
+    constexpr int kPU = 16;
+    ColPartial cp[kPU];
 #pragma unroll
-        for (int k = 0; k < kPU; ++k) {
-            const int q = q0 + k * kThreads;
-            cp[k] = q < npart ? part[q] : ColPartial{-1.0, INT32_MAX, 0, 0.0, 0.0};
-        }
+    for (int k = 0; k < kPU; ++k) {
+        const int q = tid + k * kThreads;
+        cp[k] = q < npart ? part[q] : ColPartial{-1.0, INT32_MAX, 0, 0.0, 0.0};
+    }
+    // row r of the panel's reflectors does not depend on the pivot: its loads
+    // go out now, behind the partials (so waiting for those does not wait
+    // for these)
+    double vr[kMaxNb];
 #pragma unroll
-        for (int k = 0; k < kPU; ++k) {
-            if (argmax_better(cp[k].best, cp[k].idx, best.v, best.i)) best = {cp[k].best, cp[k].idx};
-            sumsq += cp[k].sumsq;
-            nf |= cp[k].nonfinite;
-        }
+    for (int q = 0; q < kMaxNb; ++q) vr[q] = (active && q < i) ? (double)V[r + (int64_t)q * ldw] : 0.0;
+#pragma unroll
+    for (int k = 0; k < kPU; ++k) {
+        if (argmax_better(cp[k].best, cp[k].idx, best.v, best.i)) best = {cp[k].best, cp[k].idx};
+        sumsq += cp[k].sumsq;
+        nf |= cp[k].nonfinite;
+    }
+    for (int q = tid + kPU * kThreads; q < npart; q += kThreads) {  // more than kPU per thread: rare
+        const ColPartial cp = part[q];
+        if (argmax_better(cp.best, cp.idx, best.v, best.i)) best = {cp.best, cp.idx};
+        sumsq += cp.sumsq;
+        nf |= cp.nonfinite;
     }
     if (stop_in) return;
     best = wave_argmax(best);
@@ -261,29 +267,45 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
     const double spr = active ? (double)S[r + p * ldw] : 0.0;
     __syncthreads();
 
-    // a3: lazily updated pivot column u = S[:, p] - V F[p, :]^T (rows j..m-1)
-    double ur = spr;
+    // a3: lazily updated pivot column u = S[:, p] - V F[p, :]^T (rows j..m-1),
+    // the sum over the panel in four interleaved chains
+    double ua[4] = {spr, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < kMaxNb; ++q)
-        if (q < i) ur -= vr[q] * s_F[q];
+        if (q < i) ua[q & 3] -= vr[q] * s_F[q];
+    const double ur = (ua[0] + ua[1]) + (ua[2] + ua[3]);
     const T ut = (T)ur;
     // u[j] is kept apart (u[ldw]) so that u is zero at and above row j and the
     // GEMV can use it directly: v = e_j + scale * u.
     if (r < ldw) u[r] = (active && r != j) ? ut : T(0);
     if (r == j) u[ldw] = ut;
-    // a4 partial sums: sum_{r>j} u_r^2 and V[j+1:, q]^T u[j+1:]
+    // a4 partial sums over the chunk's rows: sum_{r>j} u_r^2 and
+    // V[j+1:, q]^T u[j+1:], q < i.  Each thread's i + 1 products go to a row
+    // of sP; 32-row slices of every column are then summed in parallel and
+    // the eight slice sums in a fixed order (no chain of i wave reductions).
     const double w = (active && r > j) ? (double)ut : 0.0;
-    const double s0 = wave_sum(w * w);
-    if (lane == 0) s_red[wave][0] = s0;
+    const int ncol = i + 1;
+    double* sP = reinterpret_cast<double*>(smem_raw);  // kThreads x (nb + 1)
+    const int ldp = nb + 1;
+    sP[tid * ldp] = w * w;
 #pragma unroll
-    for (int q = 0; q < kMaxNb; ++q) {
-        if (q < i) {
-            const double pq = wave_sum(vr[q] * w);
-            if (lane == 0) s_red[wave][1 + q] = pq;
-        }
+    for (int q = 0; q < kMaxNb; ++q)
+        if (q < i) sP[tid * ldp + 1 + q] = vr[q] * w;
+    __syncthreads();
+    for (int c = tid % 32; c < ncol; c += 32) {
+        const int h = tid / 32;  // slice of 32 rows
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int rr = 0; rr < 32; ++rr) a[rr & 3] += sP[(h * 32 + rr) * ldp + c];
+        s_red[h][c] = (a[0] + a[1]) + (a[2] + a[3]);
     }
     __syncthreads();
-    if (tid <= i) partA[(int64_t)blockIdx.x * kPartAStride + tid] = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
+    if (tid < ncol) {
+        double t = 0.0;
+#pragma unroll
+        for (int h = 0; h < kThreads / 32; ++h) t += s_red[h][tid];
+        partA[(int64_t)blockIdx.x * kPartAStride + tid] = t;
+    }
 
 }
 
@@ -1709,6 +1731,9 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
                                      512 * 33 * 8));
         MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      1024 * 17 * 8));
+        // and the pivot kernel's per-row products (kThreads x (nb + 1))
+        MIID_HIP(hipFuncSetAttribute((const void*)k_pivot_col<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     kThreads * (kMaxNb + 1) * 8));
         attr_done = true;
     }
 
@@ -1797,7 +1822,8 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
         const int jb = (j / nb) * nb;
         const int i = j - jb;
         int pr = prof_take(MIID_K_PIVOT, j, m - j, 1);
-        MIID_LAUNCH(pr, k_pivot_col<T>, dim3(P.NA), dim3(kThreads), 0, stream, S, ldw, m, V, F, nb, u, part,
+        MIID_LAUNCH(pr, k_pivot_col<T>, dim3(P.NA), dim3(kThreads), (size_t)kThreads * (nb + 1) * 8, stream, S, ldw, m,
+                    V, F, nb, u, part,
                     P.npart, partA, st, J, j, i, (int)P.tol, P.eps);
         pr = prof_take(MIID_K_GEMV, j, m - j, n - j);
         switch (P.cpw) {
