@@ -131,6 +131,15 @@ def omega_bf16(seed: int, l: int, m: int) -> np.ndarray:
     return np.asfortranarray(bf16_round(g.standard_normal((l, m))))
 
 
+def column_sample(seed: int, n: int, k: int, p: int | None = None) -> np.ndarray:
+    """The random column sample of the column-sampling randomized ID: p
+    distinct indices of range(n) drawn uniformly without replacement; p
+    defaults to the paper's k + floor(0.2 k).  int32, in draw order."""
+    if p is None:
+        p = k + int(0.2 * k)
+    return rng(seed).choice(n, size=p, replace=False).astype(np.int32)
+
+
 def bf16_bits(x_bf16_exact: np.ndarray) -> np.ndarray:
     """uint16 bit patterns of float32 values that are exact bfloat16."""
     f = np.asarray(x_bf16_exact, dtype=np.float32)

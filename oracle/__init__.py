@@ -113,7 +113,11 @@ def id(A: np.ndarray, k: int | None = None, eps: float | None = None, kmax: int 
     """
     A = np.asarray(A, dtype=np.float64)
     transposed = A.shape[0] > A.shape[1]
-    W = np.asfortranarray(A.T if transposed else A)
+    return _id_of(np.asfortranarray(A.T if transposed else A), transposed, k, eps, kmax, force)
+
+
+def _id_of(W: np.ndarray, transposed: bool, k, eps, kmax, force) -> IDResult:
+    """The column ID of W as given (m x n, any shape with k <= min(m, n))."""
     m, n = W.shape
     if (k is None) == (eps is None):
         raise ValueError("give exactly one of k or eps")
@@ -181,6 +185,28 @@ def rid(A: np.ndarray, Omega: np.ndarray, k: int) -> tuple[IDResult, np.ndarray]
     instead; this is the sketched variant whose CPQR stage is the same.)"""
     Y = matmul(np.asarray(Omega, dtype=np.float64), np.asarray(A, dtype=np.float64))
     return id(Y, k=k), Y
+
+
+def rid_sample(A: np.ndarray, idx: np.ndarray, k: int) -> tuple[np.ndarray, np.ndarray, IDResult]:
+    """The paper's randomized ID by column sampling (Section 2.2 and its
+    Optim RID listing), with the random sample ``idx`` (p distinct column
+    indices) an input: A_S = A[:, idx]; the column-pivoted QR of A_S,
+    truncated after k steps (Section 4.1), selects k of its columns (no
+    transpose, A_S is usually tall); cols = idx[selected], C = A[:, cols];
+    R_k is the leading k x k triangle of A_S's factor, and Z solves the
+    symmetric system R_k^T R_k Z = C^T A (eq. final_eq, over the full A),
+    here by numpy's LAPACK solve (the paper calls a symmetric-indefinite
+    solver; the solution is the same).  Returns (cols, Z, the ID result of
+    A_S)."""
+    A = np.asarray(A, dtype=np.float64)
+    idx = np.asarray(idx, dtype=np.int64)
+    AS = np.asfortranarray(A[:, idx])
+    res = _id_of(AS, False, k, None, None, None)
+    cols = idx[res.J]
+    Rk = res.R[:, res.J]          # R holds the rows in original order: R[:, J] = R11
+    C = np.asfortranarray(A[:, cols])
+    Z = np.linalg.solve(matmul(Rk.T, Rk), matmul(C.T, A))
+    return cols.astype(np.int32), Z, res
 
 
 def batched(blocks, eps: float) -> list[IDResult]:

@@ -325,6 +325,78 @@ def test_rid_exact_for_rank_k():
 
 
 # --------------------------------------------------------------------------
+# the paper's randomized ID by column sampling
+# --------------------------------------------------------------------------
+def test_rid_sample_full_sample_equals_id():
+    """Sampling every column (in order, or shuffled): the CPQR of A_S is the
+    CPQR of A up to a column relabelling, and the full-A least-squares Z is
+    the ID's [I T] P^T -- pins the sampled path (gather, column ID of A_S,
+    normal equations) against the deterministic ID."""
+    g = idgen.rng(41)
+    A = g.standard_normal((40, 120)) @ np.diag(0.9 ** np.arange(120))
+    ref = oracle.id(A, k=12)
+    for idx in (np.arange(120), g.permutation(120)):
+        cols, Z, _ = oracle.rid_sample(A, idx, 12)
+        assert list(cols) == list(ref.J)
+        assert np.abs(Z - ref.Z).max() <= 1e-9
+
+
+def test_rid_sample_normal_equations_and_identity():
+    """C^T (A - C Z) = 0 (Z is the least-squares solution over the full A),
+    Z[:, cols] = I, and the chosen columns come from the sample."""
+    g = idgen.rng(42)
+    A = g.standard_normal((80, 300)) @ np.diag(0.97 ** np.arange(300))
+    k = 20
+    idx = idgen.column_sample(43, 300, k)
+    assert len(idx) == 24 and len(set(idx)) == 24
+    cols, Z, res = oracle.rid_sample(A, idx, k)
+    assert set(cols) <= set(idx) and len(set(cols)) == k
+    C = A[:, cols]
+    assert np.linalg.norm(C.T @ (A - C @ Z)) <= 1e-9 * np.linalg.norm(C) * np.linalg.norm(A)
+    assert np.abs(Z[:, cols] - np.eye(k)).max() <= 1e-9
+    # the same Z as a library least-squares solve of min ||A - C Z||
+    assert np.abs(Z - np.linalg.lstsq(C, A, rcond=None)[0]).max() <= 1e-8
+
+
+def test_rid_sample_tall_sample_is_a_column_id():
+    """A_S (m x p, m > p) is factored as it is -- a column ID, not the dual
+    ID of its transpose -- and the pivots follow the greedy rule on A_S."""
+    g = idgen.rng(44)
+    A = g.standard_normal((100, 400)) @ np.diag(0.95 ** np.arange(400))
+    idx = idgen.column_sample(45, 400, 20)
+    cols, Z, res = oracle.rid_sample(A, idx, 20)
+    assert not res.transposed
+    AS = A[:, idx]
+    # step j's pivot has the largest residual norm after projecting out the
+    # previous pivots (the greedy rule written out with numpy's QR)
+    chosen = []
+    for j in range(20):
+        if chosen:
+            Q, _ = np.linalg.qr(AS[:, chosen])
+            Rr = AS - Q @ (Q.T @ AS)
+        else:
+            Rr = AS
+        nrm = np.linalg.norm(Rr, axis=0)
+        nrm[chosen] = -1.0
+        chosen.append(int(np.argmax(nrm)))
+    assert list(cols) == [int(idx[c]) for c in chosen]
+
+
+def test_rid_sample_planted_skeleton():
+    """A planted ID whose skeleton lies inside the sample: the sampled RID
+    finds the skeleton and the planted coefficients exactly."""
+    m, n, k = 50, 160, 8
+    A, planted, U, perm = idgen.planted_id(46, m, n, k, r=0.9)
+    g = idgen.rng(47)
+    others = g.choice(np.setdiff1d(np.arange(n), planted), size=4, replace=False)
+    idx = g.permutation(np.concatenate([planted, others])).astype(np.int32)
+    cols, Z, _ = oracle.rid_sample(A, idx, k)
+    assert sorted(cols) == sorted(planted)
+    assert list(cols) == list(planted)          # the pivot order too (steps separated by 1 - r)
+    assert np.abs(Z[:, perm[k:]] - U).max() <= 1e-10
+
+
+# --------------------------------------------------------------------------
 # derivative: finite differences, a dense least-squares reference, and
 # closed-form special cases
 # --------------------------------------------------------------------------
