@@ -133,10 +133,10 @@ def main() -> int:
                     help="build the 4096 x 16384 input with the numpy recipe on the host (no device QR; "
                          "for counter-collection runs)")
     ap.add_argument("--only", default="all",
-                    help="comma list of sections to run: id64,id32,rid,batched,bwd (default all); "
+                    help="comma list of sections to run: id64,id32,rid,ridsample,batched,bwd (default all); "
                          "the value is the FP64 ID, so id64 always runs")
     args = ap.parse_args()
-    only = set(args.only.split(",")) if args.only != "all" else {"id64", "id32", "rid", "batched", "bwd"}
+    only = set(args.only.split(",")) if args.only != "all" else {"id64", "id32", "rid", "ridsample", "batched", "bwd"}
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the ID hot path is built for a single MI355X "
               "(multi-GPU sharding is described in DESIGN.md, not implemented).", file=sys.stderr)
@@ -216,6 +216,25 @@ def main() -> int:
         if stp:
             extra["rid_cpqr_step_us"] = round(1000.0 * sum(r.ms for r in stp) / len(stp), 2)
         log(f"[bench] RID {ms_rid:.3f} ms")
+
+    if "ridsample" in only:
+        # the paper's randomized ID by column sampling (p = k + 0.2 k), FP64,
+        # Z by the normal equations over the full A
+        log("[bench] column-sampling RID (FP64, p = k + 0.2 k)")
+        idx = idgen.column_sample(12, n, k)
+        out_s = miid_api.rid_sample_raw(A64, idx, k)
+        for _ in range(args.warmup):
+            miid_api.rid_sample_raw(A64, idx, k, out=out_s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            miid_api.rid_sample_raw(A64, idx, k, out=out_s)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms_s = (t1 - t0) * 1000.0 / args.steps
+        extra["rid_sample_fp64_ms"] = round(ms_s, 4)
+        extra["rid_sample_speedup_vs_fp64_id"] = round(ms64 / ms_s, 2)
+        log(f"[bench] sampled RID {ms_s:.3f} ms")
 
     if "batched" in only:
         # batched IDs: 4096 kernel-matrix blocks, tolerance 1e-6, FP32, one launch

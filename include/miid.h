@@ -52,6 +52,8 @@ typedef enum { MIID_F32 = 0, MIID_F64 = 1 } miid_dtype;
 
 /* option flags */
 #define MIID_NO_REFINE 1u      /* skip the refinement step of the triangular solve */
+#define MIID_KEEP_COLUMNS 2u   /* id_cpqr: column ID even when m > n (no dual ID of A^T);
+                                  then k <= n is required                           */
 
 /* Tuning hints, 4-bit fields of miid_opts.flags (0 = library default).  They
  * change launch shapes only, never the arithmetic's definition; the
@@ -176,6 +178,40 @@ int rid_sketch_cpqr(const float *A, int64_t m, int64_t n, int64_t lda,
                     void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * The paper's randomized ID by column sampling (Section 2.2 and its Optim
+ * RID listing).  The column-pivoted QR of A_S = A[:, idx] (m x p: the p
+ * sampled columns; the paper samples p = k + floor(0.2 k) without
+ * replacement -- the sample is an input here) selects k of them, so
+ * J = idx[selected] and C = A_S P_k = A[:, J]; Z is the least-squares
+ * solution over the FULL A, R_k^T R_k Z = C^T A (eq. final_eq), R_k the
+ * leading k x k triangle of A_S's factor, solved as Z = R_k^{-1} R_k^{-T}
+ * (C^T A) in FP64 (C^T A on the matrix cores in the working precision).
+ * Z[:, J[c]] is set to the c-th unit vector exactly (Definition 1).
+ *
+ *  A     (1)  m x n, lda >= m, dtype, read only
+ *  idx   (6)  device int32[p]: the sampled column indices (distinct, in
+ *             [0, n); an index outside gives a zero column of A_S)
+ *  p     (7)  1 <= p <= n
+ *  opts  (8)  fixed rank only: k >= 1, k <= min(m, p, 1024); nb, flags as
+ *             for id_cpqr (MIID_KEEP_COLUMNS is implied, MIID_NO_REFINE has
+ *             no effect on the least-squares solve)
+ *  J     (9)  k int32; entries >= k_out are -1
+ *  Z     (10) k x n, ldz >= k, dtype, columns in original order; rows
+ *             >= k_out zero
+ *  R11   (12) nullable: R_k, k x k FP64, ldr >= k
+ *  C     (14) nullable: m x k, ldc >= m, dtype: A[:, J]
+ *  info  (16) device miid_info of the CPQR of A_S (a_norm, r22_norm refer to
+ *             A_S)
+ * ---------------------------------------------------------------------- */
+size_t miid_rid_sample_workspace(int64_t m, int64_t n, int32_t p, miid_dtype dtype,
+                                 const miid_opts *opts);
+int rid_sample_cpqr(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
+                    const int32_t *idx, int32_t p, const miid_opts *opts,
+                    int32_t *J, void *Z, int64_t ldz, double *R11, int64_t ldr,
+                    void *C, int64_t ldc, miid_info *info,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched tolerance-mode IDs of many independent small blocks (for instance
  * the off-diagonal blocks of a hierarchical kernel-matrix compression), in
  * one persistent launch.  Block b is m[b] x n[b] (column-major, leading
@@ -195,8 +231,7 @@ int rid_sketch_cpqr(const float *A, int64_t m, int64_t n, int64_t lda,
  * Limits: 1 <= m[b] <= 256, m[b] <= n[b] <= 1024, 1 <= kmax <= 64.  A block
  * outside them is skipped with k_out = 0 and status MIID_BLOCK_UNSUPPORTED;
  * the others are unaffected (likewise a block holding a NaN only gets its
- * own MIID_NONFINITE).  Blocks are processed largest first when
- * nblk <= 8192, in index order otherwise.
+ * own MIID_NONFINITE).  Blocks are processed largest first (by m n).
  * ---------------------------------------------------------------------- */
 size_t miid_batched_workspace(int32_t nblk, miid_dtype dtype);
 int id_batched(int32_t nblk, const void *A, const int64_t *a_off, const int32_t *m,

@@ -23,12 +23,14 @@ MIID_TRANSPOSED = 4
 MIID_KMAX_HIT = 8
 
 MIID_NO_REFINE = 1
+MIID_KEEP_COLUMNS = 2
 
 # every symbol declared in include/miid.h
 EXPORTED = [
     "miid_version", "miid_last_hip_error",
     "miid_id_workspace", "id_cpqr",
     "miid_rid_workspace", "rid_sketch_cpqr",
+    "miid_rid_sample_workspace", "rid_sample_cpqr",
     "miid_batched_workspace", "id_batched",
     "miid_backward_workspace", "id_backward",
 ]
@@ -82,6 +84,11 @@ def load(path: str = LIB_PATH):
     lib.miid_id_workspace.argtypes = [I64, I64, ctypes.c_int, OPTS]
     lib.id_cpqr.restype = ctypes.c_int
     lib.id_cpqr.argtypes = [P, I64, I64, I64, ctypes.c_int, OPTS, P, P, I64, P, I64, P, I64, P, P, SZ, P]
+    lib.miid_rid_sample_workspace.restype = SZ
+    lib.miid_rid_sample_workspace.argtypes = [I64, I64, I32, ctypes.c_int, OPTS]
+    lib.rid_sample_cpqr.restype = ctypes.c_int
+    lib.rid_sample_cpqr.argtypes = [P, I64, I64, I64, ctypes.c_int, P, I32, OPTS, P, P, I64, P, I64, P, I64, P, P,
+                                    SZ, P]
     if hasattr(lib, "rid_sketch_cpqr"):
         lib.miid_rid_workspace.restype = SZ
         lib.miid_rid_workspace.argtypes = [I64, I64, I32, OPTS]

@@ -158,6 +158,52 @@ def id(A: torch.Tensor, k: int | None = None, eps: float | None = None, kmax: in
     return _finish(out)
 
 
+def rid_sample_raw(A: torch.Tensor, idx, k: int, nb: int = 0, want_C: bool = True, want_R11: bool = False,
+                   out: dict | None = None, hints: int = 0):
+    """Enqueue rid_sample_cpqr without synchronising (see :func:`rid_sample`)."""
+    lib = _abi.load()
+    if A.dtype not in _DT or not A.is_cuda:
+        raise TypeError("A must be a float32/float64 CUDA tensor")
+    A = colmajor(A)
+    m, n = A.shape
+    idx_t = torch.as_tensor(idx, dtype=torch.int32, device=A.device).contiguous()
+    p = int(idx_t.numel())
+    opts = _opts(k, None, k, nb, True, hints)
+    dt = _DT[A.dtype]
+    ws_bytes = lib.miid_rid_sample_workspace(m, n, p, dt, ctypes.byref(opts))
+    if ws_bytes == 0:
+        _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_rid_sample_workspace")
+    ws = _WS.get("rid_sample", ws_bytes, A.device)
+    dev = A.device
+    if out is None:
+        out = {
+            "J": torch.empty(k, dtype=torch.int32, device=dev),
+            "Z": empty_colmajor(k, n, A.dtype, dev),
+            "C": empty_colmajor(m, k, A.dtype, dev) if want_C else None,
+            "R11": empty_colmajor(k, k, torch.float64, dev) if want_R11 else None,
+            "info": torch.empty(ctypes.sizeof(_abi.MiidInfo), dtype=torch.uint8, device=dev),
+        }
+    out["idx"] = idx_t
+    Z, C, R11 = out["Z"], out["C"], out["R11"]
+    rc = lib.rid_sample_cpqr(_ptr(A), m, n, _ld(A), dt, _ptr(idx_t), p, ctypes.byref(opts), _ptr(out["J"]),
+                             _ptr(Z), _ld(Z), _ptr(R11), _ld(R11) if R11 is not None else 1, _ptr(C),
+                             _ld(C) if C is not None else 1, _ptr(out["info"]), _ptr(ws), ws_bytes, _stream())
+    _abi.check(rc, "rid_sample_cpqr")
+    return out
+
+
+def rid_sample(A: torch.Tensor, idx, k: int, nb: int = 0, want_C: bool = True, want_R11: bool = False,
+               hints: int = 0) -> IDResult:
+    """The paper's randomized ID by column sampling (its Optim RID): the
+    column-pivoted QR of A[:, idx] picks k of the sampled columns
+    (J = idx[selected], C = A[:, J]) and Z solves R_k^T R_k Z = C^T A over the
+    full A.  ``idx`` holds the sample (the paper draws p = k + floor(0.2 k)
+    distinct columns; the random numbers are an input).  ``a_norm`` and
+    ``r22_norm`` of the result refer to A[:, idx]."""
+    out = rid_sample_raw(A, idx, k, nb=nb, want_C=want_C, want_R11=want_R11, hints=hints)
+    return _finish(out)
+
+
 def rid_raw(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: float | None = None,
             kmax: int | None = None, mode: int = 1, nb: int = 0, refine: bool = True, want_C: bool = True,
             want_Y: bool = False, want_R11: bool = False, out: dict | None = None, hints: int = 0):

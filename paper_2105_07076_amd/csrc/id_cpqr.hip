@@ -1070,7 +1070,11 @@ __global__ void __launch_bounds__(kTB) k_trsm_dinv(const double* __restrict__ R1
 // B operand lane l = X[k l / 16][col l % 16] (LDS), output element e of
 // lane l = row l / 16 + 4 e, column l % 16.
 // Z[:, J[c]] = e_c exactly; rows >= K are zero.
-template <typename T, int NC>
+// SEMI: the right-hand sides are first replaced by R11^{-T} B with the same
+// machinery read transposed (top-down over the row blocks, the transposed
+// diagonal-block inverses), so that Z = R11^{-1} R11^{-T} B -- the solution of
+// R11^T R11 Z = B (no refinement sweep in this form).
+template <typename T, int NC, bool SEMI = false>
 __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, int64_t n,
                                                      const double* __restrict__ R11s, int kpad,
                                                      const double* __restrict__ Dinv,
@@ -1107,7 +1111,41 @@ __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, in
         }
     }
     __syncthreads();
-    for (int sweep = 0; sweep < (refine ? 2 : 1); ++sweep) {
+    if (SEMI) {
+        // Y = R11^{-T} B: for row block b top-down, T = B_b - sum_{c < b}
+        // R11[c, b]^T Y_c, Y_b = (D_b^{-1})^T T
+        for (int b = 0; b < nbk; ++b) {
+            const int r0 = b * kTB;
+            d4_t acc;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = sX[(r0 + tr + lq + 4 * e) * NCP + tc + l16];
+            const double* Db = Dinv + (int64_t)b * kTB * kTB;
+            const double* ap = R11s + lq + (int64_t)(r0 + tr + l16) * kpad;  // R11[k][row] = (R11^T)[row][k]
+            for (int k0 = 0; k0 < r0; k0 += kTB) {
+                double av[kTB / 4], xv[kTB / 4];
+#pragma unroll
+                for (int q = 0; q < kTB / 4; ++q) av[q] = ap[k0 + 4 * q];
+#pragma unroll
+                for (int q = 0; q < kTB / 4; ++q) xv[q] = sX[(k0 + 4 * q + lq) * NCP + tc + l16];
+#pragma unroll
+                for (int q = 0; q < kTB / 4; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[q], xv[q], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) sT[tr + lq + 4 * e][tc + l16] = acc[e];
+            __syncthreads();
+            d4_t out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k0 = 0; k0 < kTB; k0 += 4) {
+                const double av = Db[(k0 + lq) + (tr + l16) * kTB];  // (D_b^{-1})^T
+                const double xv = sT[k0 + lq][tc + l16];
+                out = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xv, out, 0, 0, 0);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) sX[(r0 + tr + lq + 4 * e) * NCP + tc + l16] = out[e];
+            __syncthreads();
+        }
+    }
+    for (int sweep = 0; sweep < (refine && !SEMI ? 2 : 1); ++sweep) {
         for (int b = nbk - 1; b >= 0; --b) {
             const int r0 = b * kTB;
             d4_t acc;
@@ -1529,7 +1567,7 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
     if (!o || o->k < 0 || (o->k == 0 && (o->kmax < 1 || !(o->eps >= 0.0))) || o->nb < 0) return -6;
     P->M = M;
     P->N = N;
-    P->trans = M > N;
+    P->trans = M > N && !(o->flags & MIID_KEEP_COLUMNS);
     P->m = P->trans ? N : M;
     P->n = P->trans ? M : N;
     P->tol = o->k == 0;
@@ -1539,7 +1577,7 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
     // below once the path is known)
     P->nb = o->nb != 0 ? o->nb : 32;
     P->refine = !(o->flags & MIID_NO_REFINE);
-    if (P->nb > kMaxNb || P->kmax > P->m || P->kmax > kMaxK) return MIID_E_UNSUPPORTED;
+    if (P->nb > kMaxNb || P->kmax > P->m || P->kmax > P->n || P->kmax > kMaxK) return MIID_E_UNSUPPORTED;
     P->esz = dtype == MIID_F64 ? 8 : 4;
     P->ldw = (int64_t)align_up((size_t)P->m, 64);
     if ((size_t)P->ldw * P->esz > kMaxVecLds) return MIID_E_UNSUPPORTED;
@@ -1731,6 +1769,12 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
                                      512 * 33 * 8));
         MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      1024 * 17 * 8));
+        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 64, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     256 * 65 * 8));
+        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 32, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     512 * 33 * 8));
+        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 16, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     1024 * 17 * 8));
         // and the pivot kernel's per-row products (kThreads x (nb + 1))
         MIID_HIP(hipFuncSetAttribute((const void*)k_pivot_col<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      kThreads * (kMaxNb + 1) * 8));
@@ -1898,6 +1942,186 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// The paper's randomized ID by column sampling (Section 2.2, the Optim RID
+// listing): CPQR of A_S = A[:, idx] (m x p) for J, then Z from
+// R_k^T R_k Z = C^T A over the full A (eq. final_eq).
+// ---------------------------------------------------------------------------
+
+// A_S[:, c] = A[:, idx[c]] (an index outside [0, n) gives a zero column)
+template <typename T>
+__global__ void k_gather_cols(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                              const int32_t* __restrict__ idx, T* __restrict__ As) {
+    const int c = blockIdx.y;
+    const int64_t src = idx[c];
+    const bool ok = src >= 0 && src < n;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x)
+        As[r + (int64_t)c * m] = ok ? A[r + src * lda] : T(0);
+}
+
+// J[i] = idx[J_S[i]]; sel[J[i]] = i (sel was filled with -1)
+__global__ void k_map_idx(const int32_t* __restrict__ Js, const int32_t* __restrict__ idx, int k, int64_t n,
+                          int32_t* __restrict__ J, int32_t* __restrict__ sel) {
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        const int s = Js[i];
+        const int32_t g = s >= 0 ? idx[s] : -1;
+        J[i] = g;
+        if (g >= 0 && g < n) sel[g] = i;
+    }
+}
+
+// G (k x n, row-major: G[i n + l]) = C^T A, C m x k (ldc), A m x n (lda),
+// on the matrix cores: 64 x 64 output tile per workgroup, 32 x 32 per wave
+// (2 x 2 blocks of 16 x 16), K = m in steps of 4, the operands of eight
+// steps in flight at a time.  Operand lane l: C^T[row l % 16][k l / 16]
+// (= C[k][row], contiguous in k) and A[k l / 16][column l % 16].
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gemm_tn(const T* __restrict__ C, int64_t ldc, const T* __restrict__ A,
+                                                      int64_t lda, int64_t m, int k, int64_t n, T* __restrict__ G) {
+    using A4 = typename Acc4<T>::type;
+    const int i0 = blockIdx.x * 64;  // rows of G
+    const int64_t j0 = (int64_t)blockIdx.y * 64;
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
+    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    const int l16 = lane % 16, lg = lane / 16;
+    A4 acc[2][2];
+#pragma unroll
+    for (int br = 0; br < 2; ++br)
+#pragma unroll
+        for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[br][bc][e] = T(0);
+    const T* cp[2];
+    const T* ap[2];
+    bool rok[2], cok[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int row = i0 + wr + h * 16 + l16;
+        const int64_t col = j0 + wc + h * 16 + l16;
+        rok[h] = row < k;
+        cok[h] = col < n;
+        cp[h] = C + (int64_t)(rok[h] ? row : 0) * ldc;
+        ap[h] = A + (cok[h] ? col : 0) * lda;
+    }
+    constexpr int U = 8;  // K steps of 4 per batch of loads
+    int64_t k0 = 0;
+    for (; k0 + 4 * U <= m; k0 += 4 * U) {
+        T a[U][2], b[U][2];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t kk = k0 + 4 * u + lg;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                a[u][h] = rok[h] ? cp[h][kk] : T(0);
+                b[u][h] = cok[h] ? ap[h][kk] : T(0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int br = 0; br < 2; ++br)
+#pragma unroll
+                for (int bc = 0; bc < 2; ++bc) acc[br][bc] = mfma16x16x4(a[u][br], b[u][bc], acc[br][bc]);
+    }
+    for (; k0 < m; k0 += 4) {  // the ragged end of K
+        const int64_t kk = k0 + lg;
+        T a[2], b[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            a[h] = (rok[h] && kk < m) ? cp[h][kk] : T(0);
+            b[h] = (cok[h] && kk < m) ? ap[h][kk] : T(0);
+        }
+#pragma unroll
+        for (int br = 0; br < 2; ++br)
+#pragma unroll
+            for (int bc = 0; bc < 2; ++bc) acc[br][bc] = mfma16x16x4(a[br], b[bc], acc[br][bc]);
+    }
+    // output element e of lane l: row Acc4::row(l / 16, e), column l % 16
+#pragma unroll
+    for (int br = 0; br < 2; ++br)
+#pragma unroll
+        for (int bc = 0; bc < 2; ++bc)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = i0 + wr + br * 16 + Acc4<T>::row(lg, e);
+                const int64_t col = j0 + wc + bc * 16 + l16;
+                if (row < k && col < n) G[(int64_t)row * n + col] = acc[br][bc][e];
+            }
+}
+
+struct RsPlan {
+    IdPlan id;  // the CPQR of A_S (its workspace comes first)
+    size_t oAs, oZs, oJs, oC, oG, oSel, total;
+};
+
+static int rs_plan(int64_t m, int64_t n, int32_t p, miid_dtype dtype, const miid_opts* o, RsPlan* Q) {
+    if (p < 1 || p > n) return -7;
+    if (!o || o->k < 1) return -8;  // fixed rank only
+    miid_opts oo = *o;
+    oo.flags |= MIID_KEEP_COLUMNS;
+    const int rc = make_plan(m, p, dtype, &oo, &Q->id);
+    if (rc != 0) return rc == -3 ? -7 : (rc == -6 ? -8 : rc);
+    const size_t esz = dtype == MIID_F64 ? 8 : 4;
+    const int k = Q->id.kmax;
+    size_t off = Q->id.total;
+    auto take = [&](size_t bytes) {
+        const size_t o2 = off;
+        off = align_up(off + bytes, 256);
+        return o2;
+    };
+    Q->oAs = take((size_t)m * p * esz);
+    Q->oZs = take((size_t)k * p * esz);
+    Q->oJs = take((size_t)k * 4);
+    Q->oC = take((size_t)m * k * esz);
+    Q->oG = take((size_t)k * n * esz);
+    Q->oSel = take((size_t)n * 4);
+    Q->total = off;
+    return 0;
+}
+
+template <typename T>
+static int run_rid_sample(const RsPlan& Q, const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* idx, int p,
+                          int32_t* J, T* Z, int64_t ldz, double* R11, int64_t ldr, T* C, int64_t ldc,
+                          miid_info* info, unsigned char* w, hipStream_t s) {
+    const IdPlan& P = Q.id;
+    const int k = P.kmax;
+    T* As = reinterpret_cast<T*>(w + Q.oAs);
+    T* Zs = reinterpret_cast<T*>(w + Q.oZs);
+    int32_t* Js = reinterpret_cast<int32_t*>(w + Q.oJs);
+    T* Cx = C ? C : reinterpret_cast<T*>(w + Q.oC);
+    const int64_t ldcx = C ? ldc : m;
+    T* G = reinterpret_cast<T*>(w + Q.oG);
+    int32_t* sel = reinterpret_cast<int32_t*>(w + Q.oSel);
+    hipLaunchKernelGGL(k_gather_cols<T>, dim3((unsigned)std::min<int64_t>((m + 255) / 256, 64), (unsigned)p), dim3(256),
+                       0, s, A, lda, m, n, idx, As);
+    // the CPQR of A_S (its own column ID, no transpose): J_S, R_k (also
+    // left, padded, with its diagonal-block inverses, in the CPQR's
+    // workspace), C = A_S[:, J_S], info
+    const int rc = run_id<T>(P, As, m, Js, Zs, k, R11, ldr, Cx, ldcx, info, w, s, false, As, m, m);
+    if (rc != 0) return rc;
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, s, sel, n,
+                       (int32_t)-1);
+    hipLaunchKernelGGL(k_map_idx, dim3(1), dim3(256), 0, s, Js, idx, k, n, J, sel);
+    // C^T A, then Z = R_k^{-1} R_k^{-T} (C^T A) with Z[:, J] = I
+    hipLaunchKernelGGL(k_gemm_tn<T>, dim3((unsigned)((k + 63) / 64), (unsigned)((n + 63) / 64)), dim3(kThreads), 0, s, Cx,
+                       ldcx, A, lda, m, k, n, G);
+    const double* R11s = reinterpret_cast<const double*>(w + P.oR11);
+    const double* Dinv = reinterpret_cast<const double*>(w + P.oDinv);
+    const DevState* st = reinterpret_cast<const DevState*>(w + P.ostate);
+    if (P.kpad <= 256)
+        hipLaunchKernelGGL((k_trsm_blk<T, 64, true>), dim3((unsigned)((n + 63) / 64)), dim3(8 * 64),
+                           (size_t)P.kpad * 65 * 8, s, G, n, R11s, P.kpad, Dinv, st, k, sel, Z, ldz, k, 0);
+    else if (P.kpad <= 512)
+        hipLaunchKernelGGL((k_trsm_blk<T, 32, true>), dim3((unsigned)((n + 31) / 32)), dim3(8 * 32),
+                           (size_t)P.kpad * 33 * 8, s, G, n, R11s, P.kpad, Dinv, st, k, sel, Z, ldz, k, 0);
+    else
+        hipLaunchKernelGGL((k_trsm_blk<T, 16, true>), dim3((unsigned)((n + 15) / 16)), dim3(8 * 16),
+                           (size_t)P.kpad * 17 * 8, s, G, n, R11s, P.kpad, Dinv, st, k, sel, Z, ldz, k, 0);
+    MIID_HIP(hipGetLastError());
+    return 0;
+}
+
 template int run_id<float>(const IdPlan&, const float*, int64_t, int32_t*, float*, int64_t, double*, int64_t, float*,
                            int64_t, miid_info*, unsigned char*, hipStream_t, bool, const float*, int64_t, int64_t);
 template int run_id<double>(const IdPlan&, const double*, int64_t, int32_t*, double*, int64_t, double*, int64_t,
@@ -1909,6 +2133,42 @@ template int run_id<double>(const IdPlan&, const double*, int64_t, int32_t*, dou
 using namespace miid;
 
 extern "C" {
+
+size_t miid_rid_sample_workspace(int64_t m, int64_t n, int32_t p, miid_dtype dtype, const miid_opts* opts) {
+    RsPlan Q;
+    if (m < 1 || n < 1 || rs_plan(m, n, p, dtype, opts, &Q) != 0) return 0;
+    return Q.total;
+}
+
+int rid_sample_cpqr(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const int32_t* idx, int32_t p,
+                    const miid_opts* opts, int32_t* J, void* Z, int64_t ldz, double* R11, int64_t ldr, void* C,
+                    int64_t ldc, miid_info* info, void* ws, size_t ws_bytes, void* stream) {
+    if (!A) return -1;
+    if (m < 1) return -2;
+    if (n < 1) return -3;
+    if (lda < m) return -4;
+    if (dtype != MIID_F32 && dtype != MIID_F64) return -5;
+    if (!idx) return -6;
+    RsPlan Q;
+    const int rc = rs_plan(m, n, p, dtype, opts, &Q);
+    if (rc != 0) return rc;
+    const int k = Q.id.kmax;
+    if (!J) return -9;
+    if (!Z) return -10;
+    if (ldz < k) return -11;
+    if (R11 && ldr < k) return -13;
+    if (C && ldc < m) return -15;
+    if (!info) return -16;
+    if (!ws) return -17;
+    if (ws_bytes < Q.total) return MIID_E_WORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+    if (dtype == MIID_F64)
+        return run_rid_sample<double>(Q, (const double*)A, m, n, lda, idx, p, J, (double*)Z, ldz, R11, ldr, (double*)C,
+                                      ldc, info, w, s);
+    return run_rid_sample<float>(Q, (const float*)A, m, n, lda, idx, p, J, (float*)Z, ldz, R11, ldr, (float*)C, ldc,
+                                 info, w, s);
+}
 
 size_t miid_id_workspace(int64_t m, int64_t n, miid_dtype dtype, const miid_opts* opts) {
     IdPlan P;
