@@ -1971,81 +1971,95 @@ __global__ void k_map_idx(const int32_t* __restrict__ Js, const int32_t* __restr
 }
 
 // G (k x n, row-major: G[i n + l]) = C^T A, C m x k (ldc), A m x n (lda),
-// on the matrix cores: 64 x 64 output tile per workgroup, 32 x 32 per wave
-// (2 x 2 blocks of 16 x 16), K = m in steps of 4, the operands of eight
-// steps in flight at a time.  Operand lane l: C^T[row l % 16][k l / 16]
+// on the matrix cores.  Workgroup tile 128 x 128, wave tile 64 x 64 (4 x 4
+// blocks of 16 x 16: sixteen products per eight operand loads), K = m in
+// steps of 4; the operands of the next U steps are loaded while the current
+// U steps are multiplied.  Operand lane l: C^T[row l % 16][k l / 16]
 // (= C[k][row], contiguous in k) and A[k l / 16][column l % 16].
+constexpr int kGtB = 4;  // 16 x 16 blocks per wave side
+constexpr int kGtU = 4;  // K steps (of 4) per batch of loads
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_gemm_tn(const T* __restrict__ C, int64_t ldc, const T* __restrict__ A,
                                                       int64_t lda, int64_t m, int k, int64_t n, T* __restrict__ G) {
     using A4 = typename Acc4<T>::type;
-    const int i0 = blockIdx.x * 64;  // rows of G
-    const int64_t j0 = (int64_t)blockIdx.y * 64;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
-    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    const int i0 = blockIdx.x * 128 + (wave & 1) * 64;               // this wave's rows of G
+    const int64_t j0 = (int64_t)blockIdx.y * 128 + (wave >> 1) * 64;  // and columns
     const int l16 = lane % 16, lg = lane / 16;
-    A4 acc[2][2];
+    A4 acc[kGtB][kGtB];
 #pragma unroll
-    for (int br = 0; br < 2; ++br)
+    for (int br = 0; br < kGtB; ++br)
 #pragma unroll
-        for (int bc = 0; bc < 2; ++bc)
+        for (int bc = 0; bc < kGtB; ++bc)
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc[br][bc][e] = T(0);
-    const T* cp[2];
-    const T* ap[2];
-    bool rok[2], cok[2];
+    const T* cp[kGtB];
+    const T* ap[kGtB];
+    bool rok[kGtB], cok[kGtB];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int row = i0 + wr + h * 16 + l16;
-        const int64_t col = j0 + wc + h * 16 + l16;
+    for (int h = 0; h < kGtB; ++h) {
+        const int row = i0 + h * 16 + l16;
+        const int64_t col = j0 + h * 16 + l16;
         rok[h] = row < k;
         cok[h] = col < n;
-        cp[h] = C + (int64_t)(rok[h] ? row : 0) * ldc;
-        ap[h] = A + (cok[h] ? col : 0) * lda;
+        cp[h] = C + (int64_t)(rok[h] ? row : 0) * ldc + lg;
+        ap[h] = A + (cok[h] ? col : 0) * lda + lg;
     }
-    constexpr int U = 8;  // K steps of 4 per batch of loads
-    int64_t k0 = 0;
-    for (; k0 + 4 * U <= m; k0 += 4 * U) {
-        T a[U][2], b[U][2];
+    auto load = [&](int64_t k0, T (&a)[kGtU][kGtB], T (&b)[kGtU][kGtB]) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t kk = k0 + 4 * u + lg;
+        for (int u = 0; u < kGtU; ++u)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                a[u][h] = rok[h] ? cp[h][kk] : T(0);
-                b[u][h] = cok[h] ? ap[h][kk] : T(0);
+            for (int h = 0; h < kGtB; ++h) {
+                a[u][h] = rok[h] ? cp[h][k0 + 4 * u] : T(0);
+                b[u][h] = cok[h] ? ap[h][k0 + 4 * u] : T(0);
             }
+    };
+    auto mul = [&](const T (&a)[kGtU][kGtB], const T (&b)[kGtU][kGtB]) {
+#pragma unroll
+        for (int u = 0; u < kGtU; ++u)
+#pragma unroll
+            for (int br = 0; br < kGtB; ++br)
+#pragma unroll
+                for (int bc = 0; bc < kGtB; ++bc) acc[br][bc] = mfma16x16x4(a[u][br], b[u][bc], acc[br][bc]);
+    };
+    constexpr int KB = 4 * kGtU;  // K per batch
+    const int64_t kfull = m / KB * KB;
+    if (kfull > 0) {
+        T a0[kGtU][kGtB], b0[kGtU][kGtB], a1[kGtU][kGtB], b1[kGtU][kGtB];
+        load(0, a0, b0);
+        int64_t k0 = 0;
+        for (; k0 + 2 * KB <= kfull; k0 += 2 * KB) {
+            load(k0 + KB, a1, b1);
+            mul(a0, b0);
+            if (k0 + 2 * KB < kfull) load(k0 + 2 * KB, a0, b0);
+            mul(a1, b1);
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int br = 0; br < 2; ++br)
-#pragma unroll
-                for (int bc = 0; bc < 2; ++bc) acc[br][bc] = mfma16x16x4(a[u][br], b[u][bc], acc[br][bc]);
+        if (k0 < kfull) mul(a0, b0);  // an odd number of batches: the last one is in a0
     }
-    for (; k0 < m; k0 += 4) {  // the ragged end of K
+    for (int64_t k0 = kfull; k0 < m; k0 += 4) {  // the ragged end of K
         const int64_t kk = k0 + lg;
-        T a[2], b[2];
+        T a[kGtB], b[kGtB];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            a[h] = (rok[h] && kk < m) ? cp[h][kk] : T(0);
-            b[h] = (cok[h] && kk < m) ? ap[h][kk] : T(0);
+        for (int h = 0; h < kGtB; ++h) {
+            a[h] = (rok[h] && kk < m) ? cp[h][k0] : T(0);
+            b[h] = (cok[h] && kk < m) ? ap[h][k0] : T(0);
         }
 #pragma unroll
-        for (int br = 0; br < 2; ++br)
+        for (int br = 0; br < kGtB; ++br)
 #pragma unroll
-            for (int bc = 0; bc < 2; ++bc) acc[br][bc] = mfma16x16x4(a[br], b[bc], acc[br][bc]);
+            for (int bc = 0; bc < kGtB; ++bc) acc[br][bc] = mfma16x16x4(a[br], b[bc], acc[br][bc]);
     }
     // output element e of lane l: row Acc4::row(l / 16, e), column l % 16
 #pragma unroll
-    for (int br = 0; br < 2; ++br)
+    for (int br = 0; br < kGtB; ++br)
 #pragma unroll
-        for (int bc = 0; bc < 2; ++bc)
+        for (int bc = 0; bc < kGtB; ++bc)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = i0 + wr + br * 16 + Acc4<T>::row(lg, e);
-                const int64_t col = j0 + wc + bc * 16 + l16;
+                const int row = i0 + br * 16 + Acc4<T>::row(lg, e);
+                const int64_t col = j0 + bc * 16 + l16;
                 if (row < k && col < n) G[(int64_t)row * n + col] = acc[br][bc][e];
             }
 }
@@ -2104,8 +2118,8 @@ static int run_rid_sample(const RsPlan& Q, const T* A, int64_t m, int64_t n, int
                        (int32_t)-1);
     hipLaunchKernelGGL(k_map_idx, dim3(1), dim3(256), 0, s, Js, idx, k, n, J, sel);
     // C^T A, then Z = R_k^{-1} R_k^{-T} (C^T A) with Z[:, J] = I
-    hipLaunchKernelGGL(k_gemm_tn<T>, dim3((unsigned)((k + 63) / 64), (unsigned)((n + 63) / 64)), dim3(kThreads), 0, s, Cx,
-                       ldcx, A, lda, m, k, n, G);
+    hipLaunchKernelGGL(k_gemm_tn<T>, dim3((unsigned)((k + 127) / 128), (unsigned)((n + 127) / 128)), dim3(kThreads), 0, s,
+                       Cx, ldcx, A, lda, m, k, n, G);
     const double* R11s = reinterpret_cast<const double*>(w + P.oR11);
     const double* Dinv = reinterpret_cast<const double*>(w + P.oDinv);
     const DevState* st = reinterpret_cast<const DevState*>(w + P.ostate);
