@@ -1977,7 +1977,7 @@ __global__ void k_map_idx(const int32_t* __restrict__ Js, const int32_t* __restr
 // U steps are multiplied.  Operand lane l: C^T[row l % 16][k l / 16]
 // (= C[k][row], contiguous in k) and A[k l / 16][column l % 16].
 constexpr int kGtB = 4;  // 16 x 16 blocks per wave side
-constexpr int kGtU = 4;  // K steps (of 4) per batch of loads
+constexpr int kGtU = 4;  // K steps (of 4) per batch of loads (2: the same, 8: slower)
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_gemm_tn(const T* __restrict__ C, int64_t ldc, const T* __restrict__ A,
