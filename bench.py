@@ -83,9 +83,9 @@ def time_id(miid_api, lib, A, k, steps, warmup, sample_every=7):
 # passes (scaled against a copy kernel of known size), valid only for the
 # kernel sources they were taken on.
 GEMV_TRAFFIC = {
-    "bytes_per_launch": 532.0e6,
+    "bytes_per_launch": 532.1e6,
     "sources": {
-        "paper_2105_07076_amd/csrc/id_cpqr.hip": "a2458d42e37c13d7018456a03521dc437bcd4ad1c17f99d93fdb93f97c779bb3",
+        "paper_2105_07076_amd/csrc/id_cpqr.hip": "2dfd0c3561d0a6a36af218de640d08e523754dfe32b0a978e15de5d61198570f",
         "paper_2105_07076_amd/csrc/common.hpp": "77e3f522d4607da471046f7b4d08b5688ce5617e1b620ace976254481bb74ae8",
         "paper_2105_07076_amd/csrc/cpqr.hpp": "e002806934b941a7b8c686698d55d3e93423adffd1eefd46e79fcbc23b7204ff",
     },
