@@ -61,42 +61,10 @@ __global__ void k_bw_gather(const T* __restrict__ A, int64_t lda, int64_t m, con
         C[r + (int64_t)q * m] = A[r + src * lda];
 }
 
-// M[:, cols] = R11^{-1} R11^{-T} Gz[:, cols] in FP64 for 16 columns per
-// workgroup (Gz = gZ with the J columns zeroed); thread (g, c) owns column c
-// and rows g, g + 16, ...  Right-looking substitution, one barrier per row.
 template <typename T>
-__global__ void __launch_bounds__(kBwThreads) k_bw_solve(const T* __restrict__ gZ, int64_t ldgz, int64_t n, int k,
-                                                         const double* __restrict__ R11, int64_t ldr,
-                                                         const int32_t* __restrict__ sel, T* __restrict__ M) {
-    constexpr int NC = 16, G = kBwThreads / NC;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* w = reinterpret_cast<double*>(smem_raw);  // [k][NC]
-    const int c = threadIdx.x % NC, g = threadIdx.x / NC;
-    const int64_t col = (int64_t)blockIdx.x * NC + c;
-    const bool live = col < n && (gZ != nullptr) && sel[col < n ? col : 0] < 0;
-    for (int q = g; q < k; q += G) w[q * NC + c] = live ? (double)gZ[q + col * ldgz] : 0.0;
-    __syncthreads();
-    // forward: R11^T y = Gz  (row t of R11 is column t of R11^T)
-    for (int t = 0; t < k; ++t) {
-        if (g == t % G) w[t * NC + c] /= R11[t + (int64_t)t * ldr];
-        __syncthreads();
-        const double yt = w[t * NC + c];
-        for (int q = t + 1 + ((g - (t + 1)) % G + G) % G; q < k; q += G) w[q * NC + c] -= R11[t + (int64_t)q * ldr] * yt;
-        __syncthreads();
-    }
-    // backward: R11 x = y
-    for (int t = k - 1; t >= 0; --t) {
-        if (g == t % G) w[t * NC + c] /= R11[t + (int64_t)t * ldr];
-        __syncthreads();
-        const double xt = w[t * NC + c];
-        for (int q = g; q < t; q += G) w[q * NC + c] -= R11[q + (int64_t)t * ldr] * xt;
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < k * NC; e += kBwThreads) {
-        const int q = e % k, cc = e / k;
-        const int64_t cl = (int64_t)blockIdx.x * NC + cc;
-        if (cl < n) M[q + cl * k] = (T)w[q * NC + cc];
-    }
+__global__ void k_bw_zero(T* __restrict__ p, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = T(0);
 }
 
 // OUT (rows x cols, ldo) = X (rows x K, ldx) * Y (K x cols, ldy), K small.
@@ -231,7 +199,7 @@ __global__ void k_bw_jcols(const T* __restrict__ C, const T* __restrict__ P, con
 
 struct BwPlan {
     int nz;
-    size_t oSel, oC, oM, oPart, oP, oQ, total;
+    size_t oSel, oC, oM, oPart, oP, oQ, oSemi, total;
 };
 
 static BwPlan bw_plan(int64_t m, int64_t n, int32_t k, size_t esz) {
@@ -250,6 +218,7 @@ static BwPlan bw_plan(int64_t m, int64_t n, int32_t k, size_t esz) {
     B.oPart = take(part_elems * esz);
     B.oP = take((size_t)m * k * esz);
     B.oQ = take((size_t)k * k * esz);
+    B.oSemi = take(semi_solve_workspace(k));
     B.total = off;
     return B;
 }
@@ -264,18 +233,21 @@ static int run_bw(const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* 
     T* part = reinterpret_cast<T*>(ws + B.oPart);
     T* P = reinterpret_cast<T*>(ws + B.oP);
     T* Q = reinterpret_cast<T*>(ws + B.oQ);
-    static bool attr = false;
-    if (!attr) {
-        MIID_HIP(hipFuncSetAttribute((const void*)k_bw_solve<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
-        attr = true;
-    }
     hipLaunchKernelGGL(k_bw_sel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, s, J, k, n,
                        sel);
     hipLaunchKernelGGL(k_bw_sel2, dim3((k + 255) / 256), dim3(256), 0, s, J, k, sel);
     hipLaunchKernelGGL(k_bw_gather<T>, dim3((unsigned)std::min<int64_t>((m + 255) / 256, 64), (unsigned)k), dim3(256), 0,
                        s, A, lda, m, J, C);
-    hipLaunchKernelGGL(k_bw_solve<T>, dim3((unsigned)((n + 15) / 16)), dim3(kBwThreads), (size_t)k * 16 * 8, s, gZ,
-                       ldgz, n, k, R11, ldr, sel, M);
+    // M = R11^{-1} R11^{-T} Gz (Gz = gZ with the J columns zeroed) on the
+    // matrix cores: the block triangular solve, transposed then forward
+    if (gZ) {
+        const int rc = semi_solve<T>(R11, ldr, k, gZ, ldgz, n, sel, M, (int64_t)k, ws + B.oSemi, s);
+        if (rc != 0) return rc;
+    } else {
+        const int64_t cnt = (int64_t)k * n;
+        hipLaunchKernelGGL(k_bw_zero<T>, dim3((unsigned)std::min<int64_t>((cnt + 255) / 256, 4096)), dim3(256), 0, s, M,
+                           cnt);
+    }
     int pr = prof_take(MIID_K_BWD_GEMM, 0, m, n);
     // gA = C M  (J columns come out zero: M[:, J] = 0)
     MIID_LAUNCH(pr, k_bw_gemm_nn<T>, dim3((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64)), dim3(kBwThreads),

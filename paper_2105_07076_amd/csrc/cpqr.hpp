@@ -45,4 +45,13 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
            int64_t ldc, miid_info* info, unsigned char* ws, hipStream_t stream, bool staged, const T* Csrc,
            int64_t ldcsrc, int64_t crows);
 
+// M = R11^{-1} R11^{-T} B on the matrix cores (the solution of
+// R11^T R11 M = B), R11 k x k FP64 upper triangular (ldr), B and M k x n
+// column-major (ldb, ldm); the columns marked in sel (sel[c] >= 0) are
+// treated as zero right-hand sides.  ws holds semi_solve_workspace(k) bytes.
+size_t semi_solve_workspace(int k);
+template <typename T>
+int semi_solve(const double* R11, int64_t ldr, int k, const T* B, int64_t ldb, int64_t n, const int32_t* sel, T* M,
+               int64_t ldm, unsigned char* ws, hipStream_t s);
+
 }  // namespace miid

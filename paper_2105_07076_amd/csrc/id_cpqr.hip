@@ -1074,13 +1074,18 @@ __global__ void __launch_bounds__(kTB) k_trsm_dinv(const double* __restrict__ R1
 // machinery read transposed (top-down over the row blocks, the transposed
 // diagonal-block inverses), so that Z = R11^{-1} R11^{-T} B -- the solution of
 // R11^T R11 Z = B (no refinement sweep in this form).
-template <typename T, int NC, bool SEMI = false>
+// JMODE 0: the columns marked in sel (sel[c] = step index) are written as
+// exact unit vectors (Z[:, J] = I); JMODE 1: their right-hand sides are read
+// as zero (the solution's columns come out zero).  The right-hand side
+// element (q, c) is R[q rs + c cs] (rows of R: rs = n, cs = 1).
+template <typename T, int NC, bool SEMI = false, int JMODE = 0>
 __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, int64_t n,
                                                      const double* __restrict__ R11s, int kpad,
                                                      const double* __restrict__ Dinv,
                                                      const DevState* __restrict__ st, int ksteps,
                                                      const int32_t* __restrict__ sel, T* __restrict__ Z,
-                                                     int64_t ldz, int kmax, int refine) {
+                                                     int64_t ldz, int kmax, int refine, int64_t rs,
+                                                     int64_t cs) {
     constexpr int NT = 8 * NC;
     constexpr int NCP = NC + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1095,6 +1100,10 @@ __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, in
     const int l16 = lane % 16, lq = lane / 16;
     const int64_t c0 = (int64_t)blockIdx.x * NC;
     const int64_t col = c0 + tc + l16;  // this lane's output column
+    // the workgroup's columns' selection marks (one load per column)
+    __shared__ int32_t s_sel[NC];
+    for (int cc = tid; cc < NC; cc += NT) s_sel[cc] = c0 + cc < n ? sel[c0 + cc] : -1;
+    __syncthreads();
     // the right-hand sides into LDS, eight loads per thread in flight
     for (int e0 = tid; e0 < kend * NC; e0 += 8 * NT) {
         double v[8];
@@ -1102,7 +1111,8 @@ __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, in
         for (int u = 0; u < 8; ++u) {
             const int e = e0 + u * NT;
             const int q = e / NC, c = e % NC;
-            v[u] = (e < kend * NC && q < K && c0 + c < n) ? (double)R[(int64_t)q * n + c0 + c] : 0.0;
+            const bool zc = JMODE == 1 && e < kend * NC && s_sel[c] >= 0;
+            v[u] = (e < kend * NC && q < K && c0 + c < n && !zc) ? (double)R[(int64_t)q * rs + (c0 + c) * cs] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -1155,7 +1165,7 @@ __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, in
                 if (sweep == 0)
                     acc[e] = sX[row * NCP + tc + l16];
                 else
-                    acc[e] = (row < K && col < n) ? (double)R[(int64_t)row * n + col] : 0.0;
+                    acc[e] = (row < K && col < n) ? (double)R[(int64_t)row * rs + col * cs] : 0.0;
             }
             // one kTB-deep slice of R11 at a time (kend - kstart is a
             // multiple of kTB): its eight operand loads are all in flight
@@ -1190,18 +1200,14 @@ __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, in
             __syncthreads();
         }
     }
-    // Z, column by column of the workgroup's NC: the columns' selection
-    // marks first (one load per column), then the stores
-    __shared__ int32_t s_sel[NC];
-    for (int cc = tid; cc < NC; cc += NT) s_sel[cc] = c0 + cc < n ? sel[c0 + cc] : -1;
-    __syncthreads();
+    // Z, column by column of the workgroup's NC
     for (int e = tid; e < kmax * NC; e += NT) {
         const int q = e % kmax, cc = e / kmax;
         const int64_t c = c0 + cc;
         if (c >= n) continue;
         const int s = s_sel[cc];
         double val;
-        if (s >= 0 && s < K)
+        if (JMODE == 0 && s >= 0 && s < K)
             val = (q == s) ? 1.0 : 0.0;
         else
             val = q < K ? sX[q * NCP + cc] : 0.0;
@@ -1919,15 +1925,15 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
         if (P.kpad <= 256) {
             MIID_LAUNCH(pr, (k_trsm_blk<T, 64>), dim3((unsigned)((n + 63) / 64)), dim3(8 * 64),
                         (size_t)P.kpad * 65 * 8, stream, R, n, R11s, P.kpad, Dinv, st, ksteps, sel, Z, ldz, P.kmax,
-                        (int)P.refine);
+                        (int)P.refine, n, (int64_t)1);
         } else if (P.kpad <= 512) {
             MIID_LAUNCH(pr, (k_trsm_blk<T, 32>), dim3((unsigned)((n + 31) / 32)), dim3(8 * 32),
                         (size_t)P.kpad * 33 * 8, stream, R, n, R11s, P.kpad, Dinv, st, ksteps, sel, Z, ldz, P.kmax,
-                        (int)P.refine);
+                        (int)P.refine, n, (int64_t)1);
         } else {
             MIID_LAUNCH(pr, (k_trsm_blk<T, 16>), dim3((unsigned)((n + 15) / 16)), dim3(8 * 16),
                         (size_t)P.kpad * 17 * 8, stream, R, n, R11s, P.kpad, Dinv, st, ksteps, sel, Z, ldz, P.kmax,
-                        (int)P.refine);
+                        (int)P.refine, n, (int64_t)1);
         }
     }
     // a10: C, info
@@ -2125,16 +2131,76 @@ static int run_rid_sample(const RsPlan& Q, const T* A, int64_t m, int64_t n, int
     const DevState* st = reinterpret_cast<const DevState*>(w + P.ostate);
     if (P.kpad <= 256)
         hipLaunchKernelGGL((k_trsm_blk<T, 64, true>), dim3((unsigned)((n + 63) / 64)), dim3(8 * 64),
-                           (size_t)P.kpad * 65 * 8, s, G, n, R11s, P.kpad, Dinv, st, k, sel, Z, ldz, k, 0);
+                           (size_t)P.kpad * 65 * 8, s, G, n, R11s, P.kpad, Dinv, st, k, sel, Z, ldz, k, 0, n,
+                           (int64_t)1);
     else if (P.kpad <= 512)
         hipLaunchKernelGGL((k_trsm_blk<T, 32, true>), dim3((unsigned)((n + 31) / 32)), dim3(8 * 32),
-                           (size_t)P.kpad * 33 * 8, s, G, n, R11s, P.kpad, Dinv, st, k, sel, Z, ldz, k, 0);
+                           (size_t)P.kpad * 33 * 8, s, G, n, R11s, P.kpad, Dinv, st, k, sel, Z, ldz, k, 0, n,
+                           (int64_t)1);
     else
         hipLaunchKernelGGL((k_trsm_blk<T, 16, true>), dim3((unsigned)((n + 15) / 16)), dim3(8 * 16),
-                           (size_t)P.kpad * 17 * 8, s, G, n, R11s, P.kpad, Dinv, st, k, sel, Z, ldz, k, 0);
+                           (size_t)P.kpad * 17 * 8, s, G, n, R11s, P.kpad, Dinv, st, k, sel, Z, ldz, k, 0, n,
+                           (int64_t)1);
     MIID_HIP(hipGetLastError());
     return 0;
 }
+
+// R11s (kpad x kpad, column-major) = R11 (upper triangle) padded with the
+// identity
+__global__ void k_pad_r11(const double* __restrict__ R11, int64_t ldr, int k, int kpad, double* __restrict__ R11s) {
+    const int64_t total = (int64_t)kpad * kpad;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int a = (int)(e % kpad), b = (int)(e / kpad);
+        R11s[e] = (a < k && b < k) ? (a <= b ? R11[a + (int64_t)b * ldr] : 0.0) : (a == b ? 1.0 : 0.0);
+    }
+}
+
+size_t semi_solve_workspace(int k) {
+    const size_t kpad = align_up((size_t)k, kTB);
+    return align_up(kpad * kpad * 8, 256) + align_up(kpad * kTB * 8, 256) + align_up(sizeof(DevState), 256);
+}
+
+template <typename T>
+int semi_solve(const double* R11, int64_t ldr, int k, const T* B, int64_t ldb, int64_t n, const int32_t* sel, T* M,
+               int64_t ldm, unsigned char* ws, hipStream_t s) {
+    const int kpad = (int)align_up((size_t)k, kTB);
+    double* R11s = reinterpret_cast<double*>(ws);
+    double* Dinv = reinterpret_cast<double*>(ws + align_up((size_t)kpad * kpad * 8, 256));
+    DevState* st = reinterpret_cast<DevState*>(ws + align_up((size_t)kpad * kpad * 8, 256) +
+                                                align_up((size_t)kpad * kTB * 8, 256));
+    static bool attr_done = false;
+    if (!attr_done) {
+        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 64, true, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     256 * 65 * 8));
+        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 32, true, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     512 * 33 * 8));
+        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 16, true, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     1024 * 17 * 8));
+        attr_done = true;
+    }
+    hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned char*>(st),
+                       (int64_t)sizeof(DevState), (unsigned char)0);  // not stopped: K = k
+    const int64_t total = (int64_t)kpad * kpad;
+    hipLaunchKernelGGL(k_pad_r11, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)), dim3(256), 0, s, R11, ldr,
+                       k, kpad, R11s);
+    hipLaunchKernelGGL(k_trsm_dinv, dim3((unsigned)(kpad / kTB)), dim3(kTB), 0, s, R11s, kpad, Dinv);
+    if (kpad <= 256)
+        hipLaunchKernelGGL((k_trsm_blk<T, 64, true, 1>), dim3((unsigned)((n + 63) / 64)), dim3(8 * 64),
+                           (size_t)kpad * 65 * 8, s, B, n, R11s, kpad, Dinv, st, k, sel, M, ldm, k, 0, (int64_t)1, ldb);
+    else if (kpad <= 512)
+        hipLaunchKernelGGL((k_trsm_blk<T, 32, true, 1>), dim3((unsigned)((n + 31) / 32)), dim3(8 * 32),
+                           (size_t)kpad * 33 * 8, s, B, n, R11s, kpad, Dinv, st, k, sel, M, ldm, k, 0, (int64_t)1, ldb);
+    else
+        hipLaunchKernelGGL((k_trsm_blk<T, 16, true, 1>), dim3((unsigned)((n + 15) / 16)), dim3(8 * 16),
+                           (size_t)kpad * 17 * 8, s, B, n, R11s, kpad, Dinv, st, k, sel, M, ldm, k, 0, (int64_t)1, ldb);
+    MIID_HIP(hipGetLastError());
+    return 0;
+}
+
+template int semi_solve<float>(const double*, int64_t, int, const float*, int64_t, int64_t, const int32_t*, float*,
+                               int64_t, unsigned char*, hipStream_t);
+template int semi_solve<double>(const double*, int64_t, int, const double*, int64_t, int64_t, const int32_t*, double*,
+                                int64_t, unsigned char*, hipStream_t);
 
 template int run_id<float>(const IdPlan&, const float*, int64_t, int32_t*, float*, int64_t, double*, int64_t, float*,
                            int64_t, miid_info*, unsigned char*, hipStream_t, bool, const float*, int64_t, int64_t);
