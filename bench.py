@@ -216,6 +216,18 @@ def main() -> int:
         if stp:
             extra["rid_cpqr_step_us"] = round(1000.0 * sum(r.ms for r in stp) / len(stp), 2)
         log(f"[bench] RID {ms_rid:.3f} ms")
+        # the same RID with Z = C^+ A over the full A (the paper's Z)
+        out_l = miid_api.rid_raw(A32, Om, k=k, mode=1, lstsq=True)
+        for _ in range(args.warmup):
+            miid_api.rid_raw(A32, Om, k=k, mode=1, lstsq=True, out=out_l)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            miid_api.rid_raw(A32, Om, k=k, mode=1, lstsq=True, out=out_l)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        extra["rid_lstsq_ms"] = round((t1 - t0) * 1000.0 / args.steps, 4)
+        log(f"[bench] RID with least-squares Z {extra['rid_lstsq_ms']:.3f} ms")
 
     if "ridsample" in only:
         # the paper's randomized ID by column sampling (p = k + 0.2 k), FP64,

@@ -54,6 +54,8 @@ typedef enum { MIID_F32 = 0, MIID_F64 = 1 } miid_dtype;
 #define MIID_NO_REFINE 1u      /* skip the refinement step of the triangular solve */
 #define MIID_KEEP_COLUMNS 2u   /* id_cpqr: column ID even when m > n (no dual ID of A^T);
                                   then k <= n is required                           */
+#define MIID_LSTSQ_Z 4u        /* rid_sketch_cpqr, fixed rank only: Z = C^+ A over the
+                                  full A instead of T from the sketch             */
 
 /* Tuning hints, 4-bit fields of miid_opts.flags (0 = library default).  They
  * change launch shapes only, never the arithmetic's definition; the
@@ -167,6 +169,13 @@ int id_cpqr(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
  *                 ~ 2^-16 relative in Y)
  *  J, Z, C, R11, info: as in id_cpqr with dtype FP32; Z is kmax x n
  *  Y      (15) nullable, l x n FP32, ldy >= l: the sketch
+ * With MIID_LSTSQ_Z in opts.flags (fixed rank, k <= m) Z is instead the
+ * least-squares coefficient matrix over the full A, Z = C^+ A, the paper's
+ * way of forming the randomized ID's Z (Section 2.2, eq. final_eq): the
+ * sketch's k columns are handed to the column-sampling path below as its
+ * sample, so J comes out as the same skeleton reordered by the pivoted QR
+ * of C, R11 is that QR's triangular factor, and Z solves R11^T R11 Z = C^T A
+ * with Z[:, J] = I.  info still describes the CPQR of Y.
  * Limits: k <= l <= min(n, 1024) (kmax <= l in tolerance mode), m <= n.
  * ---------------------------------------------------------------------- */
 size_t miid_rid_workspace(int64_t m, int64_t n, int32_t l, const miid_opts *opts);

@@ -24,6 +24,7 @@ MIID_KMAX_HIT = 8
 
 MIID_NO_REFINE = 1
 MIID_KEEP_COLUMNS = 2
+MIID_LSTSQ_Z = 4
 
 # every symbol declared in include/miid.h
 EXPORTED = [

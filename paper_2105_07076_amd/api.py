@@ -206,7 +206,8 @@ def rid_sample(A: torch.Tensor, idx, k: int, nb: int = 0, want_C: bool = True, w
 
 def rid_raw(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: float | None = None,
             kmax: int | None = None, mode: int = 1, nb: int = 0, refine: bool = True, want_C: bool = True,
-            want_Y: bool = False, want_R11: bool = False, out: dict | None = None, hints: int = 0):
+            want_Y: bool = False, want_R11: bool = False, out: dict | None = None, hints: int = 0,
+            lstsq: bool = False):
     """Enqueue rid_sketch_cpqr without synchronising (see :func:`rid`)."""
     lib = _abi.load()
     if A.dtype != torch.float32 or not A.is_cuda:
@@ -223,6 +224,10 @@ def rid_raw(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: flo
         kmax = l if k is None else k
     kk = k if k is not None else kmax
     opts = _opts(k, eps, kmax, nb, refine, hints)
+    if lstsq:
+        if k is None:
+            raise ValueError("lstsq needs a fixed rank k")
+        opts.flags |= _abi.MIID_LSTSQ_Z
     ws_bytes = lib.miid_rid_workspace(m, n, l, ctypes.byref(opts))
     if ws_bytes == 0:
         _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_rid_workspace")
@@ -248,16 +253,19 @@ def rid_raw(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: flo
 
 def rid(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: float | None = None,
         kmax: int | None = None, mode: int = 1, nb: int = 0, refine: bool = True, want_C: bool = True,
-        want_Y: bool = False, want_R11: bool = False, hints: int = 0) -> IDResult:
+        want_Y: bool = False, want_R11: bool = False, hints: int = 0, lstsq: bool = False) -> IDResult:
     """Randomized ID of A (m x n float32, m <= n) with the Gaussian row sketch
     Y = omega A computed on the matrix cores.
 
     ``omega`` is an l x m bfloat16 tensor (the random numbers the method
     draws are an input).  ``mode`` 1 splits A as hi + lo bfloat16 (two
     passes), 0 rounds it once.  J and T come from the CPQR of Y; C = A[:, J].
+    With ``lstsq`` (fixed rank) Z is instead C^+ A over the full A, the
+    paper's way of forming the randomized ID's Z: J is then the sketch's
+    skeleton reordered by the pivoted QR of C, and R11 is that QR's factor.
     ``a_norm``/``r22_norm`` in the result refer to Y."""
     out = rid_raw(A, omega, k=k, eps=eps, kmax=kmax, mode=mode, nb=nb, refine=refine, want_C=want_C,
-                  want_Y=want_Y, want_R11=want_R11, hints=hints)
+                  want_Y=want_Y, want_R11=want_R11, hints=hints, lstsq=lstsq)
     return _finish(out, Y=out["Y"])
 
 

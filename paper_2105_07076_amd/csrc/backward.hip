@@ -7,8 +7,10 @@
 // zeroed and M = (C^T C)^{-1} Gz = R11^{-1} R11^{-T} Gz:
 //     gA          = C M
 //     gA[:, J]    = gC + A M^T - C (Z M^T + M Z^T)    (C M is zero there)
-// Kernels: the two FP64 triangular solves for M (column tiles in LDS); the
-// products C M and A M^T on the matrix cores (16x16x4 MFMA in the working
+// Kernels: the two FP64 triangular solves for M in one launch (the blocked
+// solve of the forward pass, run transposed then forward, on the FP64 matrix
+// cores with the right-hand-side tiles in LDS); the products C M and A M^T on
+// the matrix cores (16x16x4 MFMA in the working
 // precision; A M^T split over n with a fixed-order second pass, so the result
 // is deterministic); the small k x k and m x k terms on the vector units.
 #include <algorithm>

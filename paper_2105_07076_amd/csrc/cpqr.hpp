@@ -45,6 +45,19 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
            int64_t ldc, miid_info* info, unsigned char* ws, hipStream_t stream, bool staged, const T* Csrc,
            int64_t ldcsrc, int64_t crows);
 
+// The column-sampling randomized ID: the CPQR of A_S = A[:, idx] (m x p,
+// its own column ID) picks J = idx[J_S] and R_k; Z solves
+// R_k^T R_k Z = C^T A over the full A (Z[:, J] = I).
+struct RsPlan {
+    IdPlan id;  // the CPQR of A_S (its workspace comes first)
+    size_t oAs, oZs, oJs, oC, oG, oSel, total;
+};
+int rs_plan(int64_t m, int64_t n, int32_t p, miid_dtype dtype, const miid_opts* o, RsPlan* Q);
+template <typename T>
+int run_rid_sample(const RsPlan& Q, const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* idx, int p,
+                   int32_t* J, T* Z, int64_t ldz, double* R11, int64_t ldr, T* C, int64_t ldc, miid_info* info,
+                   unsigned char* w, hipStream_t s);
+
 // M = R11^{-1} R11^{-T} B on the matrix cores (the solution of
 // R11^T R11 M = B), R11 k x k FP64 upper triangular (ldr), B and M k x n
 // column-major (ldb, ldm); the columns marked in sel (sel[c] >= 0) are

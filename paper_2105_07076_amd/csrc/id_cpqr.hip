@@ -2070,12 +2070,7 @@ __global__ void __launch_bounds__(kThreads) k_gemm_tn(const T* __restrict__ C, i
             }
 }
 
-struct RsPlan {
-    IdPlan id;  // the CPQR of A_S (its workspace comes first)
-    size_t oAs, oZs, oJs, oC, oG, oSel, total;
-};
-
-static int rs_plan(int64_t m, int64_t n, int32_t p, miid_dtype dtype, const miid_opts* o, RsPlan* Q) {
+int rs_plan(int64_t m, int64_t n, int32_t p, miid_dtype dtype, const miid_opts* o, RsPlan* Q) {
     if (p < 1 || p > n) return -7;
     if (!o || o->k < 1) return -8;  // fixed rank only
     miid_opts oo = *o;
@@ -2101,7 +2096,7 @@ static int rs_plan(int64_t m, int64_t n, int32_t p, miid_dtype dtype, const miid
 }
 
 template <typename T>
-static int run_rid_sample(const RsPlan& Q, const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* idx, int p,
+int run_rid_sample(const RsPlan& Q, const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* idx, int p,
                           int32_t* J, T* Z, int64_t ldz, double* R11, int64_t ldr, T* C, int64_t ldc,
                           miid_info* info, unsigned char* w, hipStream_t s) {
     const IdPlan& P = Q.id;
@@ -2197,6 +2192,12 @@ int semi_solve(const double* R11, int64_t ldr, int k, const T* B, int64_t ldb, i
     return 0;
 }
 
+template int run_rid_sample<float>(const RsPlan&, const float*, int64_t, int64_t, int64_t, const int32_t*, int, int32_t*,
+                                   float*, int64_t, double*, int64_t, float*, int64_t, miid_info*, unsigned char*,
+                                   hipStream_t);
+template int run_rid_sample<double>(const RsPlan&, const double*, int64_t, int64_t, int64_t, const int32_t*, int,
+                                    int32_t*, double*, int64_t, double*, int64_t, double*, int64_t, miid_info*,
+                                    unsigned char*, hipStream_t);
 template int semi_solve<float>(const double*, int64_t, int, const float*, int64_t, int64_t, const int32_t*, float*,
                                int64_t, unsigned char*, hipStream_t);
 template int semi_solve<double>(const double*, int64_t, int, const double*, int64_t, int64_t, const int32_t*, double*,

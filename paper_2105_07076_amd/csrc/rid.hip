@@ -224,7 +224,27 @@ struct RidPlan {
     int mt_total;    // 16-row tiles of Y
     int64_t mpad;    // K padded to 32
     size_t oWt, total;
+    // least-squares Z over the full A: the column-sampling path with the
+    // sketch's skeleton as its sample (its own workspace, the copied
+    // skeleton, its info)
+    bool lstsq;
+    RsPlan rs;
+    size_t oRs, oJk, oInfo2;
 };
+
+// Jk = J (the sample the least-squares pass reads while it rewrites J)
+__global__ void k_copy_i32(const int32_t* __restrict__ src, int n, int32_t* __restrict__ dst) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// the sketch's info keeps its norms; k_out and the rank-deficiency bit also
+// take the least-squares pass's CPQR of C into account
+__global__ void k_merge_info(miid_info* __restrict__ info, const miid_info* __restrict__ info2) {
+    if (threadIdx.x == 0) {
+        if (info2->k_out < info->k_out) info->k_out = info2->k_out;
+        info->status |= info2->status & MIID_RANK_DEFICIENT;
+    }
+}
 
 static int make_rid_plan(int64_t m, int64_t n, int32_t l, const miid_opts* opts, RidPlan* R) {
     if (m < 1) return -2;
@@ -239,6 +259,16 @@ static int make_rid_plan(int64_t m, int64_t n, int32_t l, const miid_opts* opts,
     R->mpad = (int64_t)align_up((size_t)m, kSkK);
     R->oWt = align_up(R->id.total, 256);
     R->total = align_up(R->oWt + (size_t)R->lpad * R->mpad * 2, 256);
+    R->lstsq = opts && (opts->flags & MIID_LSTSQ_Z);
+    if (R->lstsq) {
+        if (opts->k < 1 || opts->k > m) return MIID_E_UNSUPPORTED;
+        const int rc2 = rs_plan(m, n, opts->k, MIID_F32, opts, &R->rs);
+        if (rc2 != 0) return rc2 == -7 || rc2 == -8 ? MIID_E_UNSUPPORTED : rc2;
+        R->oRs = R->total;
+        R->oJk = align_up(R->oRs + R->rs.total, 256);
+        R->oInfo2 = align_up(R->oJk + (size_t)opts->k * 4, 256);
+        R->total = align_up(R->oInfo2 + sizeof(miid_info), 256);
+    }
     return 0;
 }
 
@@ -304,7 +334,20 @@ int rid_sketch_cpqr(const float* A, int64_t m, int64_t n, int64_t lda, const uin
         MIID_HIP(e);
     }
     MIID_HIP(hipGetLastError());
-    return run_id<float>(R.id, A, lda, J, Z, ldz, R11, ldr, C, ldc, info, w, s, true, A, lda, m);
+    const int rc2 = run_id<float>(R.id, A, lda, J, Z, ldz, R11, ldr, C, ldc, info, w, s, true, A, lda, m);
+    if (rc2 != 0 || !R.lstsq) return rc2;
+    // Z = C^+ A: the sketch's k columns as the sample of the column-sampling
+    // path (a skeleton cut short by an exact zero residual ends in -1
+    // entries, which gather as zero columns and stop C's CPQR there too)
+    const int k = R.id.kmax;
+    int32_t* Jk = reinterpret_cast<int32_t*>(w + R.oJk);
+    miid_info* info2 = reinterpret_cast<miid_info*>(w + R.oInfo2);
+    hipLaunchKernelGGL(k_copy_i32, dim3(1), dim3(256), 0, s, J, k, Jk);
+    const int rc3 = run_rid_sample<float>(R.rs, A, m, n, lda, Jk, k, J, Z, ldz, R11, ldr, C, ldc, info2, w + R.oRs, s);
+    if (rc3 != 0) return rc3;
+    hipLaunchKernelGGL(k_merge_info, dim3(1), dim3(64), 0, s, info, info2);
+    MIID_HIP(hipGetLastError());
+    return 0;
 }
 
 }  // extern "C"

@@ -185,3 +185,95 @@ def test_rid_16384x65536_k512():
     err = np.linalg.norm(Acols - C @ Z[:, cols]) / np.linalg.norm(Acols)
     tail = np.exp(-k / 128.0)
     assert 0.5 * tail <= err <= 10.0 * tail, f"sampled relative error {err:.3e}, tail {tail:.3e}"
+
+
+# --------------------------------------------------------------------------
+# least-squares Z over the full A (MIID_LSTSQ_Z): the sketch's skeleton as the
+# column sample of the paper's Z construction, Z = C^+ A
+# --------------------------------------------------------------------------
+def _lstsq_pair(A_t, Om_t, k, mode=1):
+    miid = _miid()
+    rs = miid.rid(A_t, Om_t, k=k, mode=mode)
+    rl = miid.rid(A_t, Om_t, k=k, mode=mode, lstsq=True, want_R11=True)
+    torch.cuda.synchronize()
+    return rs, rl
+
+
+def _check_lstsq_against_oracle(A64, Js, rl, k, cols=None):
+    """The least-squares pass against the oracle's column-sampling RID with
+    the sketch's skeleton Js as the sample: the same k columns, C's pivot
+    order margin-aware (FP32), R11 and Z within the FP32 bars."""
+    J = to_np(rl.J)
+    assert sorted(J.tolist()) == sorted(Js.tolist())
+    pos = np.array([int(np.where(Js == j)[0][0]) for j in J], dtype=np.int32)
+    # C's column CPQR: padded with zero columns to at least m columns so that
+    # the oracle takes the column ID (a tall matrix gets the dual ID there);
+    # a zero column is never picked ahead of a nonzero residual
+    m = A64.shape[0]
+    C64 = np.hstack([A64[:, Js], np.zeros((m, max(0, m - k)))])
+    ref, ties = pivot_parity(C64, pos, k, U32)
+    Z = to_np(rl.Z).astype(np.float64)
+    assert np.array_equal(Z[:, J], np.eye(k))
+    Rk = ref.R[:, ref.J]
+    assert rel(to_np(rl.R11), Rk) <= max(1e-5, 8.0 * U32 * np.linalg.cond(Rk))
+    # Z = C^+ A on the checked columns, in the GPU's skeleton order
+    S = np.arange(A64.shape[1]) if cols is None else np.asarray(cols)
+    Cg = A64[:, J]
+    Zref = np.linalg.lstsq(Cg, A64[:, S], rcond=None)[0]
+    bar = max(1e-5, 256.0 * U32 * np.linalg.cond(Rk) ** 2)
+    assert rel(Z[:, S], Zref) <= bar, f"Z error {rel(Z[:, S], Zref):.3e} > {bar:.3e}"
+    return ties
+
+
+@pytest.mark.parametrize("m,n,l,k", [(64, 200, 26, 16), (100, 333, 50, 40), (257, 1000, 74, 64)])
+def test_rid_lstsq_matches_oracle(m, n, l, k):
+    g = idgen.rng(m * 5 + n)
+    A = g.standard_normal((m, n)) @ np.diag(0.97 ** np.arange(n))
+    A_t = torch.tensor(A, dtype=torch.float32, device="cuda")
+    A64 = A_t.double().cpu().numpy()
+    Om_t = torch.tensor(idgen.omega_bf16(m + 3, l, m), dtype=torch.bfloat16, device="cuda")
+    rs, rl = _lstsq_pair(A_t, Om_t, k)
+    assert rl.k == k
+    Js = to_np(rs.J)
+    _check_lstsq_against_oracle(A64, Js, rl, k)
+    # C = A[:, J] exactly, and Z is the best for this skeleton: no larger
+    # error than T from the sketch, column by column
+    J = to_np(rl.J)
+    assert np.array_equal(to_np(rl.C).astype(np.float64), A64[:, J])
+    el = np.linalg.norm(A64 - A64[:, J] @ to_np(rl.Z).astype(np.float64), axis=0)
+    es = np.linalg.norm(A64 - A64[:, Js] @ to_np(rs.Z).astype(np.float64), axis=0)
+    _no_worse(el, es, np.linalg.norm(A64, axis=0))
+
+
+def _no_worse(el, es, anorm):
+    """Least squares is optimal for the skeleton: no larger error than T from
+    the sketch, in total and column by column up to FP32 rounding."""
+    assert np.linalg.norm(el) <= np.linalg.norm(es) * (1.0 + 1e-4)
+    assert np.all(el <= es + 1e-3 * anorm)
+
+
+def test_rid_lstsq_rejects_tolerance_mode():
+    miid = _miid()
+    A_t = torch.ones((16, 40), dtype=torch.float32, device="cuda")
+    Om_t = torch.ones((8, 16), dtype=torch.bfloat16, device="cuda")
+    with pytest.raises(ValueError):
+        miid.rid(A_t, Om_t, eps=1e-3, lstsq=True)
+
+
+def test_rid_lstsq_cfg2_full_size():
+    """4096 x 16384, k = 256, l = 266 with Z = C^+ A: Z on 64 sampled columns
+    against FP64 least squares on the GPU's skeleton; per-column errors on 256
+    sampled columns no larger than with T from the sketch."""
+    A_t = idgen.lowrank_plus_noise_device(2, 4096, 16384, np.exp(-np.arange(4096) / 64.0), 1e-8,
+                                          dtype=torch.float32)
+    Om_t = torch.tensor(idgen.omega_bf16(77, 266, 4096), dtype=torch.bfloat16, device="cuda")
+    rs, rl = _lstsq_pair(A_t, Om_t, 256)
+    assert rl.k == 256
+    A64 = A_t.double().cpu().numpy()
+    g = idgen.rng(80)
+    cols = np.sort(g.choice(16384, 256, replace=False))
+    _check_lstsq_against_oracle(A64, to_np(rs.J), rl, 256, cols=cols[:64])
+    J, Js = to_np(rl.J), to_np(rs.J)
+    el = np.linalg.norm(A64[:, cols] - A64[:, J] @ to_np(rl.Z).astype(np.float64)[:, cols], axis=0)
+    es = np.linalg.norm(A64[:, cols] - A64[:, Js] @ to_np(rs.Z).astype(np.float64)[:, cols], axis=0)
+    _no_worse(el, es, np.linalg.norm(A64[:, cols], axis=0))
