@@ -133,10 +133,11 @@ def main() -> int:
                     help="build the 4096 x 16384 input with the numpy recipe on the host (no device QR; "
                          "for counter-collection runs)")
     ap.add_argument("--only", default="all",
-                    help="comma list of sections to run: id64,id32,rid,ridsample,batched,bwd (default all); "
+                    help="comma list of sections to run: id64,id32,rid,ridsample,paper,batched,bwd (default all); "
                          "the value is the FP64 ID, so id64 always runs")
     args = ap.parse_args()
-    only = set(args.only.split(",")) if args.only != "all" else {"id64", "id32", "rid", "ridsample", "batched", "bwd"}
+    sections = {"id64", "id32", "rid", "ridsample", "paper", "batched", "bwd"}
+    only = set(args.only.split(",")) if args.only != "all" else sections
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the ID hot path is built for a single MI355X "
               "(multi-GPU sharding is described in DESIGN.md, not implemented).", file=sys.stderr)
@@ -247,6 +248,30 @@ def main() -> int:
         extra["rid_sample_fp64_ms"] = round(ms_s, 4)
         extra["rid_sample_speedup_vs_fp64_id"] = round(ms64 / ms_s, 2)
         log(f"[bench] sampled RID {ms_s:.3f} ms")
+
+    if "paper" in only:
+        # the paper's own shape (Gaussian 784 x 1000, k = 190; its timing
+        # table), context beside the metric: FP64 ID and column-sampling RID
+        log("[bench] paper-shaped 784 x 1000, k = 190 (FP64)")
+        Ap = torch.tensor(idgen.paper_dataset("gaussian", seed=0), device="cuda")
+        idx_p = idgen.column_sample(100, 1000, 190)
+
+        def timed(fn):
+            o = fn(None)
+            for _ in range(args.warmup):
+                fn(o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn(o)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1000.0 / args.steps
+
+        extra["paper_784x1000_k190_id_fp64_ms"] = round(timed(lambda o: miid_api.id_raw(Ap, k=190, out=o)), 4)
+        extra["paper_784x1000_k190_rid_sample_fp64_ms"] = round(
+            timed(lambda o: miid_api.rid_sample_raw(Ap, idx_p, 190, out=o)), 4)
+        log(f"[bench] paper shape: ID {extra['paper_784x1000_k190_id_fp64_ms']:.3f} ms, "
+            f"sampled RID {extra['paper_784x1000_k190_rid_sample_fp64_ms']:.3f} ms")
 
     if "batched" in only:
         # batched IDs: 4096 kernel-matrix blocks, tolerance 1e-6, FP32, one launch

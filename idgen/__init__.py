@@ -113,6 +113,33 @@ def paper_dataset(name: str, seed: int = 0, m: int = 784, n: int = 1000) -> np.n
     return np.asfortranarray(A)
 
 
+# shapes and nonzero counts of the paper's three sparse datasets (its table
+# of sparse dataset information); the matrices themselves are not available
+SPARSE_SHAPES = {"sparse1": (1138, 4054), "sparse2": (846, 10894), "sparse3": (531, 7422)}
+
+
+def sparse_standin(name: str, seed: int = 0) -> np.ndarray:
+    """A stand-in for one of the paper's sparse datasets, stored densely as
+    the paper did: a random symmetric n x n matrix with the dataset's shape
+    and nonzero count, a nonzero diagonal plus symmetric off-diagonal pairs at
+    uniformly random positions, values uniform in (0, 1] (weighted graphs)."""
+    n, nnz = SPARSE_SHAPES[name]
+    g = rng(seed)
+    A = np.zeros((n, n))
+    A[np.arange(n), np.arange(n)] = 1.0 - g.random(n)
+    pairs = (nnz - n) // 2
+    placed = 0
+    while placed < pairs:
+        i = g.integers(0, n, size=pairs - placed)
+        j = g.integers(0, n, size=pairs - placed)
+        for a, b in zip(i, j):
+            if a != b and A[a, b] == 0.0 and placed < pairs:
+                v = 1.0 - g.random()
+                A[a, b] = A[b, a] = v
+                placed += 1
+    return np.asfortranarray(A)
+
+
 def bf16_round(x: np.ndarray) -> np.ndarray:
     """Round float values to the nearest bfloat16 (ties to even); returns
     float32 values that are exactly representable in bfloat16."""

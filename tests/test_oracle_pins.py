@@ -304,6 +304,30 @@ def test_paper_table2_relative_error(name):
     assert np.abs(res.Z).max() == row["id_max_abs_Z"]
 
 
+@pytest.mark.parametrize("name", ["boolean", "gaussian", "uniform"])
+def test_paper_table2_optim_rid(name):
+    """The column-sampling RID's Table 2 error and Table 1 max |Z| (Optim RID
+    columns, means over the paper's 10 runs of p = k + floor(0.2 k) sampled
+    columns) on the synthetic datasets."""
+    tab = _paper_table()
+    row = tab["rows"][name]
+    A = idgen.paper_dataset(name, seed=0)
+    k = tab["k"]
+    errs, zmax = [], []
+    for run in range(tab["rid_runs"]):
+        idx = idgen.column_sample(100 + run, A.shape[1], k)
+        assert len(idx) == k + int(0.2 * k)
+        cols, Z, _ = oracle.rid_sample(A, idx, k)
+        errs.append(oracle.error(A, cols, Z) / np.linalg.norm(A))
+        zmax.append(np.abs(Z).max())
+    assert abs(np.mean(errs) - row["rid_rel_error"]) <= tab["abs_tol"]
+    # printed as 1 (to three decimals): every run's largest entry is the
+    # identity block's
+    assert abs(np.mean(zmax) - row["rid_max_abs_Z"]) <= 5e-4
+    # and stays well above the rank-k optimum (Eckart-Young)
+    assert np.mean(errs) >= row["svd_rel_error"] + 0.05
+
+
 # --------------------------------------------------------------------------
 # randomized ID special cases
 # --------------------------------------------------------------------------
