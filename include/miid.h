@@ -49,6 +49,9 @@ typedef enum { MIID_F32 = 0, MIID_F64 = 1 } miid_dtype;
 #define MIID_TRANSPOSED 4u     /* m > n: the dual ID of A^T was computed      */
 #define MIID_KMAX_HIT 8u       /* tolerance mode stopped at kmax, not at eps  */
 #define MIID_BLOCK_UNSUPPORTED 16u /* id_batched: block outside the size limits */
+#define MIID_LSTSQ_BREAKDOWN 32u   /* rid_sketch_cpqr with MIID_LSTSQ_Z: C^T C is not
+                                      positive definite in FP64 (C's columns
+                                      numerically dependent): Z unspecified */
 
 /* option flags */
 #define MIID_NO_REFINE 1u      /* skip the refinement step of the triangular solve */
@@ -171,11 +174,11 @@ int id_cpqr(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
  *  Y      (15) nullable, l x n FP32, ldy >= l: the sketch
  * With MIID_LSTSQ_Z in opts.flags (fixed rank, k <= m) Z is instead the
  * least-squares coefficient matrix over the full A, Z = C^+ A, the paper's
- * way of forming the randomized ID's Z (Section 2.2, eq. final_eq): the
- * sketch's k columns are handed to the column-sampling path below as its
- * sample, so J comes out as the same skeleton reordered by the pivoted QR
- * of C, R11 is that QR's triangular factor, and Z solves R11^T R11 Z = C^T A
- * with Z[:, J] = I.  info still describes the CPQR of Y.
+ * way of forming the randomized ID's Z (Section 2.2, eq. final_eq), for the
+ * skeleton J the sketch selected (same J, same order): R11 is then the
+ * Cholesky factor of C^T C (computed in FP64, R11^T R11 = C^T C, positive
+ * diagonal) and Z solves R11^T R11 Z = C^T A with Z[:, J] = I.  info still
+ * describes the CPQR of Y, plus MIID_LSTSQ_BREAKDOWN.
  * Limits: k <= l <= min(n, 1024) (kmax <= l in tolerance mode), m <= n.
  * ---------------------------------------------------------------------- */
 size_t miid_rid_workspace(int64_t m, int64_t n, int32_t l, const miid_opts *opts);

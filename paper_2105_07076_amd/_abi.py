@@ -21,6 +21,7 @@ MIID_RANK_DEFICIENT = 1
 MIID_NONFINITE = 2
 MIID_TRANSPOSED = 4
 MIID_KMAX_HIT = 8
+MIID_LSTSQ_BREAKDOWN = 32
 
 MIID_NO_REFINE = 1
 MIID_KEEP_COLUMNS = 2

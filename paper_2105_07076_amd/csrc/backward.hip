@@ -243,7 +243,7 @@ static int run_bw(const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* 
     // M = R11^{-1} R11^{-T} Gz (Gz = gZ with the J columns zeroed) on the
     // matrix cores: the block triangular solve, transposed then forward
     if (gZ) {
-        const int rc = semi_solve<T>(R11, ldr, k, gZ, ldgz, n, sel, M, (int64_t)k, ws + B.oSemi, s);
+        const int rc = semi_solve<T>(R11, ldr, k, gZ, (int64_t)1, ldgz, n, sel, 1, M, (int64_t)k, ws + B.oSemi, s);
         if (rc != 0) return rc;
     } else {
         const int64_t cnt = (int64_t)k * n;

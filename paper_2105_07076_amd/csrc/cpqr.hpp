@@ -45,26 +45,31 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
            int64_t ldc, miid_info* info, unsigned char* ws, hipStream_t stream, bool staged, const T* Csrc,
            int64_t ldcsrc, int64_t crows);
 
-// The column-sampling randomized ID: the CPQR of A_S = A[:, idx] (m x p,
-// its own column ID) picks J = idx[J_S] and R_k; Z solves
-// R_k^T R_k Z = C^T A over the full A (Z[:, J] = I).
-struct RsPlan {
-    IdPlan id;  // the CPQR of A_S (its workspace comes first)
-    size_t oAs, oZs, oJs, oC, oG, oSel, total;
-};
-int rs_plan(int64_t m, int64_t n, int32_t p, miid_dtype dtype, const miid_opts* o, RsPlan* Q);
-template <typename T>
-int run_rid_sample(const RsPlan& Q, const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* idx, int p,
-                   int32_t* J, T* Z, int64_t ldz, double* R11, int64_t ldr, T* C, int64_t ldc, miid_info* info,
-                   unsigned char* w, hipStream_t s);
-
 // M = R11^{-1} R11^{-T} B on the matrix cores (the solution of
-// R11^T R11 M = B), R11 k x k FP64 upper triangular (ldr), B and M k x n
-// column-major (ldb, ldm); the columns marked in sel (sel[c] >= 0) are
-// treated as zero right-hand sides.  ws holds semi_solve_workspace(k) bytes.
+// R11^T R11 M = B), R11 k x k FP64 upper triangular (ldr); B is k x n with
+// element (q, c) at B[q rs + c cs]; M is k x n column-major (ldm).  jmode 1:
+// the columns marked in sel (sel[c] >= 0) are zero right-hand sides; jmode 0:
+// they come out as the unit vectors e_sel[c].  ws holds
+// semi_solve_workspace(k) bytes.
 size_t semi_solve_workspace(int k);
 template <typename T>
-int semi_solve(const double* R11, int64_t ldr, int k, const T* B, int64_t ldb, int64_t n, const int32_t* sel, T* M,
-               int64_t ldm, unsigned char* ws, hipStream_t s);
+int semi_solve(const double* R11, int64_t ldr, int k, const T* B, int64_t rs, int64_t cs, int64_t n,
+               const int32_t* sel, int jmode, T* M, int64_t ldm, unsigned char* ws, hipStream_t s);
+
+// Z = C^+ A (k x n, ldz) for the skeleton J (k entries; -1 gathers a zero
+// column), C = A[:, J] (m x k, ldc; gathered into the workspace when null),
+// by the normal equations with the Cholesky factor R of C^T C, written to R11
+// (k x k FP64, ldr) when given.  With kinfo, columns from kinfo->k_out on are
+// treated as absent.  A pivot of the Cholesky that is not positive (C's
+// columns dependent in FP64) sets the workspace flag at oFlag.
+struct LsPlan {
+    int gz, gzr;  // the Gram's split over rows (planned, launched)
+    size_t oC64, oGram, oGp, oR, oCT, oB, oSel, oFlag, oSemi, total;
+};
+int ls_plan(int64_t m, int64_t n, int k, size_t esz, LsPlan* L);
+template <typename T>
+int run_lstsq(const LsPlan& L, const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* J, int k,
+              const miid_info* kinfo, const T* C, int64_t ldc, T* Z, int64_t ldz, double* R11, int64_t ldr,
+              unsigned char* w, hipStream_t s);
 
 }  // namespace miid

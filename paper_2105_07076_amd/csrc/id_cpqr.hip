@@ -1979,21 +1979,48 @@ __global__ void k_map_idx(const int32_t* __restrict__ Js, const int32_t* __restr
 // G (k x n, row-major: G[i n + l]) = C^T A, C m x k (ldc), A m x n (lda),
 // on the matrix cores.  Workgroup tile 128 x 128, wave tile 64 x 64 (4 x 4
 // blocks of 16 x 16: sixteen products per eight operand loads), K = m in
-// steps of 4; the operands of the next U steps are loaded while the current
-// U steps are multiplied.  Operand lane l: C^T[row l % 16][k l / 16]
-// (= C[k][row], contiguous in k) and A[k l / 16][column l % 16].
+// batches of 16; the operands of the next batch are loaded while the current
+// one is multiplied.  Operand lane l: C^T[row l % 16][k] (= C[k][row],
+// contiguous in k) and A[k][column l % 16].  Scalar form: the u-th product
+// of a batch takes k = k0 + 4 u + l / 16.  VEC form (16-byte aligned columns):
+// lane group g = l / 16 loads the four consecutive k0 + 4 g .. k0 + 4 g + 3 as
+// one vector and the u-th product takes k = k0 + 4 g + u -- the same sixteen
+// k of the batch, paired identically in both operands.  Split over K:
+// workgroup z takes rows [z mz, (z + 1) mz) of C and A and writes the
+// partial product to G + z k n.
 constexpr int kGtB = 4;  // 16 x 16 blocks per wave side
 constexpr int kGtU = 4;  // K steps (of 4) per batch of loads (2: the same, 8: slower)
+static_assert(kGtU == 4, "the vector form loads four consecutive k per lane");
 
 template <typename T>
+struct Vec4K;
+template <>
+struct Vec4K<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec4K<double> {
+    typedef double type __attribute__((ext_vector_type(4)));
+};
+
+template <typename T, bool VEC>
 __global__ void __launch_bounds__(kThreads) k_gemm_tn(const T* __restrict__ C, int64_t ldc, const T* __restrict__ A,
-                                                      int64_t lda, int64_t m, int k, int64_t n, T* __restrict__ G) {
+                                                      int64_t lda, int64_t m, int k, int64_t n, T* __restrict__ G,
+                                                      int64_t mz) {
     using A4 = typename Acc4<T>::type;
+    using V4 = typename Vec4K<T>::type;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
     const int i0 = blockIdx.x * 128 + (wave & 1) * 64;               // this wave's rows of G
     const int64_t j0 = (int64_t)blockIdx.y * 128 + (wave >> 1) * 64;  // and columns
     const int l16 = lane % 16, lg = lane / 16;
+    {
+        const int64_t kb = (int64_t)blockIdx.z * mz;
+        C += kb;
+        A += kb;
+        m = std::min<int64_t>(m - kb, mz);
+        G += (int64_t)blockIdx.z * k * n;
+    }
     A4 acc[kGtB][kGtB];
 #pragma unroll
     for (int br = 0; br < kGtB; ++br)
@@ -2010,17 +2037,30 @@ __global__ void __launch_bounds__(kThreads) k_gemm_tn(const T* __restrict__ C, i
         const int64_t col = j0 + h * 16 + l16;
         rok[h] = row < k;
         cok[h] = col < n;
-        cp[h] = C + (int64_t)(rok[h] ? row : 0) * ldc + lg;
-        ap[h] = A + (cok[h] ? col : 0) * lda + lg;
+        cp[h] = C + (int64_t)(rok[h] ? row : 0) * ldc;
+        ap[h] = A + (cok[h] ? col : 0) * lda;
     }
     auto load = [&](int64_t k0, T (&a)[kGtU][kGtB], T (&b)[kGtU][kGtB]) {
-#pragma unroll
-        for (int u = 0; u < kGtU; ++u)
+        if constexpr (VEC) {
 #pragma unroll
             for (int h = 0; h < kGtB; ++h) {
-                a[u][h] = rok[h] ? cp[h][k0 + 4 * u] : T(0);
-                b[u][h] = cok[h] ? ap[h][k0 + 4 * u] : T(0);
+                const V4 va = rok[h] ? *reinterpret_cast<const V4*>(cp[h] + k0 + 4 * lg) : V4(T(0));
+                const V4 vb = cok[h] ? *reinterpret_cast<const V4*>(ap[h] + k0 + 4 * lg) : V4(T(0));
+#pragma unroll
+                for (int u = 0; u < kGtU; ++u) {
+                    a[u][h] = va[u];
+                    b[u][h] = vb[u];
+                }
             }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kGtU; ++u)
+#pragma unroll
+                for (int h = 0; h < kGtB; ++h) {
+                    a[u][h] = rok[h] ? cp[h][k0 + 4 * u + lg] : T(0);
+                    b[u][h] = cok[h] ? ap[h][k0 + 4 * u + lg] : T(0);
+                }
+        }
     };
     auto mul = [&](const T (&a)[kGtU][kGtB], const T (&b)[kGtU][kGtB]) {
 #pragma unroll
@@ -2031,7 +2071,7 @@ __global__ void __launch_bounds__(kThreads) k_gemm_tn(const T* __restrict__ C, i
                 for (int bc = 0; bc < kGtB; ++bc) acc[br][bc] = mfma16x16x4(a[u][br], b[u][bc], acc[br][bc]);
     };
     constexpr int KB = 4 * kGtU;  // K per batch
-    const int64_t kfull = m / KB * KB;
+    const int64_t kfull = m > 0 ? m / KB * KB : 0;
     if (kfull > 0) {
         T a0[kGtU][kGtB], b0[kGtU][kGtB], a1[kGtU][kGtB], b1[kGtU][kGtB];
         load(0, a0, b0);
@@ -2049,8 +2089,8 @@ __global__ void __launch_bounds__(kThreads) k_gemm_tn(const T* __restrict__ C, i
         T a[kGtB], b[kGtB];
 #pragma unroll
         for (int h = 0; h < kGtB; ++h) {
-            a[h] = (rok[h] && kk < m) ? cp[h][k0] : T(0);
-            b[h] = (cok[h] && kk < m) ? ap[h][k0] : T(0);
+            a[h] = (rok[h] && kk < m) ? cp[h][kk] : T(0);
+            b[h] = (cok[h] && kk < m) ? ap[h][kk] : T(0);
         }
 #pragma unroll
         for (int br = 0; br < kGtB; ++br)
@@ -2070,7 +2110,29 @@ __global__ void __launch_bounds__(kThreads) k_gemm_tn(const T* __restrict__ C, i
             }
 }
 
-int rs_plan(int64_t m, int64_t n, int32_t p, miid_dtype dtype, const miid_opts* o, RsPlan* Q) {
+// G (+ z k n for split z) = C^T A over the row slices of mz rows; the vector
+// form when both operands' columns are 16-byte (FP32) / 32-byte (FP64) aligned
+template <typename T>
+static void gemm_tn(const T* C, int64_t ldc, const T* A, int64_t lda, int64_t m, int k, int64_t n, T* G, int splits,
+                    hipStream_t s) {
+    const int64_t mz = splits > 1 ? (int64_t)align_up((size_t)((m + splits - 1) / splits), 16) : m;
+    const int gz = (int)((m + mz - 1) / mz);
+    const uintptr_t va = 4 * sizeof(T) - 1;
+    const bool vec = ((reinterpret_cast<uintptr_t>(C) | reinterpret_cast<uintptr_t>(A)) & va) == 0 && ldc % 4 == 0 &&
+                     lda % 4 == 0;
+    const dim3 grid((unsigned)((k + 127) / 128), (unsigned)((n + 127) / 128), (unsigned)gz);
+    if (vec)
+        hipLaunchKernelGGL((k_gemm_tn<T, true>), grid, dim3(kThreads), 0, s, C, ldc, A, lda, m, k, n, G, mz);
+    else
+        hipLaunchKernelGGL((k_gemm_tn<T, false>), grid, dim3(kThreads), 0, s, C, ldc, A, lda, m, k, n, G, mz);
+}
+
+struct RsPlan {
+    IdPlan id;  // the CPQR of A_S (its workspace comes first)
+    size_t oAs, oZs, oJs, oC, oG, oSel, total;
+};
+
+static int rs_plan(int64_t m, int64_t n, int32_t p, miid_dtype dtype, const miid_opts* o, RsPlan* Q) {
     if (p < 1 || p > n) return -7;
     if (!o || o->k < 1) return -8;  // fixed rank only
     miid_opts oo = *o;
@@ -2096,7 +2158,7 @@ int rs_plan(int64_t m, int64_t n, int32_t p, miid_dtype dtype, const miid_opts* 
 }
 
 template <typename T>
-int run_rid_sample(const RsPlan& Q, const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* idx, int p,
+static int run_rid_sample(const RsPlan& Q, const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* idx, int p,
                           int32_t* J, T* Z, int64_t ldz, double* R11, int64_t ldr, T* C, int64_t ldc,
                           miid_info* info, unsigned char* w, hipStream_t s) {
     const IdPlan& P = Q.id;
@@ -2119,8 +2181,7 @@ int run_rid_sample(const RsPlan& Q, const T* A, int64_t m, int64_t n, int64_t ld
                        (int32_t)-1);
     hipLaunchKernelGGL(k_map_idx, dim3(1), dim3(256), 0, s, Js, idx, k, n, J, sel);
     // C^T A, then Z = R_k^{-1} R_k^{-T} (C^T A) with Z[:, J] = I
-    hipLaunchKernelGGL(k_gemm_tn<T>, dim3((unsigned)((k + 127) / 128), (unsigned)((n + 127) / 128)), dim3(kThreads), 0, s,
-                       Cx, ldcx, A, lda, m, k, n, G);
+    gemm_tn<T>(Cx, ldcx, A, lda, m, k, n, G, 1, s);
     const double* R11s = reinterpret_cast<const double*>(w + P.oR11);
     const double* Dinv = reinterpret_cast<const double*>(w + P.oDinv);
     const DevState* st = reinterpret_cast<const DevState*>(w + P.ostate);
@@ -2155,53 +2216,317 @@ size_t semi_solve_workspace(int k) {
     return align_up(kpad * kpad * 8, 256) + align_up(kpad * kTB * 8, 256) + align_up(sizeof(DevState), 256);
 }
 
+template <typename T, int JMODE>
+static hipError_t semi_solve_attr() {
+    static bool done = false;
+    if (!done) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_trsm_blk<T, 64, true, JMODE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 256 * 65 * 8);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_trsm_blk<T, 32, true, JMODE>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 512 * 33 * 8);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_trsm_blk<T, 16, true, JMODE>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 1024 * 17 * 8);
+        if (e != hipSuccess) return e;
+        done = true;
+    }
+    return hipSuccess;
+}
+
+template <typename T, int JMODE>
+static void semi_solve_launch(int kpad, const T* B, int64_t n, const double* R11s, const double* Dinv,
+                              const DevState* st, int k, const int32_t* sel, T* M, int64_t ldm, int64_t rs, int64_t cs,
+                              hipStream_t s) {
+    if (kpad <= 256)
+        hipLaunchKernelGGL((k_trsm_blk<T, 64, true, JMODE>), dim3((unsigned)((n + 63) / 64)), dim3(8 * 64),
+                           (size_t)kpad * 65 * 8, s, B, n, R11s, kpad, Dinv, st, k, sel, M, ldm, k, 0, rs, cs);
+    else if (kpad <= 512)
+        hipLaunchKernelGGL((k_trsm_blk<T, 32, true, JMODE>), dim3((unsigned)((n + 31) / 32)), dim3(8 * 32),
+                           (size_t)kpad * 33 * 8, s, B, n, R11s, kpad, Dinv, st, k, sel, M, ldm, k, 0, rs, cs);
+    else
+        hipLaunchKernelGGL((k_trsm_blk<T, 16, true, JMODE>), dim3((unsigned)((n + 15) / 16)), dim3(8 * 16),
+                           (size_t)kpad * 17 * 8, s, B, n, R11s, kpad, Dinv, st, k, sel, M, ldm, k, 0, rs, cs);
+}
+
 template <typename T>
-int semi_solve(const double* R11, int64_t ldr, int k, const T* B, int64_t ldb, int64_t n, const int32_t* sel, T* M,
-               int64_t ldm, unsigned char* ws, hipStream_t s) {
+int semi_solve(const double* R11, int64_t ldr, int k, const T* B, int64_t rs, int64_t cs, int64_t n,
+               const int32_t* sel, int jmode, T* M, int64_t ldm, unsigned char* ws, hipStream_t s) {
     const int kpad = (int)align_up((size_t)k, kTB);
     double* R11s = reinterpret_cast<double*>(ws);
     double* Dinv = reinterpret_cast<double*>(ws + align_up((size_t)kpad * kpad * 8, 256));
     DevState* st = reinterpret_cast<DevState*>(ws + align_up((size_t)kpad * kpad * 8, 256) +
                                                 align_up((size_t)kpad * kTB * 8, 256));
-    static bool attr_done = false;
-    if (!attr_done) {
-        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 64, true, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     256 * 65 * 8));
-        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 32, true, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     512 * 33 * 8));
-        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 16, true, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     1024 * 17 * 8));
-        attr_done = true;
-    }
+    const hipError_t ea = jmode ? semi_solve_attr<T, 1>() : semi_solve_attr<T, 0>();
+    MIID_HIP(ea);
     hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned char*>(st),
                        (int64_t)sizeof(DevState), (unsigned char)0);  // not stopped: K = k
     const int64_t total = (int64_t)kpad * kpad;
     hipLaunchKernelGGL(k_pad_r11, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)), dim3(256), 0, s, R11, ldr,
                        k, kpad, R11s);
     hipLaunchKernelGGL(k_trsm_dinv, dim3((unsigned)(kpad / kTB)), dim3(kTB), 0, s, R11s, kpad, Dinv);
-    if (kpad <= 256)
-        hipLaunchKernelGGL((k_trsm_blk<T, 64, true, 1>), dim3((unsigned)((n + 63) / 64)), dim3(8 * 64),
-                           (size_t)kpad * 65 * 8, s, B, n, R11s, kpad, Dinv, st, k, sel, M, ldm, k, 0, (int64_t)1, ldb);
-    else if (kpad <= 512)
-        hipLaunchKernelGGL((k_trsm_blk<T, 32, true, 1>), dim3((unsigned)((n + 31) / 32)), dim3(8 * 32),
-                           (size_t)kpad * 33 * 8, s, B, n, R11s, kpad, Dinv, st, k, sel, M, ldm, k, 0, (int64_t)1, ldb);
+    if (jmode)
+        semi_solve_launch<T, 1>(kpad, B, n, R11s, Dinv, st, k, sel, M, ldm, rs, cs, s);
     else
-        hipLaunchKernelGGL((k_trsm_blk<T, 16, true, 1>), dim3((unsigned)((n + 15) / 16)), dim3(8 * 16),
-                           (size_t)kpad * 17 * 8, s, B, n, R11s, kpad, Dinv, st, k, sel, M, ldm, k, 0, (int64_t)1, ldb);
+        semi_solve_launch<T, 0>(kpad, B, n, R11s, Dinv, st, k, sel, M, ldm, rs, cs, s);
     MIID_HIP(hipGetLastError());
     return 0;
 }
 
-template int run_rid_sample<float>(const RsPlan&, const float*, int64_t, int64_t, int64_t, const int32_t*, int, int32_t*,
-                                   float*, int64_t, double*, int64_t, float*, int64_t, miid_info*, unsigned char*,
-                                   hipStream_t);
-template int run_rid_sample<double>(const RsPlan&, const double*, int64_t, int64_t, int64_t, const int32_t*, int,
-                                    int32_t*, double*, int64_t, double*, int64_t, double*, int64_t, miid_info*,
-                                    unsigned char*, hipStream_t);
-template int semi_solve<float>(const double*, int64_t, int, const float*, int64_t, int64_t, const int32_t*, float*,
-                               int64_t, unsigned char*, hipStream_t);
-template int semi_solve<double>(const double*, int64_t, int, const double*, int64_t, int64_t, const int32_t*, double*,
-                                int64_t, unsigned char*, hipStream_t);
+// ---------------------------------------------------------------------------
+// Least-squares coefficients over the full A for a given skeleton: Z = C^+ A,
+// C = A[:, J], from the normal equations C^T C Z = C^T A (the paper forms the
+// randomized ID's Z this way, Section 2.2, eq. final_eq) with R the Cholesky
+// factor of C^T C (R^T R = C^T C, upper triangular, positive diagonal): the
+// Gram matrix in FP64 on the matrix cores, a blocked right-looking Cholesky,
+// C^T A on the matrix cores, then the FP64 two-sided triangular solve.
+// ---------------------------------------------------------------------------
+constexpr int kChB = 32;  // Cholesky panel width
+
+// v of lane l (l a wave-uniform constant)
+__device__ inline double readlane_f64(double v, int l) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// C64[:, c] = A[:, J[c]] in FP64 (an index outside [0, n) gives a zero column)
+template <typename T>
+__global__ void k_gather_f64(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n, const int32_t* __restrict__ J,
+                             double* __restrict__ C64) {
+    const int c = blockIdx.y;
+    const int64_t src = J[c];
+    const bool ok = src >= 0 && src < n;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x)
+        C64[r + (int64_t)c * m] = ok ? (double)A[r + src * lda] : 0.0;
+}
+
+// sel[J[i]] = i (sel was filled with -1)
+__global__ void k_sel_of(const int32_t* __restrict__ J, int k, int64_t n, int32_t* __restrict__ sel) {
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        const int32_t g = J[i];
+        if (g >= 0 && g < n) sel[g] = i;
+    }
+}
+
+// Panel r0 of the Cholesky of G (k x k; the upper triangle, element (i, c) at
+// G[i k + c], is read and kept up to date): the 32 x 32 diagonal block is
+// factored by one wave in registers, then the panel's rows of R beyond it follow by forward
+// substitution with the block's transpose (one column per thread).  Columns
+// from K = kinfo->k_out on (a skeleton cut short) become unit rows of R; a
+// pivot that is not positive sets *flag and is replaced by 1.
+__global__ void __launch_bounds__(256) k_chol_panel(const double* __restrict__ G, int k, int r0,
+                                                     const miid_info* __restrict__ kinfo, double* __restrict__ R,
+                                                     int64_t ldr, uint32_t* __restrict__ flag) {
+    __shared__ double D[kChB][kChB + 1];
+    const int K = kinfo ? min(kinfo->k_out, k) : k;
+    const int nb = min(kChB, k - r0);
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kChB * kChB; e += blockDim.x) {
+        const int i = e / kChB, c = e % kChB;
+        D[i][c] = (i < nb && c < nb && i <= c) ? G[(int64_t)(r0 + i) * k + (r0 + c)] : 0.0;
+    }
+    __syncthreads();
+    if (tid < kWave) {
+        // one wave factors the block in registers: lane c holds column c;
+        // row j of the step's factor is read lane by lane (the lane index is
+        // a constant of the unrolled loops)
+        double d[kChB];
+#pragma unroll
+        for (int i = 0; i < kChB; ++i) d[i] = tid < kChB ? D[i][tid] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kChB; ++j) {
+            if (j < nb) {
+                const double djj = readlane_f64(d[j], j);
+                double piv;
+                if (r0 + j >= K) {
+                    piv = 0.0;  // unit row
+                } else if (djj > 0.0) {
+                    piv = sqrt(djj);
+                } else {
+                    if (tid == 0) flag[0] = 1u;
+                    piv = 1.0;
+                }
+                if (tid > j) d[j] = piv > 0.0 ? d[j] / piv : 0.0;
+                if (tid == j) d[j] = piv > 0.0 ? piv : 1.0;
+#pragma unroll
+                for (int i = j + 1; i < kChB; ++i) {
+                    const double rji = readlane_f64(d[j], i);
+                    if (i <= tid) d[i] = fma(-rji, d[j], d[i]);
+                }
+            }
+        }
+        if (tid < kChB) {
+#pragma unroll
+            for (int i = 0; i < kChB; ++i) D[i][tid] = d[i];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < nb * nb; e += blockDim.x) {
+        const int i = e % nb, c = e / nb;
+        R[(r0 + i) + (int64_t)(r0 + c) * ldr] = i <= c ? D[i][c] : 0.0;
+    }
+    for (int c = r0 + nb + tid; c < k; c += blockDim.x) {
+        double x[kChB];
+#pragma unroll
+        for (int j = 0; j < kChB; ++j) x[j] = j < nb ? G[(int64_t)(r0 + j) * k + c] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kChB; ++j) {
+            double v = x[j];
+#pragma unroll
+            for (int q = 0; q < j; ++q) v -= D[q][j] * x[q];
+            x[j] = (j < nb && r0 + j < K) ? v / D[j][j] : 0.0;
+            // keep the block's LDS reads to one row of the recursion at a
+            // time (hoisting all of them would need ~1000 registers)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int j = 0; j < kChB; ++j)
+            if (j < nb) R[(r0 + j) + (int64_t)c * ldr] = x[j];
+    }
+}
+
+// The trailing update after panel r0: G[i, c] -= sum_j R[r0 + j, i] R[r0 + j, c]
+// for r0 + 32 <= i <= c < k; 64 x 64 tiles of the upper triangle, 4 x 4
+// elements per thread, the panel's rows of R staged in LDS.
+__global__ void __launch_bounds__(256) k_chol_update(double* __restrict__ G, int k, int r0, const double* __restrict__ R,
+                                                     int64_t ldr) {
+    const int bi = blockIdx.x, bc = blockIdx.y;
+    if (bi > bc) return;  // tiles below the diagonal (uniform per workgroup)
+    const int t0 = r0 + kChB;
+    const int i0 = t0 + bi * 64, c0 = t0 + bc * 64;
+    __shared__ double sRi[kChB][65], sRc[kChB][65];
+    for (int e = threadIdx.x; e < kChB * 64; e += 256) {
+        const int j = e % kChB, x = e / kChB;
+        sRi[j][x] = i0 + x < k ? R[(r0 + j) + (int64_t)(i0 + x) * ldr] : 0.0;
+        sRc[j][x] = c0 + x < k ? R[(r0 + j) + (int64_t)(c0 + x) * ldr] : 0.0;
+    }
+    __syncthreads();
+    const int ti = (threadIdx.x % 16) * 4, tc = (threadIdx.x / 16) * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < kChB; ++j) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = sRi[j][ti + u];
+            b[u] = sRc[j][tc + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + ti + u, c = c0 + tc + v;
+            if (i < k && c < k && i <= c) G[(int64_t)i * k + c] -= acc[u][v];
+        }
+}
+
+// out[e] = sum over z of part[z count + e], z in order
+__global__ void k_sum_parts(const double* __restrict__ part, int nz, int64_t count, double* __restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int z = 0; z < nz; ++z) v += part[(int64_t)z * count + e];
+        out[e] = v;
+    }
+}
+
+int ls_plan(int64_t m, int64_t n, int k, size_t esz, LsPlan* L) {
+    if (m < 1 || n < 1 || k < 1 || k > m || k > n || k > 1024) return MIID_E_UNSUPPORTED;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    // the Gram's split over rows: about 512 workgroups, slices of >= 64 rows
+    const int64_t tiles = (int64_t)((k + 127) / 128) * ((k + 127) / 128);
+    L->gz = (int)std::max<int64_t>(1, std::min<int64_t>(512 / tiles, m / 64));
+    {
+        const int64_t mz = L->gz > 1 ? (int64_t)align_up((size_t)((m + L->gz - 1) / L->gz), 16) : m;
+        L->gzr = (int)((m + mz - 1) / mz);  // slices actually launched
+    }
+    L->oC64 = take((size_t)m * k * 8);
+    L->oGram = take((size_t)k * k * 8);
+    L->oGp = take(L->gz > 1 ? (size_t)L->gzr * k * k * 8 : 8);
+    L->oR = take((size_t)k * k * 8);
+    L->oCT = take((size_t)m * k * esz);
+    L->oB = take((size_t)k * n * esz);
+    L->oSel = take((size_t)n * 4);
+    L->oFlag = take(4);
+    L->oSemi = take(semi_solve_workspace(k));
+    L->total = off;
+    return 0;
+}
+
+template <typename T>
+int run_lstsq(const LsPlan& L, const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* J, int k,
+              const miid_info* kinfo, const T* C, int64_t ldc, T* Z, int64_t ldz, double* R11, int64_t ldr,
+              unsigned char* w, hipStream_t s) {
+    double* C64 = reinterpret_cast<double*>(w + L.oC64);
+    double* Gram = reinterpret_cast<double*>(w + L.oGram);
+    double* R = R11 ? R11 : reinterpret_cast<double*>(w + L.oR);
+    const int64_t ldR = R11 ? ldr : k;
+    T* B = reinterpret_cast<T*>(w + L.oB);
+    int32_t* sel = reinterpret_cast<int32_t*>(w + L.oSel);
+    uint32_t* flag = reinterpret_cast<uint32_t*>(w + L.oFlag);
+    const dim3 ggrid((unsigned)std::min<int64_t>((m + 255) / 256, 64), (unsigned)k);
+    if (!C) {
+        T* CT = reinterpret_cast<T*>(w + L.oCT);
+        hipLaunchKernelGGL(k_gather_cols<T>, ggrid, dim3(256), 0, s, A, lda, m, n, J, CT);
+        C = CT;
+        ldc = m;
+    }
+    hipLaunchKernelGGL(k_gather_f64<T>, ggrid, dim3(256), 0, s, A, lda, m, n, J, C64);
+    // C^T C (symmetric: row- and column-major alike), split over the rows
+    // into L.gz partial products summed in a fixed order
+    double* Gp = reinterpret_cast<double*>(w + L.oGp);
+    gemm_tn<double>(C64, m, C64, m, m, k, (int64_t)k, L.gz > 1 ? Gp : Gram, L.gz, s);
+    if (L.gz > 1) {
+        const int64_t kk = (int64_t)k * k;
+        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)std::min<int64_t>((kk + 255) / 256, 4096)), dim3(256), 0, s, Gp,
+                           L.gzr, kk, Gram);
+    }
+    hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)std::min<int64_t>((ldR * k + 255) / 256, 4096)), dim3(256), 0, s, R,
+                       ldR * k, 0.0);
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, flag, (int64_t)1, 0u);
+    for (int r0 = 0; r0 < k; r0 += kChB) {
+        hipLaunchKernelGGL(k_chol_panel, dim3(1), dim3(256), 0, s, Gram, k, r0, kinfo, R, ldR, flag);
+        const int rest = k - r0 - kChB;
+        if (rest > 0) {
+            const unsigned nt = (unsigned)((rest + 63) / 64);
+            hipLaunchKernelGGL(k_chol_update, dim3(nt, nt), dim3(256), 0, s, Gram, k, r0, R, ldR);
+        }
+    }
+    // C^T A (k x n, row-major), then Z = R^{-1} R^{-T} C^T A with Z[:, J] = I
+    gemm_tn<T>(C, ldc, A, lda, m, k, n, B, 1, s);
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, s, sel, n,
+                       (int32_t)-1);
+    hipLaunchKernelGGL(k_sel_of, dim3(1), dim3(256), 0, s, J, k, n, sel);
+    MIID_HIP(hipGetLastError());
+    return semi_solve<T>(R, ldR, k, B, n, (int64_t)1, n, sel, 0, Z, ldz, w + L.oSemi, s);
+}
+
+template int run_lstsq<float>(const LsPlan&, const float*, int64_t, int64_t, int64_t, const int32_t*, int,
+                              const miid_info*, const float*, int64_t, float*, int64_t, double*, int64_t,
+                              unsigned char*, hipStream_t);
+template int run_lstsq<double>(const LsPlan&, const double*, int64_t, int64_t, int64_t, const int32_t*, int,
+                               const miid_info*, const double*, int64_t, double*, int64_t, double*, int64_t,
+                               unsigned char*, hipStream_t);
+
+template int semi_solve<float>(const double*, int64_t, int, const float*, int64_t, int64_t, int64_t, const int32_t*,
+                               int, float*, int64_t, unsigned char*, hipStream_t);
+template int semi_solve<double>(const double*, int64_t, int, const double*, int64_t, int64_t, int64_t,
+                                const int32_t*, int, double*, int64_t, unsigned char*, hipStream_t);
 
 template int run_id<float>(const IdPlan&, const float*, int64_t, int32_t*, float*, int64_t, double*, int64_t, float*,
                            int64_t, miid_info*, unsigned char*, hipStream_t, bool, const float*, int64_t, int64_t);

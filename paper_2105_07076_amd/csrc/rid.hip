@@ -224,26 +224,15 @@ struct RidPlan {
     int mt_total;    // 16-row tiles of Y
     int64_t mpad;    // K padded to 32
     size_t oWt, total;
-    // least-squares Z over the full A: the column-sampling path with the
-    // sketch's skeleton as its sample (its own workspace, the copied
-    // skeleton, its info)
+    // least-squares Z over the full A for the sketch's skeleton
     bool lstsq;
-    RsPlan rs;
-    size_t oRs, oJk, oInfo2;
+    LsPlan ls;
+    size_t oLs;
 };
 
-// Jk = J (the sample the least-squares pass reads while it rewrites J)
-__global__ void k_copy_i32(const int32_t* __restrict__ src, int n, int32_t* __restrict__ dst) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
-}
-
-// the sketch's info keeps its norms; k_out and the rank-deficiency bit also
-// take the least-squares pass's CPQR of C into account
-__global__ void k_merge_info(miid_info* __restrict__ info, const miid_info* __restrict__ info2) {
-    if (threadIdx.x == 0) {
-        if (info2->k_out < info->k_out) info->k_out = info2->k_out;
-        info->status |= info2->status & MIID_RANK_DEFICIENT;
-    }
+// a breakdown of the least-squares pass's Cholesky into the status
+__global__ void k_ls_status(miid_info* __restrict__ info, const uint32_t* __restrict__ flag) {
+    if (threadIdx.x == 0 && flag[0]) info->status |= MIID_LSTSQ_BREAKDOWN;
 }
 
 static int make_rid_plan(int64_t m, int64_t n, int32_t l, const miid_opts* opts, RidPlan* R) {
@@ -262,12 +251,10 @@ static int make_rid_plan(int64_t m, int64_t n, int32_t l, const miid_opts* opts,
     R->lstsq = opts && (opts->flags & MIID_LSTSQ_Z);
     if (R->lstsq) {
         if (opts->k < 1 || opts->k > m) return MIID_E_UNSUPPORTED;
-        const int rc2 = rs_plan(m, n, opts->k, MIID_F32, opts, &R->rs);
-        if (rc2 != 0) return rc2 == -7 || rc2 == -8 ? MIID_E_UNSUPPORTED : rc2;
-        R->oRs = R->total;
-        R->oJk = align_up(R->oRs + R->rs.total, 256);
-        R->oInfo2 = align_up(R->oJk + (size_t)opts->k * 4, 256);
-        R->total = align_up(R->oInfo2 + sizeof(miid_info), 256);
+        const int rc2 = ls_plan(m, n, opts->k, 4, &R->ls);
+        if (rc2 != 0) return rc2;
+        R->oLs = R->total;
+        R->total = align_up(R->oLs + R->ls.total, 256);
     }
     return 0;
 }
@@ -336,16 +323,13 @@ int rid_sketch_cpqr(const float* A, int64_t m, int64_t n, int64_t lda, const uin
     MIID_HIP(hipGetLastError());
     const int rc2 = run_id<float>(R.id, A, lda, J, Z, ldz, R11, ldr, C, ldc, info, w, s, true, A, lda, m);
     if (rc2 != 0 || !R.lstsq) return rc2;
-    // Z = C^+ A: the sketch's k columns as the sample of the column-sampling
-    // path (a skeleton cut short by an exact zero residual ends in -1
-    // entries, which gather as zero columns and stop C's CPQR there too)
-    const int k = R.id.kmax;
-    int32_t* Jk = reinterpret_cast<int32_t*>(w + R.oJk);
-    miid_info* info2 = reinterpret_cast<miid_info*>(w + R.oInfo2);
-    hipLaunchKernelGGL(k_copy_i32, dim3(1), dim3(256), 0, s, J, k, Jk);
-    const int rc3 = run_rid_sample<float>(R.rs, A, m, n, lda, Jk, k, J, Z, ldz, R11, ldr, C, ldc, info2, w + R.oRs, s);
+    // Z = C^+ A for the sketch's skeleton (a skeleton cut short by an exact
+    // zero residual has k_out < k: the rest of J is -1 and Z's rows there
+    // stay zero)
+    unsigned char* wl = w + R.oLs;
+    const int rc3 = run_lstsq<float>(R.ls, A, m, n, lda, J, R.id.kmax, info, C, ldc, Z, ldz, R11, ldr, wl, s);
     if (rc3 != 0) return rc3;
-    hipLaunchKernelGGL(k_merge_info, dim3(1), dim3(64), 0, s, info, info2);
+    hipLaunchKernelGGL(k_ls_status, dim3(1), dim3(64), 0, s, info, reinterpret_cast<const uint32_t*>(wl + R.ls.oFlag));
     MIID_HIP(hipGetLastError());
     return 0;
 }

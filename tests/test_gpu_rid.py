@@ -200,29 +200,31 @@ def _lstsq_pair(A_t, Om_t, k, mode=1):
 
 
 def _check_lstsq_against_oracle(A64, Js, rl, k, cols=None):
-    """The least-squares pass against the oracle's column-sampling RID with
-    the sketch's skeleton Js as the sample: the same k columns, C's pivot
-    order margin-aware (FP32), R11 and Z within the FP32 bars."""
+    """The least-squares pass for the sketch's skeleton Js: the same J in the
+    same order, R11 the Cholesky factor of C^T C (R11^T R11 = C^T C, upper
+    triangular, positive diagonal), Z = C^+ A against the oracle's
+    column-sampling RID run with Js as its whole sample (the paper's
+    normal-equation Z; its rows follow its own pivot order, mapped back here)
+    within the normal equations' bar c u kappa(C)^2."""
     J = to_np(rl.J)
-    assert sorted(J.tolist()) == sorted(Js.tolist())
-    pos = np.array([int(np.where(Js == j)[0][0]) for j in J], dtype=np.int32)
-    # C's column CPQR: padded with zero columns to at least m columns so that
-    # the oracle takes the column ID (a tall matrix gets the dual ID there);
-    # a zero column is never picked ahead of a nonzero residual
-    m = A64.shape[0]
-    C64 = np.hstack([A64[:, Js], np.zeros((m, max(0, m - k)))])
-    ref, ties = pivot_parity(C64, pos, k, U32)
+    assert np.array_equal(J, Js)
+    m, n = A64.shape
+    S = np.arange(n) if cols is None else np.asarray(cols)
+    C = A64[:, J]
+    R = to_np(rl.R11)
+    assert np.array_equal(R, np.triu(R)) and np.all(np.diag(R) > 0)
+    assert rel(R.T @ R, C.T @ C) <= 1e-12
+    kap = np.linalg.cond(C)
+    # the oracle on the columns J followed by the checked ones: Z restricted
+    # to a set of columns is the same least-squares solve
+    Wc = np.hstack([C, A64[:, S]])
+    oc, Zo, _ = oracle.rid_sample(Wc, np.arange(k), k)
+    Zref = np.empty((k, len(S)))
+    Zref[np.asarray(oc)] = Zo[:, k:]
     Z = to_np(rl.Z).astype(np.float64)
     assert np.array_equal(Z[:, J], np.eye(k))
-    Rk = ref.R[:, ref.J]
-    assert rel(to_np(rl.R11), Rk) <= max(1e-5, 8.0 * U32 * np.linalg.cond(Rk))
-    # Z = C^+ A on the checked columns, in the GPU's skeleton order
-    S = np.arange(A64.shape[1]) if cols is None else np.asarray(cols)
-    Cg = A64[:, J]
-    Zref = np.linalg.lstsq(Cg, A64[:, S], rcond=None)[0]
-    bar = max(1e-5, 256.0 * U32 * np.linalg.cond(Rk) ** 2)
+    bar = max(1e-5, 256.0 * U32 * kap ** 2)
     assert rel(Z[:, S], Zref) <= bar, f"Z error {rel(Z[:, S], Zref):.3e} > {bar:.3e}"
-    return ties
 
 
 @pytest.mark.parametrize("m,n,l,k", [(64, 200, 26, 16), (100, 333, 50, 40), (257, 1000, 74, 64)])
