@@ -85,9 +85,9 @@ def time_id(miid_api, lib, A, k, steps, warmup, sample_every=7):
 GEMV_TRAFFIC = {
     "bytes_per_launch": 532.1e6,
     "sources": {
-        "paper_2105_07076_amd/csrc/id_cpqr.hip": "2dfd0c3561d0a6a36af218de640d08e523754dfe32b0a978e15de5d61198570f",
+        "paper_2105_07076_amd/csrc/id_cpqr.hip": "5a0a6e9be1711371ec7867f3cc8036036d3a207aa33bfec834b3ec41e9f3daad",
         "paper_2105_07076_amd/csrc/common.hpp": "77e3f522d4607da471046f7b4d08b5688ce5617e1b620ace976254481bb74ae8",
-        "paper_2105_07076_amd/csrc/cpqr.hpp": "e002806934b941a7b8c686698d55d3e93423adffd1eefd46e79fcbc23b7204ff",
+        "paper_2105_07076_amd/csrc/cpqr.hpp": "c5af1863f13e79013f7e57c2d630a8f7b6596f8e47994e4c871b31b405454bf3",
     },
 }
 

@@ -57,11 +57,11 @@ int semi_solve(const double* R11, int64_t ldr, int k, const T* B, int64_t rs, in
                const int32_t* sel, int jmode, T* M, int64_t ldm, unsigned char* ws, hipStream_t s);
 
 // Z = C^+ A (k x n, ldz) for the skeleton J (k entries; -1 gathers a zero
-// column), C = A[:, J] (m x k, ldc; gathered into the workspace when null),
-// by the normal equations with the Cholesky factor R of C^T C, written to R11
-// (k x k FP64, ldr) when given.  With kinfo, columns from kinfo->k_out on are
-// treated as absent.  A pivot of the Cholesky that is not positive (C's
-// columns dependent in FP64) sets the workspace flag at oFlag.
+// column, whose row of Z comes out zero), C = A[:, J] gathered into the
+// workspace, by the normal equations with the Cholesky factor R of C^T C,
+// written to R11 (k x k FP64, ldr) when given.  With kinfo, columns from
+// kinfo->k_out on are treated as absent.  A pivot of the Cholesky that is not
+// positive (C's columns dependent in FP64) sets the workspace flag at oFlag.
 struct LsPlan {
     int gz, gzr;  // the Gram's split over rows (planned, launched)
     size_t oC64, oGram, oGp, oR, oCT, oB, oSel, oFlag, oSemi, total;
@@ -69,7 +69,6 @@ struct LsPlan {
 int ls_plan(int64_t m, int64_t n, int k, size_t esz, LsPlan* L);
 template <typename T>
 int run_lstsq(const LsPlan& L, const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* J, int k,
-              const miid_info* kinfo, const T* C, int64_t ldc, T* Z, int64_t ldz, double* R11, int64_t ldr,
-              unsigned char* w, hipStream_t s);
+              const miid_info* kinfo, T* Z, int64_t ldz, double* R11, int64_t ldr, unsigned char* w, hipStream_t s);
 
 }  // namespace miid

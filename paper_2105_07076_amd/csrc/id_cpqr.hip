@@ -2470,8 +2470,7 @@ int ls_plan(int64_t m, int64_t n, int k, size_t esz, LsPlan* L) {
 
 template <typename T>
 int run_lstsq(const LsPlan& L, const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* J, int k,
-              const miid_info* kinfo, const T* C, int64_t ldc, T* Z, int64_t ldz, double* R11, int64_t ldr,
-              unsigned char* w, hipStream_t s) {
+              const miid_info* kinfo, T* Z, int64_t ldz, double* R11, int64_t ldr, unsigned char* w, hipStream_t s) {
     double* C64 = reinterpret_cast<double*>(w + L.oC64);
     double* Gram = reinterpret_cast<double*>(w + L.oGram);
     double* R = R11 ? R11 : reinterpret_cast<double*>(w + L.oR);
@@ -2479,13 +2478,11 @@ int run_lstsq(const LsPlan& L, const T* A, int64_t m, int64_t n, int64_t lda, co
     T* B = reinterpret_cast<T*>(w + L.oB);
     int32_t* sel = reinterpret_cast<int32_t*>(w + L.oSel);
     uint32_t* flag = reinterpret_cast<uint32_t*>(w + L.oFlag);
+    // C gathered here, not taken from the caller: its columns beyond a
+    // skeleton cut short (J = -1) must be zero so that Z's rows there are
     const dim3 ggrid((unsigned)std::min<int64_t>((m + 255) / 256, 64), (unsigned)k);
-    if (!C) {
-        T* CT = reinterpret_cast<T*>(w + L.oCT);
-        hipLaunchKernelGGL(k_gather_cols<T>, ggrid, dim3(256), 0, s, A, lda, m, n, J, CT);
-        C = CT;
-        ldc = m;
-    }
+    T* CT = reinterpret_cast<T*>(w + L.oCT);
+    hipLaunchKernelGGL(k_gather_cols<T>, ggrid, dim3(256), 0, s, A, lda, m, n, J, CT);
     hipLaunchKernelGGL(k_gather_f64<T>, ggrid, dim3(256), 0, s, A, lda, m, n, J, C64);
     // C^T C (symmetric: row- and column-major alike), split over the rows
     // into L.gz partial products summed in a fixed order
@@ -2508,7 +2505,7 @@ int run_lstsq(const LsPlan& L, const T* A, int64_t m, int64_t n, int64_t lda, co
         }
     }
     // C^T A (k x n, row-major), then Z = R^{-1} R^{-T} C^T A with Z[:, J] = I
-    gemm_tn<T>(C, ldc, A, lda, m, k, n, B, 1, s);
+    gemm_tn<T>(CT, m, A, lda, m, k, n, B, 1, s);
     hipLaunchKernelGGL(k_fill<int32_t>, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, s, sel, n,
                        (int32_t)-1);
     hipLaunchKernelGGL(k_sel_of, dim3(1), dim3(256), 0, s, J, k, n, sel);
@@ -2517,11 +2514,9 @@ int run_lstsq(const LsPlan& L, const T* A, int64_t m, int64_t n, int64_t lda, co
 }
 
 template int run_lstsq<float>(const LsPlan&, const float*, int64_t, int64_t, int64_t, const int32_t*, int,
-                              const miid_info*, const float*, int64_t, float*, int64_t, double*, int64_t,
-                              unsigned char*, hipStream_t);
+                              const miid_info*, float*, int64_t, double*, int64_t, unsigned char*, hipStream_t);
 template int run_lstsq<double>(const LsPlan&, const double*, int64_t, int64_t, int64_t, const int32_t*, int,
-                               const miid_info*, const double*, int64_t, double*, int64_t, double*, int64_t,
-                               unsigned char*, hipStream_t);
+                               const miid_info*, double*, int64_t, double*, int64_t, unsigned char*, hipStream_t);
 
 template int semi_solve<float>(const double*, int64_t, int, const float*, int64_t, int64_t, int64_t, const int32_t*,
                                int, float*, int64_t, unsigned char*, hipStream_t);

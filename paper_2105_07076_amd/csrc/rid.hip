@@ -327,7 +327,7 @@ int rid_sketch_cpqr(const float* A, int64_t m, int64_t n, int64_t lda, const uin
     // zero residual has k_out < k: the rest of J is -1 and Z's rows there
     // stay zero)
     unsigned char* wl = w + R.oLs;
-    const int rc3 = run_lstsq<float>(R.ls, A, m, n, lda, J, R.id.kmax, info, C, ldc, Z, ldz, R11, ldr, wl, s);
+    const int rc3 = run_lstsq<float>(R.ls, A, m, n, lda, J, R.id.kmax, info, Z, ldz, R11, ldr, wl, s);
     if (rc3 != 0) return rc3;
     hipLaunchKernelGGL(k_ls_status, dim3(1), dim3(64), 0, s, info, reinterpret_cast<const uint32_t*>(wl + R.ls.oFlag));
     MIID_HIP(hipGetLastError());

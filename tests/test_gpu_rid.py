@@ -279,3 +279,36 @@ def test_rid_lstsq_cfg2_full_size():
     el = np.linalg.norm(A64[:, cols] - A64[:, J] @ to_np(rl.Z).astype(np.float64)[:, cols], axis=0)
     es = np.linalg.norm(A64[:, cols] - A64[:, Js] @ to_np(rs.Z).astype(np.float64)[:, cols], axis=0)
     _no_worse(el, es, np.linalg.norm(A64[:, cols], axis=0))
+
+
+def test_rid_lstsq_skeleton_cut_short():
+    """Five nonzero columns and k = 8: the sketch's CPQR stops at k_out = 5
+    (MIID_RANK_DEFICIENT), the rest of the skeleton is absent, the Cholesky
+    treats it as unit rows, and C Z reproduces A."""
+    miid = _miid()
+    g = idgen.rng(21)
+    m, n = 40, 120
+    cols = [3, 17, 50, 77, 101]
+    A = np.zeros((m, n))
+    A[:, cols] = g.standard_normal((m, 5))
+    A_t = torch.tensor(A, dtype=torch.float32, device="cuda")
+    A64 = A_t.double().cpu().numpy()
+    Om_t = torch.tensor(idgen.omega_bf16(22, 16, m), dtype=torch.bfloat16, device="cuda")
+    r = miid.rid(A_t, Om_t, k=8, lstsq=True, want_R11=True)
+    torch.cuda.synchronize()
+    assert r.k == 5
+    assert r.status & 1 and not r.status & 32
+    J = to_np(r.J)
+    assert sorted(J.tolist()) == cols
+    Z = to_np(r.Z).astype(np.float64)
+    assert np.array_equal(Z[:, J], np.eye(5))
+    assert rel(A64[:, J] @ Z, A64) <= 1e-5
+    R = to_np(r.R11)
+    C = A64[:, J]
+    assert rel(R.T @ R, C.T @ C) <= 1e-12
+    # the full k x n output: rows beyond k_out are zero, J there is -1
+    from paper_2105_07076_amd import api
+    raw = api.rid_raw(A_t, Om_t, k=8, lstsq=True)
+    torch.cuda.synchronize()
+    assert np.all(to_np(raw["J"])[5:] == -1)
+    assert np.all(to_np(raw["Z"])[5:] == 0.0)
