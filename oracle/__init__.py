@@ -209,6 +209,21 @@ def rid_sample(A: np.ndarray, idx: np.ndarray, k: int) -> tuple[np.ndarray, np.n
     return cols.astype(np.int32), Z, res
 
 
+def two_sided(A: np.ndarray, k: int):
+    """Two-sided ID, A ~ W A[I, J] Z (the variant the paper credits to Cheng
+    et al. in its footnote to the ID's definition, Section 1.2): the column ID
+    of A (Section 2.1, a column ID whatever the shape) gives J and Z; the row
+    ID of its skeleton C = A[:, J] -- the paper's dual ID (Section 2's
+    footnote), i.e. the column ID of C^T -- gives I and W = Z_2^T (m x k,
+    W[I, :] = I_k).  Returns (I, J, W, Z, column-stage result, row-stage
+    result)."""
+    A = np.asarray(A, dtype=np.float64)
+    cres = _id_of(np.asfortranarray(A), False, k, None, None, None)
+    C = A[:, cres.J]
+    rres = _id_of(np.asfortranarray(C.T), False, k, None, None, None)
+    return rres.J.copy(), cres.J.copy(), np.asfortranarray(rres.Z.T), cres.Z, cres, rres
+
+
 def batched(blocks, eps: float) -> list[IDResult]:
     """Tolerance-mode ID of every block (kmax = min(m_b, n_b))."""
     out = []

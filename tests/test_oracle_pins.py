@@ -510,3 +510,55 @@ def test_haar_and_bf16_generators():
     assert np.array_equal(back.reshape(Om.shape), Om.astype(np.float32))
     assert idgen.bf16_round(np.array([1.0 + 2 ** -8], dtype=np.float32))[0] == 1.0  # tie to even
     assert idgen.bf16_round(np.array([1.0 + 3 * 2 ** -8], dtype=np.float32))[0] == 1.0 + 2 ** -6
+
+
+# --------------------------------------------------------------------------
+# two-sided ID: column ID of A, then the row (dual) ID of its skeleton
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(12))
+def test_two_sided_row_stage_is_exact_greedy_on_skeleton_rows(seed):
+    """Both stages against exact-rational brute force of the greedy rule: J on
+    the columns of A, I on the rows of the integer skeleton C = A[:, J]."""
+    g = np.random.default_rng(900 + seed)
+    m, n, k = 6, 8, 3
+    A = g.integers(-4, 5, size=(m, n)).astype(np.float64)
+    I, J, W, Z, cres, rres = oracle.two_sided(A, k)
+    cols = [[int(v) for v in A[:, l]] for l in range(n)]
+    Jx, gap_c = _greedy_exact(cols, k)
+    C = A[:, J]
+    rows = [[int(v) for v in C[r, :]] for r in range(m)]
+    Ix, gap_r = _greedy_exact(rows, k)
+    if gap_c < 1e-9 or gap_r < 1e-9:
+        pytest.skip("exact near-tie; the floating-point choice is not determined")
+    assert list(J) == Jx
+    assert list(I) == Ix
+
+
+@pytest.mark.parametrize("m,n,k", [(20, 50, 6), (50, 20, 6), (30, 30, 30)])
+def test_two_sided_exact_at_rank_k(m, n, k):
+    """Rank-k A: W A[I, J] Z reproduces A; W[I, :] and Z[:, J] are identities;
+    at k = m = n both index sets are permutations."""
+    A = idgen.integer_lowrank(7 + m, m, n, k)
+    I, J, W, Z, _, _ = oracle.two_sided(A, k)
+    assert np.array_equal(W[I, :], np.eye(k)) and np.array_equal(Z[:, J], np.eye(k))
+    M = W @ A[np.ix_(I, J)] @ Z
+    assert np.linalg.norm(A - M) <= 1e-10 * np.linalg.norm(A)
+    if k == m == n:
+        assert sorted(I.tolist()) == list(range(m)) and sorted(J.tolist()) == list(range(n))
+
+
+def test_two_sided_error_splits_into_the_stages():
+    """A - W A[I,J] Z = (A - C Z) + (C - W C[I,:]) Z, and each stage's residual
+    is its own CPQR's ||R22||_F: the two-sided error is at most the sum of the
+    stages' residuals, the second scaled by ||Z||_2."""
+    g = idgen.rng(31)
+    A = g.standard_normal((40, 90)) @ np.diag(0.93 ** np.arange(90))
+    k = 12
+    I, J, W, Z, cres, rres = oracle.two_sided(A, k)
+    C = A[:, J]
+    e1 = np.linalg.norm(A - C @ Z)
+    e2 = np.linalg.norm(C - W @ C[I, :])
+    assert abs(e1 - cres.resid[k]) <= 1e-10 * np.linalg.norm(A)
+    assert abs(e2 - rres.resid[k]) <= 1e-10 * np.linalg.norm(C)
+    e = np.linalg.norm(A - W @ A[np.ix_(I, J)] @ Z)
+    assert e <= e1 + e2 * np.linalg.norm(Z, 2) + 1e-12
