@@ -133,10 +133,10 @@ def main() -> int:
                     help="build the 4096 x 16384 input with the numpy recipe on the host (no device QR; "
                          "for counter-collection runs)")
     ap.add_argument("--only", default="all",
-                    help="comma list of sections to run: id64,id32,rid,ridsample,paper,batched,bwd (default all); "
+                    help="comma list of sections to run: id64,id32,rid,ridsample,twosided,paper,batched,bwd (default all); "
                          "the value is the FP64 ID, so id64 always runs")
     args = ap.parse_args()
-    sections = {"id64", "id32", "rid", "ridsample", "paper", "batched", "bwd"}
+    sections = {"id64", "id32", "rid", "ridsample", "twosided", "paper", "batched", "bwd"}
     only = set(args.only.split(",")) if args.only != "all" else sections
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the ID hot path is built for a single MI355X "
@@ -248,6 +248,21 @@ def main() -> int:
         extra["rid_sample_fp64_ms"] = round(ms_s, 4)
         extra["rid_sample_speedup_vs_fp64_id"] = round(ms64 / ms_s, 2)
         log(f"[bench] sampled RID {ms_s:.3f} ms")
+
+    if "twosided" in only:
+        # the two-sided ID of the metric's matrix (column ID, then the row ID
+        # of its 4096 x 256 skeleton), FP64
+        log("[bench] two-sided ID (FP64)")
+        out_t = miid_api.two_sided_raw(A64, k)
+        for _ in range(args.warmup):
+            miid_api.two_sided_raw(A64, k, out=out_t)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            miid_api.two_sided_raw(A64, k, out=out_t)
+        torch.cuda.synchronize()
+        extra["two_sided_fp64_ms"] = round((time.perf_counter() - t0) * 1000.0 / args.steps, 4)
+        log(f"[bench] two-sided ID {extra['two_sided_fp64_ms']:.3f} ms")
 
     if "paper" in only:
         # the paper's own shape (Gaussian 784 x 1000, k = 190; its timing

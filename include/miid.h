@@ -224,6 +224,31 @@ int rid_sample_cpqr(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype
                     void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Two-sided ID, A ~ W A[I, J] Z (the variant the paper credits to Cheng et
+ * al., footnote to the ID's definition, Section 1.2): the column ID of A
+ * (Section 2.1, a column ID whatever the shape: MIID_KEEP_COLUMNS is
+ * implied) gives J and Z, then the row ID of its skeleton C = A[:, J] --
+ * the dual ID of Section 2's footnote, the column ID of C^T -- gives I and
+ * W.  Both stages are the blocked CPQR + triangular solve of id_cpqr.
+ *
+ *  A          (1)  m x n, lda >= m, dtype, read only
+ *  opts       (6)  fixed rank only: 1 <= k <= min(m, n, 1024); nb, flags as
+ *                  for id_cpqr (else MIID_E_UNSUPPORTED)
+ *  J          (7)  k int32: skeleton columns; entries >= k_out are -1
+ *  Z          (8)  k x n, ldz >= k, dtype: Z[:, J[c]] = e_c
+ *  I          (10) k int32: skeleton rows (of the skeleton C, i.e. of A);
+ *                  entries >= the row stage's k_out are -1
+ *  W          (11) m x k, ldw >= m, dtype: W[I[c], :] = e_c^T
+ *  info       (13) device miid_info of the column stage (norms refer to A)
+ *  info_rows  (14) device miid_info of the row stage (norms refer to C)
+ * ---------------------------------------------------------------------- */
+size_t miid_two_sided_workspace(int64_t m, int64_t n, miid_dtype dtype, const miid_opts *opts);
+int id_two_sided(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
+                 const miid_opts *opts, int32_t *J, void *Z, int64_t ldz,
+                 int32_t *I, void *W, int64_t ldw, miid_info *info, miid_info *info_rows,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched tolerance-mode IDs of many independent small blocks (for instance
  * the off-diagonal blocks of a hierarchical kernel-matrix compression), in
  * one persistent launch.  Block b is m[b] x n[b] (column-major, leading

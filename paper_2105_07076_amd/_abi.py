@@ -33,6 +33,7 @@ EXPORTED = [
     "miid_id_workspace", "id_cpqr",
     "miid_rid_workspace", "rid_sketch_cpqr",
     "miid_rid_sample_workspace", "rid_sample_cpqr",
+    "miid_two_sided_workspace", "id_two_sided",
     "miid_batched_workspace", "id_batched",
     "miid_backward_workspace", "id_backward",
 ]
@@ -91,6 +92,10 @@ def load(path: str = LIB_PATH):
     lib.rid_sample_cpqr.restype = ctypes.c_int
     lib.rid_sample_cpqr.argtypes = [P, I64, I64, I64, ctypes.c_int, P, I32, OPTS, P, P, I64, P, I64, P, I64, P, P,
                                     SZ, P]
+    lib.miid_two_sided_workspace.restype = SZ
+    lib.miid_two_sided_workspace.argtypes = [I64, I64, ctypes.c_int, OPTS]
+    lib.id_two_sided.restype = ctypes.c_int
+    lib.id_two_sided.argtypes = [P, I64, I64, I64, ctypes.c_int, OPTS, P, P, I64, P, P, I64, P, P, P, SZ, P]
     if hasattr(lib, "rid_sketch_cpqr"):
         lib.miid_rid_workspace.restype = SZ
         lib.miid_rid_workspace.argtypes = [I64, I64, I32, OPTS]

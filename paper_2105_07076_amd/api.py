@@ -204,6 +204,62 @@ def rid_sample(A: torch.Tensor, idx, k: int, nb: int = 0, want_C: bool = True, w
     return _finish(out)
 
 
+@dataclass
+class TwoSidedResult:
+    """A ~ W A[I, J] Z: I (k_rows skeleton rows), J (k skeleton columns),
+    W (m x k_rows, W[I, :] = identity), Z (k x n, Z[:, J] = identity)."""
+    I: torch.Tensor
+    J: torch.Tensor
+    W: torch.Tensor
+    Z: torch.Tensor
+    k: int
+    k_rows: int
+    status: int
+    status_rows: int
+
+
+def two_sided_raw(A: torch.Tensor, k: int, nb: int = 0, out: dict | None = None, hints: int = 0):
+    """Enqueue id_two_sided without synchronising (see :func:`two_sided`)."""
+    lib = _abi.load()
+    if A.dtype not in _DT or not A.is_cuda:
+        raise TypeError("A must be a float32/float64 CUDA tensor")
+    A = colmajor(A)
+    m, n = A.shape
+    opts = _opts(k, None, k, nb, True, hints)
+    dt = _DT[A.dtype]
+    ws_bytes = lib.miid_two_sided_workspace(m, n, dt, ctypes.byref(opts))
+    if ws_bytes == 0:
+        _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_two_sided_workspace")
+    ws = _WS.get("two_sided", ws_bytes, A.device)
+    dev = A.device
+    if out is None:
+        isz = ctypes.sizeof(_abi.MiidInfo)
+        out = {
+            "J": torch.empty(k, dtype=torch.int32, device=dev),
+            "Z": empty_colmajor(k, n, A.dtype, dev),
+            "I": torch.empty(k, dtype=torch.int32, device=dev),
+            "W": empty_colmajor(m, k, A.dtype, dev),
+            "info": torch.empty(isz, dtype=torch.uint8, device=dev),
+            "info_rows": torch.empty(isz, dtype=torch.uint8, device=dev),
+        }
+    rc = lib.id_two_sided(_ptr(A), m, n, _ld(A), dt, ctypes.byref(opts), _ptr(out["J"]), _ptr(out["Z"]),
+                          _ld(out["Z"]), _ptr(out["I"]), _ptr(out["W"]), _ld(out["W"]), _ptr(out["info"]),
+                          _ptr(out["info_rows"]), _ptr(ws), ws_bytes, _stream())
+    _abi.check(rc, "id_two_sided")
+    return out
+
+
+def two_sided(A: torch.Tensor, k: int, nb: int = 0, hints: int = 0) -> TwoSidedResult:
+    """Two-sided ID A ~ W A[I, J] Z (fixed rank k): the column ID of A, then
+    the row (dual) ID of its skeleton C = A[:, J]."""
+    out = two_sided_raw(A, k, nb=nb, hints=hints)
+    ic = _read_info(out["info"])
+    ir = _read_info(out["info_rows"])
+    kc, kr = ic.k_out, ir.k_out
+    return TwoSidedResult(I=out["I"][:kr], J=out["J"][:kc], W=out["W"][:, :kr], Z=out["Z"][:kc], k=kc, k_rows=kr,
+                          status=ic.status, status_rows=ir.status)
+
+
 def rid_raw(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: float | None = None,
             kmax: int | None = None, mode: int = 1, nb: int = 0, refine: bool = True, want_C: bool = True,
             want_Y: bool = False, want_R11: bool = False, out: dict | None = None, hints: int = 0,
