@@ -234,7 +234,7 @@ def main() -> int:
         # the paper's randomized ID by column sampling (p = k + 0.2 k), FP64,
         # Z by the normal equations over the full A
         log("[bench] column-sampling RID (FP64, p = k + 0.2 k)")
-        idx = idgen.column_sample(12, n, k)
+        idx = torch.tensor(idgen.column_sample(12, n, k), dtype=torch.int32, device="cuda")
         out_s = miid_api.rid_sample_raw(A64, idx, k)
         for _ in range(args.warmup):
             miid_api.rid_sample_raw(A64, idx, k, out=out_s)
@@ -268,8 +268,8 @@ def main() -> int:
         # the paper's own shape (Gaussian 784 x 1000, k = 190; its timing
         # table), context beside the metric: FP64 ID and column-sampling RID
         log("[bench] paper-shaped 784 x 1000, k = 190 (FP64)")
-        Ap = torch.tensor(idgen.paper_dataset("gaussian", seed=0), device="cuda")
-        idx_p = idgen.column_sample(100, 1000, 190)
+        Ap = torch.tensor(idgen.paper_dataset("gaussian", seed=0), device="cuda").t().contiguous().t()
+        idx_p = torch.tensor(idgen.column_sample(100, 1000, 190), dtype=torch.int32, device="cuda")
 
         def timed(fn):
             o = fn(None)
@@ -285,7 +285,20 @@ def main() -> int:
         extra["paper_784x1000_k190_id_fp64_ms"] = round(timed(lambda o: miid_api.id_raw(Ap, k=190, out=o)), 4)
         extra["paper_784x1000_k190_rid_sample_fp64_ms"] = round(
             timed(lambda o: miid_api.rid_sample_raw(Ap, idx_p, 190, out=o)), 4)
-        log(f"[bench] paper shape: ID {extra['paper_784x1000_k190_id_fp64_ms']:.3f} ms, "
+        # the same ID replayed from a captured HIP graph: 190 steps of small
+        # launches, so this shows what the launch overhead costs eagerly
+        out_g = miid_api.id_raw(Ap, k=190)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            miid_api.id_raw(Ap, k=190, out=out_g)
+        extra["paper_784x1000_k190_id_fp64_graph_ms"] = round(timed(lambda o: g.replay()), 4)
+        out_e = miid_api.id_raw(Ap, k=190)
+        torch.cuda.synchronize()
+        extra["paper_graph_replay_equals_eager"] = bool(torch.equal(out_g["J"], out_e["J"]) and
+                                                        torch.equal(out_g["Z"], out_e["Z"]))
+        log(f"[bench] paper shape: ID {extra['paper_784x1000_k190_id_fp64_ms']:.3f} ms "
+            f"(graph replay {extra['paper_784x1000_k190_id_fp64_graph_ms']:.3f} ms), "
             f"sampled RID {extra['paper_784x1000_k190_rid_sample_fp64_ms']:.3f} ms")
 
     if "batched" in only:

@@ -198,8 +198,10 @@ def rid_sample(A: torch.Tensor, idx, k: int, nb: int = 0, want_C: bool = True, w
     column-pivoted QR of A[:, idx] picks k of the sampled columns
     (J = idx[selected], C = A[:, J]) and Z solves R_k^T R_k Z = C^T A over the
     full A.  ``idx`` holds the sample (the paper draws p = k + floor(0.2 k)
-    distinct columns; the random numbers are an input).  ``a_norm`` and
-    ``r22_norm`` of the result refer to A[:, idx]."""
+    distinct columns; the random numbers are an input; a device int32
+    tensor is used as it is, anything else is copied to the device on each
+    call, which graph capture does not allow).  ``a_norm`` and ``r22_norm``
+    of the result refer to A[:, idx]."""
     out = rid_sample_raw(A, idx, k, nb=nb, want_C=want_C, want_R11=want_R11, hints=hints)
     return _finish(out)
 

@@ -1,5 +1,6 @@
 """The ID entry points under HIP graph capture: id_cpqr (fixed rank),
-rid_sketch_cpqr and id_batched are enqueued on the capturing stream with
+rid_sketch_cpqr (also with the least-squares Z), rid_sample_cpqr,
+id_two_sided and id_batched are enqueued on the capturing stream with
 caller-owned buffers and no host synchronisation, so torch.cuda.CUDAGraph can
 record them.  Every replay (with eager work and synchronisations between the
 replays) must reproduce the eager result bit for bit."""
@@ -81,3 +82,28 @@ def test_graph_batched(dtype):
     torch.cuda.synchronize()
     _capture_and_check(lambda: api.batched_raw(A, blocks.a_off, blocks.m, blocks.n, 1e-6, 64, out=out),
                        [out["J"], out["Z"], out["info"]])
+
+
+def test_graph_rid_sample_and_lstsq_and_two_sided():
+    """The column-sampling RID, the sketch RID with the least-squares Z and
+    the two-sided ID under capture (the same kernels plus the Gram, Cholesky
+    and transposes)."""
+    miid = _miid()
+    from paper_2105_07076_amd import api
+    A = idgen.lowrank_plus_noise_device(15, 384, 1500, np.exp(-np.arange(384) / 32.0), 1e-8,
+                                        dtype=torch.float64)
+    idx = torch.tensor(idgen.column_sample(16, 1500, 48), dtype=torch.int32, device="cuda")  # no copy in capture
+    out = api.rid_sample_raw(A, idx, 48, want_R11=True)
+    torch.cuda.synchronize()
+    _capture_and_check(lambda: api.rid_sample_raw(A, idx, 48, want_R11=True, out=out),
+                       [out["J"], out["Z"], out["C"], out["R11"], out["info"]])
+    A32 = A.to(torch.float32)
+    Om = torch.tensor(idgen.omega_bf16(17, 58, 384), dtype=torch.bfloat16, device="cuda").t().contiguous().t()
+    out2 = api.rid_raw(A32, Om, k=48, mode=1, lstsq=True, want_R11=True)
+    torch.cuda.synchronize()
+    _capture_and_check(lambda: api.rid_raw(A32, Om, k=48, mode=1, lstsq=True, want_R11=True, out=out2),
+                       [out2["J"], out2["Z"], out2["R11"], out2["info"]])
+    out3 = api.two_sided_raw(A, 40)
+    torch.cuda.synchronize()
+    _capture_and_check(lambda: api.two_sided_raw(A, 40, out=out3),
+                       [out3["J"], out3["Z"], out3["I"], out3["W"], out3["info"], out3["info_rows"]])
