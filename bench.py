@@ -140,7 +140,7 @@ def main() -> int:
     only = set(args.only.split(",")) if args.only != "all" else sections
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the ID hot path is built for a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented).", file=sys.stderr)
+              "(sharding over several GPUs is not implemented).", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -96,7 +96,7 @@ def test_batched_small_sizes_and_kmax():
     _check_blocks(blocks, res, A64, torch.float64, range(40), eps=1e-9, kmax=8)
 
 
-@pytest.mark.skip(reason="this case went silent for 180 s on the GPU box (harness kill, no GPU fault); "
+@pytest.mark.skip(reason="this case once ran silent for 180 s on the GPU and was stopped (no GPU fault); "
                          "no cause found by reading the kernel or the host path yet, so it stays off the GPU")
 def test_batched_isolates_bad_blocks():
     """A NaN in one block and an oversized block do not disturb the others."""
