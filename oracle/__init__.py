@@ -12,7 +12,15 @@ Interpolative Decomposition".  Section 2 (A is m x n, m <= n, else work on
 A^T; rank k), Section 2.1 (CPQR selects C = A P_k; Z from the least-squares
 problem min ||A - C Z||_F, reduced to triangular solves), Definition 1
 (k columns of Z form the identity), Section 4.1 (stop the QR after k
-columns).
+columns).  Beside the ID: ``rid`` (the same CPQR on an exact FP64 sketch),
+``rid_sample`` (Section 2.2's column sampling with the normal-equation Z
+over the full A), ``two_sided`` (the column ID followed by the dual ID of
+its skeleton), ``batched`` (tolerance mode per block) and ``id_vjp`` (the
+adjoint with the pivots held fixed).
+
+Parity unpinned: none of the functions; only the intermediate rounding of
+downdated column norms is internal to the GPU path and has no counterpart
+here (the oracle recomputes exact norms every step).
 """
 from __future__ import annotations
 
