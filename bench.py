@@ -85,7 +85,7 @@ def time_id(miid_api, lib, A, k, steps, warmup, sample_every=7):
 GEMV_TRAFFIC = {
     "bytes_per_launch": 532.1e6,
     "sources": {
-        "paper_2105_07076_amd/csrc/id_cpqr.hip": "5a0a6e9be1711371ec7867f3cc8036036d3a207aa33bfec834b3ec41e9f3daad",
+        "paper_2105_07076_amd/csrc/id_cpqr.hip": "7fb2ecb8510389f1494d5be2c26f7a4f21841d734f2870e5b08f5b22aa3d15ac",
         "paper_2105_07076_amd/csrc/common.hpp": "77e3f522d4607da471046f7b4d08b5688ce5617e1b620ace976254481bb74ae8",
         "paper_2105_07076_amd/csrc/cpqr.hpp": "c5af1863f13e79013f7e57c2d630a8f7b6596f8e47994e4c871b31b405454bf3",
     },

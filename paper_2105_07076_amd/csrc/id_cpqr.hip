@@ -2302,6 +2302,13 @@ __global__ void k_gather_f64(const T* __restrict__ A, int64_t lda, int64_t m, in
         C64[r + (int64_t)c * m] = ok ? (double)A[r + src * lda] : 0.0;
 }
 
+// R[0:k, 0:k] = 0 (leading dimension ldr; nothing outside the block is touched)
+__global__ void k_zero_block(double* __restrict__ R, int64_t ldr, int k) {
+    const int64_t total = (int64_t)k * k;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+        R[e % k + (e / k) * ldr] = 0.0;
+}
+
 // sel[J[i]] = i (sel was filled with -1)
 __global__ void k_sel_of(const int32_t* __restrict__ J, int k, int64_t n, int32_t* __restrict__ sel) {
     for (int i = threadIdx.x; i < k; i += blockDim.x) {
@@ -2493,8 +2500,8 @@ int run_lstsq(const LsPlan& L, const T* A, int64_t m, int64_t n, int64_t lda, co
         hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)std::min<int64_t>((kk + 255) / 256, 4096)), dim3(256), 0, s, Gp,
                            L.gzr, kk, Gram);
     }
-    hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)std::min<int64_t>((ldR * k + 255) / 256, 4096)), dim3(256), 0, s, R,
-                       ldR * k, 0.0);
+    hipLaunchKernelGGL(k_zero_block, dim3((unsigned)std::min<int64_t>(((int64_t)k * k + 255) / 256, 4096)), dim3(256), 0,
+                       s, R, ldR, k);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(64), 0, s, flag, (int64_t)1, 0u);
     for (int r0 = 0; r0 < k; r0 += kChB) {
         hipLaunchKernelGGL(k_chol_panel, dim3(1), dim3(256), 0, s, Gram, k, r0, kinfo, R, ldR, flag);

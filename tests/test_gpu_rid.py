@@ -312,3 +312,32 @@ def test_rid_lstsq_skeleton_cut_short():
     torch.cuda.synchronize()
     assert np.all(to_np(raw["J"])[5:] == -1)
     assert np.all(to_np(raw["Z"])[5:] == 0.0)
+
+
+def test_rid_lstsq_r11_leading_dimension():
+    """A caller's R11 inside a taller buffer (ldr = k + 5): the k x k block is
+    written, the rows below it are left as they were."""
+    import ctypes
+    from paper_2105_07076_amd import _abi, api
+    _miid()
+    g = idgen.rng(23)
+    m, n, l, k = 96, 300, 50, 40
+    A = g.standard_normal((m, n)) @ np.diag(0.97 ** np.arange(n))
+    A_t = torch.tensor(A, dtype=torch.float32, device="cuda")
+    Om_t = torch.tensor(idgen.omega_bf16(24, l, m), dtype=torch.bfloat16, device="cuda")
+    big = torch.full((k, k + 5), 7.0, dtype=torch.float64, device="cuda").t()  # (k + 5) x k, column-major
+    out = {
+        "J": torch.empty(k, dtype=torch.int32, device="cuda"),
+        "Z": torch.empty((n, k), dtype=torch.float32, device="cuda").t(),
+        "C": None, "Y": None, "R11": big[:k],
+        "info": torch.empty(ctypes.sizeof(_abi.MiidInfo), dtype=torch.uint8, device="cuda"),
+    }
+    assert out["R11"].stride() == (1, k + 5)
+    api.rid_raw(A_t, Om_t, k=k, mode=1, lstsq=True, out=out)
+    torch.cuda.synchronize()
+    assert torch.all(big[k:] == 7.0)
+    R = to_np(big[:k])
+    J = to_np(out["J"])
+    C = A_t.double().cpu().numpy()[:, J]
+    assert np.array_equal(R, np.triu(R))
+    assert rel(R.T @ R, C.T @ C) <= 1e-12
