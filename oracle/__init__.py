@@ -15,7 +15,7 @@ problem min ||A - C Z||_F, reduced to triangular solves), Definition 1
 columns).  Beside the ID: ``rid`` (the same CPQR on an exact FP64 sketch),
 ``rid_sample`` (Section 2.2's column sampling with the normal-equation Z
 over the full A), ``two_sided`` (the column ID followed by the dual ID of
-its skeleton), ``batched`` (tolerance mode per block) and ``id_vjp`` (the
+its skeleton) and ``cur`` (its CUR form), ``batched`` (tolerance mode per block) and ``id_vjp`` (the
 adjoint with the pivots held fixed).
 
 Parity unpinned: none of the functions; only the intermediate rounding of
@@ -230,6 +230,17 @@ def two_sided(A: np.ndarray, k: int):
     C = A[:, cres.J]
     rres = _id_of(np.asfortranarray(C.T), False, k, None, None, None)
     return rres.J.copy(), cres.J.copy(), np.asfortranarray(rres.Z.T), cres.Z, cres, rres
+
+
+def cur(A: np.ndarray, k: int):
+    """CUR form of the two-sided ID: C = A[:, J], R = A[I, :] and U = Z R^+
+    (the k x k matrix with U R closest to Z in the Frobenius norm, so that
+    C U R ~ C Z), from the normal equations (R R^T) U^T = R Z^T solved by
+    numpy's LAPACK solve.  Returns (I, J, U)."""
+    I, J, _, Z, _, _ = two_sided(A, k)
+    R = np.asarray(A, dtype=np.float64)[I, :]
+    Ut = np.linalg.solve(matmul(R, R.T), matmul(R, Z.T))
+    return I, J, Ut.T
 
 
 def batched(blocks, eps: float) -> list[IDResult]:

@@ -562,3 +562,27 @@ def test_two_sided_error_splits_into_the_stages():
     assert abs(e2 - rres.resid[k]) <= 1e-10 * np.linalg.norm(C)
     e = np.linalg.norm(A - W @ A[np.ix_(I, J)] @ Z)
     assert e <= e1 + e2 * np.linalg.norm(Z, 2) + 1e-12
+
+
+@pytest.mark.parametrize("m,n,k", [(20, 50, 6), (50, 20, 6), (30, 30, 30)])
+def test_cur_exact_at_rank_k(m, n, k):
+    """Rank-k A: C U R reproduces A (R^+ R projects onto A's row space)."""
+    A = idgen.integer_lowrank(70 + m, m, n, k)
+    I, J, U = oracle.cur(A, k)
+    M = A[:, J] @ U @ A[I, :]
+    assert np.linalg.norm(A - M) <= 1e-9 * np.linalg.norm(A)
+
+
+def test_cur_u_is_least_squares_and_bounded_by_the_id():
+    """U minimises ||Z - U R||_F (against the SVD-based pseudo-inverse), so
+    ||A - C U R|| is at most ||A - C Z|| + ||C|| ||Z - U R||."""
+    g = idgen.rng(32)
+    A = g.standard_normal((45, 100)) @ np.diag(0.94 ** np.arange(100))
+    k = 15
+    I, J, U = oracle.cur(A, k)
+    _, _, _, Z, _, _ = oracle.two_sided(A, k)
+    R = A[I, :]
+    np.testing.assert_allclose(U, Z @ np.linalg.pinv(R), rtol=1e-9, atol=1e-9)
+    e_cur = np.linalg.norm(A - A[:, J] @ U @ R)
+    e_id = np.linalg.norm(A - A[:, J] @ Z)
+    assert e_cur <= e_id + np.linalg.norm(A[:, J], 2) * np.linalg.norm(Z - U @ R) + 1e-12
