@@ -249,6 +249,23 @@ int id_two_sided(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dt
                  void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * CUR form of the two-sided ID: A ~ C U R with C = A[:, J], R = A[I, :]
+ * (J, I from id_two_sided) and U = Z R^+ (k x k), the least-squares
+ * solution of U R ~ Z (so C U R ~ C Z), computed like the least-squares Z
+ * of rid_sketch_cpqr (FP64 Gram of R, Cholesky, two-sided solve).  Not in
+ * the paper; it completes the two-sided form.
+ *
+ *  A, opts, J, I: as for id_two_sided; U (9) k x k, ldu >= k, dtype
+ *  info, info_rows: as for id_two_sided; info_rows also gets
+ *                   MIID_LSTSQ_BREAKDOWN if R R^T is not positive definite in
+ *                   FP64
+ * ---------------------------------------------------------------------- */
+size_t miid_cur_workspace(int64_t m, int64_t n, miid_dtype dtype, const miid_opts *opts);
+int id_cur(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
+           const miid_opts *opts, int32_t *J, int32_t *I, void *U, int64_t ldu,
+           miid_info *info, miid_info *info_rows, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched tolerance-mode IDs of many independent small blocks (for instance
  * the off-diagonal blocks of a hierarchical kernel-matrix compression), in
  * one persistent launch.  Block b is m[b] x n[b] (column-major, leading

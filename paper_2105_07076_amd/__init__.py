@@ -9,8 +9,8 @@ include/miid.h; this package only marshals arguments (torch supplies device
 memory and the stream).
 """
 from ._abi import MiidError, load  # noqa: F401
-from .api import (IDResult, BatchedResult, TwoSidedResult, id, rid, rid_sample, two_sided, batched,  # noqa: F401
-                  id_backward, IDFunction)
+from .api import (IDResult, BatchedResult, TwoSidedResult, id, rid, rid_sample, two_sided, cur,  # noqa: F401
+                  batched, id_backward, IDFunction)
 from . import autotune  # noqa: F401
 
 __all__ = ["IDResult", "id", "rid", "batched", "id_backward", "IDFunction", "MiidError", "load", "autotune"]

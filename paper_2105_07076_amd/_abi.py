@@ -34,6 +34,7 @@ EXPORTED = [
     "miid_rid_workspace", "rid_sketch_cpqr",
     "miid_rid_sample_workspace", "rid_sample_cpqr",
     "miid_two_sided_workspace", "id_two_sided",
+    "miid_cur_workspace", "id_cur",
     "miid_batched_workspace", "id_batched",
     "miid_backward_workspace", "id_backward",
 ]
@@ -96,6 +97,10 @@ def load(path: str = LIB_PATH):
     lib.miid_two_sided_workspace.argtypes = [I64, I64, ctypes.c_int, OPTS]
     lib.id_two_sided.restype = ctypes.c_int
     lib.id_two_sided.argtypes = [P, I64, I64, I64, ctypes.c_int, OPTS, P, P, I64, P, P, I64, P, P, P, SZ, P]
+    lib.miid_cur_workspace.restype = SZ
+    lib.miid_cur_workspace.argtypes = [I64, I64, ctypes.c_int, OPTS]
+    lib.id_cur.restype = ctypes.c_int
+    lib.id_cur.argtypes = [P, I64, I64, I64, ctypes.c_int, OPTS, P, P, P, I64, P, P, P, SZ, P]
     if hasattr(lib, "rid_sketch_cpqr"):
         lib.miid_rid_workspace.restype = SZ
         lib.miid_rid_workspace.argtypes = [I64, I64, I32, OPTS]

@@ -262,6 +262,44 @@ def two_sided(A: torch.Tensor, k: int, nb: int = 0, hints: int = 0) -> TwoSidedR
                           status=ic.status, status_rows=ir.status)
 
 
+def cur_raw(A: torch.Tensor, k: int, nb: int = 0, out: dict | None = None, hints: int = 0):
+    """Enqueue id_cur without synchronising (see :func:`cur`)."""
+    lib = _abi.load()
+    if A.dtype not in _DT or not A.is_cuda:
+        raise TypeError("A must be a float32/float64 CUDA tensor")
+    A = colmajor(A)
+    m, n = A.shape
+    opts = _opts(k, None, k, nb, True, hints)
+    dt = _DT[A.dtype]
+    ws_bytes = lib.miid_cur_workspace(m, n, dt, ctypes.byref(opts))
+    if ws_bytes == 0:
+        _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_cur_workspace")
+    ws = _WS.get("cur", ws_bytes, A.device)
+    dev = A.device
+    if out is None:
+        isz = ctypes.sizeof(_abi.MiidInfo)
+        out = {
+            "J": torch.empty(k, dtype=torch.int32, device=dev),
+            "I": torch.empty(k, dtype=torch.int32, device=dev),
+            "U": empty_colmajor(k, k, A.dtype, dev),
+            "info": torch.empty(isz, dtype=torch.uint8, device=dev),
+            "info_rows": torch.empty(isz, dtype=torch.uint8, device=dev),
+        }
+    rc = lib.id_cur(_ptr(A), m, n, _ld(A), dt, ctypes.byref(opts), _ptr(out["J"]), _ptr(out["I"]), _ptr(out["U"]),
+                    _ld(out["U"]), _ptr(out["info"]), _ptr(out["info_rows"]), _ptr(ws), ws_bytes, _stream())
+    _abi.check(rc, "id_cur")
+    return out
+
+
+def cur(A: torch.Tensor, k: int, nb: int = 0, hints: int = 0):
+    """CUR form of the two-sided ID (fixed rank k): returns (I, J, U, status,
+    status_rows) with A ~ A[:, J] U A[I, :] and U = Z R^+."""
+    out = cur_raw(A, k, nb=nb, hints=hints)
+    ic = _read_info(out["info"])
+    ir = _read_info(out["info_rows"])
+    return out["I"], out["J"], out["U"], ic.status, ir.status
+
+
 def rid_raw(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: float | None = None,
             kmax: int | None = None, mode: int = 1, nb: int = 0, refine: bool = True, want_C: bool = True,
             want_Y: bool = False, want_R11: bool = False, out: dict | None = None, hints: int = 0,

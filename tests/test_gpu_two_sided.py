@@ -125,3 +125,45 @@ def test_two_sided_4096x16384_k256():
     e2 = np.linalg.norm(A64[:, cols] - W @ A64[np.ix_(I, J)] @ Z[:, cols])
     e1 = np.linalg.norm(A64[:, cols] - A64[:, J] @ Z[:, cols])
     assert abs(e2 - e1) <= 1e-8 * np.linalg.norm(A64[:, cols])
+
+
+# --------------------------------------------------------------------------
+# CUR form: U = Z R^+ with R = A[I, :]
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n,k", [(60, 300, 12), (300, 80, 20), (257, 1000, 70)])
+def test_cur_fp64(m, n, k):
+    """I, J as the two-sided ID's; U against the oracle's normal-equation U
+    (bar c u kappa(R)^2); the CUR error against the oracle's."""
+    miid = _miid()
+    g = idgen.rng(m * 3 + n)
+    A = g.standard_normal((m, n)) @ np.diag(0.97 ** np.arange(n))
+    A = np.asfortranarray(np.diag(0.98 ** np.arange(m)) @ A)
+    A_t = torch.tensor(A, device="cuda")
+    I, J, U, st, st_rows = miid.cur(A_t, k)
+    t = miid.two_sided(A_t, k)
+    torch.cuda.synchronize()
+    assert st == 0 and st_rows == 0
+    assert torch.equal(I, t.I) and torch.equal(J, t.J)
+    I, J, U = to_np(I), to_np(J), to_np(U)
+    R = A[I, :]
+    Zg = to_np(t.Z)
+    Uref = np.linalg.solve(R @ R.T, R @ Zg.T).T      # the oracle's formula on the GPU's own Z
+    bar = max(1e-12, 256.0 * U64 * np.linalg.cond(R) ** 2)
+    assert rel(U, Uref) <= bar, f"U error {rel(U, Uref):.3e} > {bar:.3e}"
+    oI, oJ, oU = oracle.cur(A, k)
+    if np.array_equal(I, oI) and np.array_equal(J, oJ):
+        e = np.linalg.norm(A - A[:, J] @ U @ R)
+        e_ref = np.linalg.norm(A - A[:, oJ] @ oU @ A[oI, :])
+        assert abs(e - e_ref) <= 1e-9 * np.linalg.norm(A)
+
+
+def test_cur_exact_rank_k_fp32():
+    """A rank-k integer matrix in FP32: C U R reproduces it to FP32 rounding."""
+    miid = _miid()
+    A = idgen.integer_lowrank(9, 120, 200, 8)
+    A_t = torch.tensor(A, dtype=torch.float32, device="cuda")
+    I, J, U, st, st_rows = miid.cur(A_t, 8)
+    torch.cuda.synchronize()
+    I, J, U = to_np(I), to_np(J), to_np(U).astype(np.float64)
+    M = A[:, J] @ U @ A[I, :]
+    assert np.linalg.norm(A - M) <= 1e-4 * np.linalg.norm(A)
