@@ -104,3 +104,39 @@ def test_argument_validation_before_any_device_work():
     # backward: k > m -> -7
     assert lib.id_backward(dummy, 10, 20, 10, 0, dummy, 11, dummy, 11, dummy, 11, None, 1, None, 1, dummy, 10,
                            dummy, 1 << 30, None) == -7
+
+
+def test_argument_validation_of_the_sampled_two_sided_and_cur_entry_points():
+    _abi, lib = _lib()
+    P = ctypes.c_void_p
+    dummy = P(0x1000)  # never dereferenced: validation fails first
+    big = 1 << 30
+    o = _abi.MiidOpts()
+    o.k = 4
+    tol = _abi.MiidOpts()
+    tol.eps, tol.kmax = 1e-3, 4
+    # column-sampling RID: idx null -> -6, p > n -> -7, tolerance mode -> -8
+    assert lib.rid_sample_cpqr(dummy, 10, 20, 10, 1, None, 6, ctypes.byref(o), dummy, dummy, 4, None, 1, None, 1,
+                               dummy, dummy, big, None) == -6
+    assert lib.rid_sample_cpqr(dummy, 10, 20, 10, 1, dummy, 21, ctypes.byref(o), dummy, dummy, 4, None, 1, None, 1,
+                               dummy, dummy, big, None) == -7
+    assert lib.rid_sample_cpqr(dummy, 10, 20, 10, 1, dummy, 6, ctypes.byref(tol), dummy, dummy, 4, None, 1, None, 1,
+                               dummy, dummy, big, None) == -8
+    assert lib.miid_rid_sample_workspace(10, 20, 6, 1, ctypes.byref(o)) > 0
+    # two-sided ID: fixed rank only; any shape (the column stage keeps columns)
+    assert lib.miid_two_sided_workspace(10, 20, 1, ctypes.byref(o)) > 0
+    assert lib.miid_two_sided_workspace(30, 20, 1, ctypes.byref(o)) > 0
+    assert lib.miid_two_sided_workspace(10, 20, 1, ctypes.byref(tol)) == 0
+    # ldw < m -> -12
+    assert lib.id_two_sided(dummy, 10, 20, 10, 1, ctypes.byref(o), dummy, dummy, 4, dummy, dummy, 9, dummy, dummy,
+                            dummy, big, None) == -12
+    # CUR: ldu < k -> -10
+    assert lib.miid_cur_workspace(10, 20, 1, ctypes.byref(o)) > 0
+    assert lib.id_cur(dummy, 10, 20, 10, 1, ctypes.byref(o), dummy, dummy, dummy, 3, dummy, dummy, dummy, big,
+                      None) == -10
+    # sketch RID with the least-squares Z: more workspace; fixed rank only
+    ol = _abi.MiidOpts()
+    ol.k, ol.flags = 4, _abi.MIID_LSTSQ_Z
+    assert lib.miid_rid_workspace(10, 20, 8, ctypes.byref(ol)) > lib.miid_rid_workspace(10, 20, 8, ctypes.byref(o))
+    tol.flags = _abi.MIID_LSTSQ_Z
+    assert lib.miid_rid_workspace(10, 20, 8, ctypes.byref(tol)) == 0
