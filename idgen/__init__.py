@@ -196,6 +196,17 @@ def batched_blocks(seed: int = 4, nblk: int = 4096, mmin: int = 32, mmax: int = 
     g = rng(seed)
     ms = g.integers(mmin, mmax + 1, size=nblk).astype(np.int32)
     ns = np.array([g.integers(mb, 2 * mb + 1) for mb in ms], dtype=np.int32)
+    return _kernel_blocks(g, ms, ns, sep)
+
+
+def kernel_blocks_sized(seed: int, ms, ns, sep: float = 4.0) -> BatchedBlocks:
+    """The same kernel-matrix blocks with the given sizes (m[b], n[b])."""
+    g = rng(seed)
+    return _kernel_blocks(g, np.asarray(ms, dtype=np.int32), np.asarray(ns, dtype=np.int32), sep)
+
+
+def _kernel_blocks(g, ms: np.ndarray, ns: np.ndarray, sep: float) -> BatchedBlocks:
+    nblk = len(ms)
     sizes = ms.astype(np.int64) * ns.astype(np.int64)
     off = np.zeros(nblk, dtype=np.int64)
     off[1:] = np.cumsum(sizes)[:-1]

@@ -70,14 +70,14 @@ typedef enum { MIID_F32 = 0, MIID_F64 = 1 } miid_dtype;
  *  PATH  id_cpqr/rid: 1 = blocked two-launch path, 2 = fused path (taken
  *        only where eligible: at most 576 rows in FP32 / 288 in FP64,
  *        panels of at most 32)
- *  TILE  id_batched: streamed column tile of a block that does not fit in
- *        LDS, in units of 8 KiB (1..15, capped at half of the LDS the
- *        kernel uses for blocks; default 24 KiB); the LDS left beside the
- *        two tiles keeps the block's first columns resident              */
+ *  LPC   id_batched: cap on the lanes that share one column of a block
+ *        (1, 2, 4 or 8; default 8: as many as n L <= 512 allows).  It
+ *        changes the order of the per-lane partial sums, so results can
+ *        differ in the last bits between settings                       */
 #define MIID_HINT_CPW_SHIFT 8
 #define MIID_HINT_NP_SHIFT 12
 #define MIID_HINT_PATH_SHIFT 16
-#define MIID_HINT_TILE_SHIFT 20
+#define MIID_HINT_LPC_SHIFT 20
 #define MIID_HINT(field_shift, value) (((uint32_t)(value) & 15u) << (field_shift))
 
 typedef struct {
@@ -275,7 +275,7 @@ int id_cur(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
  *
  *  A      (2)  packed blocks, dtype
  *  a_off, m, n (3-5) device int64 / int32 / int32 arrays of length nblk
- *  opts   (7)  host: eps, kmax and flags (MIID_HINT(MIID_HINT_TILE_SHIFT, t));
+ *  opts   (7)  host: eps, kmax and flags (MIID_HINT(MIID_HINT_LPC_SHIFT, l));
  *              k and nb are ignored
  *  J      (8)  packed int32: block b owns kmax_b entries at j_off[b]
  *  Z      (10) packed dtype: block b owns a kmax_b x n[b] column-major

@@ -44,7 +44,7 @@ EXPORTED = [
 MIID_HINT_CPW_SHIFT = 8
 MIID_HINT_NP_SHIFT = 12
 MIID_HINT_PATH_SHIFT = 16
-MIID_HINT_TILE_SHIFT = 20
+MIID_HINT_LPC_SHIFT = 20
 
 
 def hint(shift: int, value: int) -> int:

@@ -3,7 +3,7 @@
 The library's tuning knobs change launch shapes only, never what is computed:
 the panel width nb and the MIID_HINT fields of miid_opts.flags (columns per
 wave of the blocked path's F-GEMV, column passes per wave of the fused
-short-matrix path, the path itself, and the streamed column tile of the
+short-matrix path, the path itself, and the lanes per column of the
 batched kernel).  :func:`tune_id` and :func:`tune_batched` time every
 candidate on the caller's own data (or a seeded synthetic matrix of the given
 shape) with HIP events and return the fastest; :class:`Table` keeps results
@@ -112,13 +112,14 @@ def tune_rid(A: torch.Tensor, omega: torch.Tensor, k: int, mode: int = 1, reps: 
 
 
 def batched_candidates():
-    """Streamed column tile sizes of the batched kernel (8 to 72 KiB)."""
-    return [(f"tile={8 * t}KiB", 0, H(_abi.MIID_HINT_TILE_SHIFT, t)) for t in (1, 2, 3, 4, 6, 9)]
+    """Caps on the lanes per column of the batched kernel (1, 2, 4, 8)."""
+    return [(f"lanes<={l}", 0, H(_abi.MIID_HINT_LPC_SHIFT, l)) for l in (1, 2, 4, 8)]
 
 
 def tune_batched(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, reps: int = 3,
                  candidates=None) -> Choice:
-    """Fastest tile hint for one batch of blocks (the caller's own blocks)."""
+    """Fastest lanes-per-column cap for one batch of blocks (the caller's own
+    blocks)."""
     cands = candidates or batched_candidates()
     out = api.batched_raw(A, a_off, m, n, eps, kmax)
     timings = {}

@@ -5,26 +5,45 @@
 // chosen), Definition 1 (Z[:, J] = I).  Here each block stops at the smallest
 // k whose residual ||R22||_F <= eps ||A_b||_F.
 //
-// Design: one workgroup works on one block at a time and takes the next block
-// from an atomic queue over the blocks sorted by decreasing m * n (longest
-// first), so uneven sizes balance across the chip.  Each Householder step
-// applies the reflector to every remaining column and recomputes that
-// column's residual norm exactly (FP64 accumulation) in the same pass -- at
-// eps = 1e-6 in FP32 downdated norms would have lost all their digits.  A
-// column is handled by a 16-lane group (lane l16 takes rows l16 + 16 t; DPP
-// row sums), with the rows per lane fitted to m.  The working copy W of the
-// block is spread over the chip: its first columns in registers, the next in
-// LDS, and whatever does not fit in a per-workgroup scratch that every pass
-// streams through two LDS column tiles (the next tile's loads in flight while
-// the current one is updated, the updated one written back behind it).  The
-// waves stage their best columns at the end of a pass and every lane forms
-// the next reflector itself, so a step costs two workgroup barriers and no
-// serial section.  R stays in W's first k rows and is copied row by row into Z's
-// storage (no column swaps); the k x k triangle is staged in LDS in FP64 for
-// the solve, which then overwrites Z in place.
+// Design.  One 512-lane workgroup factors one block at a time and takes the
+// next block from an atomic queue over the blocks sorted by decreasing m n
+// (longest first).  Unlike a GEMV-style layout (many lanes per column and a
+// cross-lane sum for every dot product), a column here belongs to a group of
+// L lanes (L = 1, 2, 4 or 8, the largest that fits n L <= 512), so each
+// lane's share of the Householder step -- the dot product v^T x, the update
+// x - tau (v^T x) v and the new residual norm -- is a serial loop over the
+// rows it holds, and the only cross-lane work per column is an L-lane DPP
+// sum.  Rows are dealt to the L lanes in chunks of four (lane q holds rows
+// 4 (q + L t) + i), so every lane of the group touches the same number of
+// rows at every step.  Columns are dealt round-robin over the eight waves so
+// the four SIMDs get equal work.
+//
+// Storage: a lane's rows ("virtual rows", the column's rows chunk by chunk;
+// for n > 512 a lane holds two columns, one after the other) live in
+// registers first, then in an LDS slab indexed [row][lane] (conflict-free),
+// and only what fits in neither in a per-workgroup global scratch with the
+// same layout.  In FP32 every block with n <= 512 stays on chip.
+//
+// A step: each wave reduces the residual norms of its columns to the best
+// (value, column) and the sum of squares and writes them to LDS; barrier;
+// every lane folds the eight entries (the same result everywhere), applies
+// the stopping tests, and the pivot column's lanes copy its rows into an LDS
+// stage; barrier; every lane forms the reflector from the staged column and
+// applies H = I - tau v v^T to its columns: the dot products and the squared
+// norms as four-row sums in the working precision accumulated in FP64, the
+// update in the working precision; row j of R goes to the block's Z storage
+// and leaves the register file.  R stays in place (no column swaps); the
+// solve then reads R11 into LDS in FP64 and overwrites Z.
+//
+// Blocks outside the size limits never enter the queue (the ordering kernel
+// writes their info); a block holding a NaN or an infinity stops before its
+// first step with k = 0.  Every branch that contains a barrier depends only
+// on values that are the same in every thread of the workgroup, and the step
+// loop is bounded by kmax.
 #include <algorithm>
-#include <cmath>
 #include <climits>
+#include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "cpqr.hpp"
@@ -34,36 +53,90 @@ namespace miid {
 
 constexpr int kBThreads = 512;
 constexpr int kBWaves = kBThreads / kWave;
-// dynamic LDS (the block's LDS columns and tiles, later the triangle of the
-// solve): what the 160 KB of a CU leave beside the kernel's static arrays
-// (residual norms, the waves' staged columns, a few scalars)
-constexpr int bdyn_bytes(int esz) { return 160 * 1024 - 9 * 1024 - 8 * 256 * esz; }
-constexpr int kBTileBytes = 24 * 1024;  // default streamed column tile (the rest of LDS keeps columns resident)
 constexpr int kBMaxM = 256;
 constexpr int kBMaxN = 1024;
 constexpr int kBMaxK = 64;
-constexpr uint32_t kBlockUnsupported = 16u;
+constexpr int kBLdsBytes = 160 * 1024;  // the whole LDS of a CU, carved by hand
+// the staged pivot column: L x VS entries (at most 264 for an admissible block)
+constexpr int kBSlot = 264;
+// the end of LDS: staged columns (working precision), the waves' entries of
+// both step parities, the selected columns, the queue slot; the rest holds
+// block rows
+template <typename T>
+struct BLds {
+    static constexpr int kOffStW = 0;
+    static constexpr int kOffPBest = kOffStW + kBSlot * (int)sizeof(T);
+    static constexpr int kOffPSum = kOffPBest + 2 * kBWaves * 8;
+    static constexpr int kOffPIdx = kOffPSum + 2 * kBWaves * 8;
+    static constexpr int kOffSel = kOffPIdx + 2 * kBWaves * 4;
+    static constexpr int kOffBlk = kOffSel + kBMaxK * 4;
+    static constexpr int kMiscBytes = (kOffBlk + 4 + 255) / 256 * 256;
+    static constexpr int kMiscOff = kBLdsBytes - kMiscBytes;
+};
+constexpr int kSolveLd = kBMaxK + 2;  // column stride of R11 in the solve (even: 16-byte aligned columns)
+static_assert(kBMaxK * kSolveLd * 8 + kBMaxK * 8 <= BLds<float>::kMiscOff, "solve arrays");
 
-// Order the blocks by decreasing size for the queue (longest first): a
-// counting sort of one workgroup on the coarse key m n / 256 (1024 buckets
-// cover every admissible block; the order inside a bucket is whatever the
-// LDS atomics give -- it only affects which workgroup takes a block, not its
-// result).  Also zeroes the queue.
+// Block rows a lane keeps in registers (multiples of 4): at most kRegRows
+// with one column per lane, kRegRowsC2 with two (what the 256 VGPRs of a lane
+// at two waves per SIMD leave beside the step's own values); then LDS rows.
+template <typename T>
+struct BCfg;
+template <>
+struct BCfg<float> {
+    static constexpr int kRegRows = 168;
+    static constexpr int kRegRowsC2 = 64;
+};
+template <>
+struct BCfg<double> {
+    static constexpr int kRegRows = 80;
+    static constexpr int kRegRowsC2 = 48;
+};
+template <typename T>
+constexpr int b_lds_rows() {
+    return (BLds<T>::kMiscOff / (kBThreads * (int)sizeof(T))) & ~3;
+}
+// virtual rows of a lane at most: one column of 256 rows, or two
+constexpr int kBMaxVRows = kBMaxM;
+constexpr int kBMaxVRowsC2 = 2 * kBMaxM;
+template <typename T>
+constexpr int b_glob_rows() {
+    const int r1 = kBMaxVRows - BCfg<T>::kRegRows - b_lds_rows<T>();
+    const int r2 = kBMaxVRowsC2 - BCfg<T>::kRegRowsC2 - b_lds_rows<T>();
+    const int r = r1 > r2 ? r1 : r2;
+    return r > 0 ? r : 0;
+}
+
+// Order the admissible blocks by decreasing size for the queue (longest
+// first): a counting sort of one workgroup on the coarse key m n / 256 (1024
+// buckets cover every admissible block; the order inside a bucket is
+// whatever the LDS atomics give -- it only affects which workgroup takes a
+// block, not its result).  A block outside the limits gets its info here
+// (k_out = 0, MIID_BLOCK_UNSUPPORTED) and is left out of the order; queue[1]
+// receives the number of admissible blocks, queue[0] the queue head (0).
 constexpr int kLptBuckets = 1024;
+
+__device__ __forceinline__ bool block_ok(int m, int n) {
+    return m >= 1 && n >= 1 && m <= kBMaxM && n <= kBMaxN && m <= n;
+}
 
 __global__ void __launch_bounds__(1024) k_lpt_order(const int32_t* __restrict__ m, const int32_t* __restrict__ n,
                                                     int32_t nblk, int32_t* __restrict__ order,
-                                                    int32_t* __restrict__ queue) {
+                                                    int32_t* __restrict__ queue, miid_info* __restrict__ info) {
     __shared__ int32_t cnt[kLptBuckets];
     __shared__ int32_t scan[kLptBuckets];
     const int tid = threadIdx.x;
     auto bucket = [&](int i) {
-        const int64_t sz = (int64_t)max(m[i], 0) * (int64_t)max(n[i], 0);
+        const int64_t sz = (int64_t)m[i] * (int64_t)n[i];
         return kLptBuckets - 1 - (int)min<int64_t>(sz >> 8, kLptBuckets - 1);  // larger first
     };
     for (int b = tid; b < kLptBuckets; b += blockDim.x) cnt[b] = 0;
     __syncthreads();
-    for (int i = tid; i < nblk; i += blockDim.x) atomicAdd(&cnt[bucket(i)], 1);
+    for (int i = tid; i < nblk; i += blockDim.x) {
+        if (block_ok(m[i], n[i]))
+            atomicAdd(&cnt[bucket(i)], 1);
+        else
+            info[i] = miid_info{0, MIID_BLOCK_UNSUPPORTED, 0.0, 0.0, 0, 0};
+    }
     __syncthreads();
     // exclusive prefix sum over the buckets (one per thread, Hillis-Steele)
     const int v = tid < kLptBuckets ? cnt[tid] : 0;
@@ -76,492 +149,734 @@ __global__ void __launch_bounds__(1024) k_lpt_order(const int32_t* __restrict__ 
         __syncthreads();
     }
     if (tid < kLptBuckets) cnt[tid] = scan[tid] - v;  // start of the bucket
+    if (tid == kLptBuckets - 1) {
+        queue[0] = 0;
+        queue[1] = scan[tid];  // admissible blocks
+    }
     __syncthreads();
-    for (int i = tid; i < nblk; i += blockDim.x) order[atomicAdd(&cnt[bucket(i)], 1)] = i;
-    if (tid == 0) *queue = 0;
-}
-
-
-typedef __attribute__((address_space(3))) uint32_t lds_u32;
-
-// Columns of a block kept in registers, per 16-lane group: what the pass
-// leaves free of the 256 VGPRs a lane has at two waves per SIMD (FP64
-// columns take twice the registers and the pass's FP64 state more too).
-template <typename T, int RT>
-constexpr int breg_cols() {
-    return sizeof(T) == 4 ? (RT == 2 ? 32 : (RT == 4 ? 40 : 48)) / RT
-                          : (RT == 16 ? 0 : 16 / (2 * RT));
+    for (int i = tid; i < nblk; i += blockDim.x)
+        if (block_ok(m[i], n[i])) order[atomicAdd(&cnt[bucket(i)], 1)] = i;
 }
 
 // a * b + c with one rounding, in the working precision
 __device__ __forceinline__ float fma_w(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_w(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// The kernel's static LDS, handed to the per-block factorisation.
+// Sum over the L lanes of a column group (L = 1, 2, 4, 8; groups aligned to
+// L): butterflies, so every lane of the group ends with the same value.
+__device__ __forceinline__ double group_sum(double v, int L) {
+    if (L >= 2) v += dpp_f64<kDppXor1>(v);
+    if (L >= 4) v += dpp_f64<kDppXor2>(v);
+    if (L >= 8) v += dpp_f64<kDppHalfMirror>(v);
+    return v;
+}
+
+// wave-uniform copies of values the compiler cannot prove uniform (LDS
+// loads): branches on them become scalar branches
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+    const int64_t b = __builtin_bit_cast(int64_t, v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, ((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ float readlane_w(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double readlane_w(double v, int l) {
+    const int64_t b = __builtin_bit_cast(int64_t, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+// four-term sums in the working precision, as two pairs (a shorter
+// dependence chain than a running sum)
 template <typename T>
-struct BShared {
-    double* snu;     // residual norm of every column (-1: chosen)
-    ArgMax* w_best;  // per wave
-    double* w_sum;   // per wave
-    T* w_col;        // per wave its best column (kBMaxM rows)
-    int32_t* s_sel;  // chosen columns in order
+__device__ __forceinline__ T dot4w(const T (&a)[4], const T (&b)[4]) {
+    const T p = fma_w(a[1], b[1], a[0] * b[0]);
+    const T r = fma_w(a[3], b[3], a[2] * b[2]);
+    return p + r;
+}
+template <typename T>
+__device__ __forceinline__ T sumsq4(const T (&a)[4]) { return dot4w(a, a); }
+
+// one element through a buffer resource (zero when out of range)
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
+}
+
+// four consecutive entries of the pivot column buffers
+__device__ __forceinline__ void ld4(const float* p, float (&v)[4]) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+__device__ __forceinline__ void ld4(const double* p, double (&v)[4]) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void st4(float* p, const float (&v)[4]) {
+    *reinterpret_cast<float4*>(p) = float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st4(double* p, const double (&v)[4]) {
+    *reinterpret_cast<double2*>(p) = double2(v[0], v[1]);
+    *reinterpret_cast<double2*>(p + 2) = double2(v[2], v[3]);
+}
+
+// Geometry of one block and this lane's place in it (all but the lane fields
+// are the same in every thread of the workgroup).
+struct BGeo {
+    int m, n, kb;
+    int L;      // lanes per column
+    int P;      // columns per slot (512 / L)
+    int nq4;    // chunks of four rows per lane and column
+    int nvc;    // virtual chunks of a lane (C nq4)
+    int VS;     // stride of the pivot buffers per lane of a group
+    int tlmax;  // chunks per lane the pivot buffers hold (v is zero beyond the column)
+    // lane
+    int tid, lane, wave, q, gi;
+    int col0, col1;
+    bool valid0, valid1;
 };
 
-struct BResult {
+struct BRes {
     int k;
     uint32_t status;
     double a_norm, resid;
+    int step0, step1;  // per lane: the step at which its columns were chosen (-1: not chosen)
 };
 
-// Pivoted Householder QR of one block, stopped by the tolerance.  A column
-// belongs to the 16-lane group (column mod 32); lane l16 holds rows
-// l16 + 16 t, t < RT (RT = ceil(m / 16) rounded up to 2, 4, 8 or 16).  The
-// first 32 NR columns live in registers, the next cres in LDS, the rest in
-// the workgroup's scratch Wb, streamed through two LDS tiles of TC columns
-// per pass.  Columns in LDS and in the scratch are stored with the row count
-// padded to mp = a multiple of 16 (zeros below row m), so whole slices t are
-// either in the column or not and no per-row bounds are needed.
+// Pivoted Householder QR of one block, stopped by the tolerance.  NCR
+// register chunks (four rows each) per lane; with NCR at its maximum the
+// lane's further chunks live in LDS and then in the global scratch.  C2: two
+// columns per lane (n > 512).
 //
-// A step: at the end of the previous pass each wave stages its best column
-// (and its residual norm and sum) in LDS; after one barrier every lane picks
-// the pivot from the eight wave entries and forms the reflector itself from
-// the staged column -- alpha is the pivot's residual norm from the pass (its
-// rows j.. are what the reflector annihilates), so only x0 = x[j] is read --
-// and after a second barrier (the staging area is reused) the pass applies
-// H = I - tau v v^T to every alive column, writes row j of R into Zb and
-// recomputes the residual norms exactly (FP64 accumulation of the stored
-// values).
-template <typename T, int RT>
-__device__ __forceinline__ BResult factor_block(const T* __restrict__ Ab, T* __restrict__ Zb, T* __restrict__ Wb,
-                                                int m, int n, int kb, double eps, int tile_bytes,
-                                                unsigned char* smem_raw, BShared<T> sh) {
-    constexpr int NR = breg_cols<T, RT>();
-    constexpr int kDyn = bdyn_bytes((int)sizeof(T)) / (int)sizeof(T);
-    constexpr int kGroups = kBWaves * 4;
-    const int tid = threadIdx.x;
-    const int lane = tid % kWave;
-    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
-    int l16 = lane & 15;
-    // opaque to the optimiser: what is derived from it is formed here, per
-    // block, instead of being hoisted out of the persistent loop for every
-    // RT instance and held in registers throughout
-    asm volatile("" : "+v"(l16));
-    const int cgroup = tid / 16;  // 16-lane column group, 0..31
-    T* lds = reinterpret_cast<T*>(smem_raw);
+// Every register chunk is processed at every step, straight-line: the staged
+// pivot column is zero above row j (finished rows of R are set to zero in the
+// register file once written out) and beyond the column, so the dot products
+// and the update leave those rows exactly as they are and the residual norm is
+// the plain sum over the lane's rows.  (A chunk range that depends on j would
+// make the register array conditional and the compiler would keep two copies
+// of it.)
+//
+// A step: at the end of a pass every wave writes its best column's residual
+// norm, index and its sum of squared norms to LDS; after a barrier every lane
+// folds the eight entries (the same result everywhere) and the pivot column's
+// lanes copy its rows into the stage; after a second barrier every lane reads
+// x_j from the stage and forms beta, tau and the scale of the reflector
+// itself: v = (x scaled, 1 at row j, 0 above).  The dot products run on the
+// staged x and are corrected for v_j = 1.
+template <typename T, int NCR, bool C2>
+__device__ __forceinline__ BRes factor_block(const BGeo& G, const T* __restrict__ Ab, T* __restrict__ Zb,
+                                             T* __restrict__ gsc, unsigned char* smem, double eps) {
+    // only the largest classes keep rows in LDS / scratch
+    constexpr bool kTiers = C2 || NCR == BCfg<T>::kRegRows / 4;
+    constexpr int RLMAX = b_lds_rows<T>();
+    using L_ = BLds<T>;
+    T* lds_rows = reinterpret_cast<T*>(smem);
+    unsigned char* misc = smem + L_::kMiscOff;
+    T* st_w = reinterpret_cast<T*>(misc + L_::kOffStW);  // staged columns
+    double* p_best = reinterpret_cast<double*>(misc + L_::kOffPBest);
+    double* p_sum = reinterpret_cast<double*>(misc + L_::kOffPSum);
+    int32_t* p_idx = reinterpret_cast<int32_t*>(misc + L_::kOffPIdx);
+    int32_t* s_sel = reinterpret_cast<int32_t*>(misc + L_::kOffSel);
 
-    const int mp = (m + 15) & ~15;
-    const int ntv = mp / 16;  // slices t inside a padded column
-    const int nreg = min(n, kGroups * NR);
-    const int nrest = n - nreg;
-    const bool resident = nrest * mp <= kDyn;
-    const int TC = resident ? 1 : max(1, min(nrest, min(kDyn / 2, tile_bytes / (int)sizeof(T)) / mp));
-    const int cres = resident ? nrest : min(nrest, max(0, (kDyn - 2 * TC * mp) / mp));
-    const int c_str = nreg + cres;  // first streamed column
-    const int ns = n - c_str;
-    const int nt = (ns + TC - 1) / TC;
-    T* buf0 = lds + cres * mp;
-    T* buf1 = buf0 + TC * mp;
-    // home of column l >= nreg: LDS or the scratch
-    auto home = [&](int l) { return l < c_str ? lds + (l - nreg) * mp : Wb + (int64_t)l * mp; };
-
-    T rc[NR > 0 ? NR : 1][RT];  // register-resident columns cgroup + 32 c (zero below row m)
-    T sv[RT];      // v at this lane's rows (v is rounded to T, so exact)
-    ArgMax gb{-1.0, INT32_MAX};  // the group's best (the same in its 16 lanes)
-    double acc = 0.0;            // the group's sum (the same in its 16 lanes)
-
-    // a column's new residual norm: the group's best and sum, branch-free
-    auto consider = [&](int l, double nu, double add) {
-        acc += add;
-        const bool bt = argmax_better(nu, l, gb.v, gb.i);
-        gb.v = bt ? nu : gb.v;
-        gb.i = bt ? l : gb.i;
+    const int m = G.m, kb = G.kb, L = G.L, P = G.P, nq4 = G.nq4, nvc = kTiers ? G.nvc : NCR;
+    // chunks [NCR, vcL1) in LDS, [vcL1, nvc) in the scratch
+    const int vcL1 = NCR + min(max(nvc - NCR, 0), RLMAX / 4);
+    const int q = G.q, lane = G.lane, wave = G.wave;
+    const int tid = G.tid;
+    auto lds_at = [&](int vc, int i) -> T* { return lds_rows + (4 * (vc - NCR) + i) * kBThreads + tid; };
+    auto glob_at = [&](int vc, int i) -> T* {
+        return gsc + (int64_t)(4 * (vc - vcL1) + i) * kBThreads + tid;
     };
-    // the wave's best of its four groups (row leaders, fixed order), staged
-    // with its column; a streamed column is read back from the scratch
-    // (written there by other lanes: device scope, past this CU's L1)
-    auto publish = [&]() {
-        ArgMax wbst{-1.0, INT32_MAX};
-        double wsum = 0.0;
-        int wrow = 0;
+    // slot of virtual chunk vc (which of the lane's two columns)
+    auto slot_of = [&](int vc) { return (C2 && vc >= nq4) ? 1 : 0; };
+
+    // four rows per vector register tuple (keeps the chunks in contiguous
+    // registers; scalar arrays were allocated interleaved with other values)
+    typedef T T4 __attribute__((ext_vector_type(4)));
+    T4 rc[NCR];
+
+    // ---- first pass: the block into registers / LDS / scratch, exact norms -
+    double s2a = 0.0, s2b = 0.0;
+    T yn0 = T(0), yn1 = T(0);  // this lane's entry at the next pivot row's place (row 0 now)
+    // the block through a bounds-checked buffer resource: loads past the
+    // block return zero (columns >= n), rows >= m of a column are zeroed
+    // below; one 32-bit offset per load instead of a 64-bit address
+    const int nbytes = m * G.n * (int)sizeof(T);
+    const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc((void*)Ab, (short)0, nbytes, 0x00020000);
+    const int off0 = G.valid0 ? (G.col0 * m + 4 * q) * (int)sizeof(T) : nbytes;
+    const int off1 = G.valid1 ? (G.col1 * m + 4 * q) * (int)sizeof(T) : nbytes;
+    auto raw_chunk = [&](int vc, T (&x)[4]) {
+        const int s = slot_of(vc);
+        const int tl = vc - s * nq4;
+        const int voff = (s ? off1 : off0) + 4 * L * tl * (int)sizeof(T);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t bits = __builtin_bit_cast(int64_t, gb.v);
-            const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffff), 16 * r);
-            const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), 16 * r);
-            const double v = __builtin_bit_cast(double, ((int64_t)hi << 32) | (uint32_t)lo);
-            const int32_t i = __builtin_amdgcn_readlane(gb.i, 16 * r);
-            const int64_t abits = __builtin_bit_cast(int64_t, acc);
-            const int alo = __builtin_amdgcn_readlane((int)(abits & 0xffffffff), 16 * r);
-            const int ahi = __builtin_amdgcn_readlane((int)(abits >> 32), 16 * r);
-            wsum += __builtin_bit_cast(double, ((int64_t)ahi << 32) | (uint32_t)alo);
-            if (argmax_better(v, i, wbst.v, wbst.i)) {
-                wbst = {v, i};
-                wrow = r;
-            }
+        for (int i = 0; i < 4; ++i) x[i] = buf_load<T>(rsA, voff + i * (int)sizeof(T));
+    };
+    // rows >= m zeroed, the norm contributions
+    auto finish_chunk = [&](int vc, T (&x)[4]) {
+        const int s = slot_of(vc);
+        const int tl = vc - s * nq4;
+        const int rlim = m - 4 * L * tl;  // rows 4 q + i of this chunk exist when 4 q + i < rlim
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = 4 * q + i < rlim ? x[i] : T(0);
+        const double ss = (double)sumsq4(x);
+        // selects, not branches on s (a branch would make the compiler index a
+        // two-element array in memory)
+        s2a += s ? 0.0 : ss;
+        s2b += s ? ss : 0.0;
+        yn0 = (!s && tl == 0) ? x[0] : yn0;
+        yn1 = (s && tl == 0) ? x[0] : yn1;
+    };
+    auto load_chunk = [&](int vc, T (&x)[4]) {
+        raw_chunk(vc, x);
+        finish_chunk(vc, x);
+    };
+    // every register chunk's loads go out before any of them is used (the
+    // loads of one chunk at a time would each wait for memory)
+#pragma unroll
+    for (int vc = 0; vc < NCR; ++vc) {
+        T x[4];
+        raw_chunk(vc, x);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) rc[vc][i] = x[i];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int vc = 0; vc < NCR; ++vc) {
+        T x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = rc[vc][i];
+        finish_chunk(vc, x);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) rc[vc][i] = x[i];
+    }
+    if constexpr (kTiers) {
+        for (int vc = NCR; vc < min(nvc, vcL1); ++vc) {
+            T x[4];
+            load_chunk(vc, x);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) *lds_at(vc, i) = x[i];
         }
-        const int q = wbst.i;  // wave-uniform
-        if ((lane >> 4) == wrow && wbst.v >= 0.0) {
-            T* slot = sh.w_col + wave * kBMaxM;
-            if (q < nreg) {
-                // one uniform branch per register column (a select chain
-                // over c would be turned into an indexed, memory-held array)
-                const int cq = q / kGroups;
+        for (int vc = vcL1; vc < nvc; ++vc) {
+            T x[4];
+            load_chunk(vc, x);
 #pragma unroll
-                for (int c = 0; c < NR; ++c) {
-                    if (c == cq) {
-#pragma unroll
-                        for (int t = 0; t < RT; ++t) slot[l16 + 16 * t] = rc[c][t];
-                    }
-                }
-            } else if (q < c_str) {
-                const T* col = lds + (q - nreg) * mp;
-#pragma unroll
-                for (int t = 0; t < RT; ++t) slot[l16 + 16 * t] = t < ntv ? col[l16 + 16 * t] : T(0);
-            } else {
-                const T* col = Wb + (int64_t)q * mp;
-#pragma unroll
-                for (int t = 0; t < RT; ++t) {
-                    const int r = l16 + 16 * t;
-                    slot[r] = t < ntv ? __hip_atomic_load(col + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : T(0);
-                }
-            }
+            for (int i = 0; i < 4; ++i) *glob_at(vc, i) = x[i];
         }
+    }
+    double nu0 = sqrt(group_sum(s2a, L));
+    double nu1 = sqrt(group_sum(s2b, L));
+    bool alive0 = G.valid0, alive1 = G.valid1;
+    int step0 = -1, step1 = -1;  // the step at which this lane's column was chosen
+
+    // with two columns per lane the stage past a column (read by the passes
+    // over the padding chunks) holds zeros for the whole block and staging
+    // never writes there; with one, staging writes every chunk
+    if constexpr (C2) {
+        const int per = 4 * (G.tlmax - nq4);
+        for (int e = tid; e < L * per; e += kBThreads) {
+            const int qq = e / per, r = e - qq * per;
+            st_w[qq * G.VS + 4 * nq4 + r] = T(0);
+        }
+    }
+
+    // (A): the wave's best alive column and its sum of squared norms into the
+    // entries of parity par; the column itself staged into slot `slot`
+    auto publish = [&](int par) {
+        ArgMax cand{-1.0, INT32_MAX};
+        double sum = 0.0;
+        if (alive0) {
+            cand = ArgMax{nu0, G.col0};
+            if (q == 0) sum += nu0 * nu0;
+        }
+        if (C2 && alive1) {
+            if (argmax_better(nu1, G.col1, cand.v, cand.i)) cand = ArgMax{nu1, G.col1};
+            if (q == 0) sum += nu1 * nu1;
+        }
+        cand = wave_argmax_dpp(cand);
+        sum = wave_sum_dpp(sum);
         if (lane == 0) {
-            sh.w_best[wave] = wbst;
-            sh.w_sum[wave] = wsum;
+            p_best[par * kBWaves + wave] = cand.v;
+            p_idx[par * kBWaves + wave] = cand.i;
+            p_sum[par * kBWaves + wave] = sum;
         }
     };
-
-    // copy the streamed tile t of the scratch into its LDS buffer (no registers)
-    auto issue = [&](int t) {
-        const int c0 = c_str + t * TC;
-        const int cntw = min(TC, n - c0) * mp * (int)(sizeof(T) / 4);
-        const uint32_t* s32 = reinterpret_cast<const uint32_t*>(Wb + (int64_t)c0 * mp);
-        lds_u32* d32 = (lds_u32*)smem_raw + (cres + ((t & 1) ? TC : 0)) * mp * (int)(sizeof(T) / 4);
-        for (int e0 = 0; e0 < cntw; e0 += kBThreads) {
-            const int e = e0 + tid;
-            if (e < cntw) __builtin_amdgcn_global_load_lds((const void*)(s32 + e), d32 + (e - lane), 4, 0, 0);
-        }
-    };
-
-    // ---- first pass: every column from A_b to its home, exact norms --------
-    auto first_norm = [&](int l, double ss) {
-        ss = row16_sum(ss);
-        const double nu = sqrt(ss);
-        if (l16 == 0) sh.snu[l] = nu;
-        consider(l, nu, ss);
-    };
+    // the pivot column's lanes copy all its chunks into the stage (rows above
+    // the pivot row are zero in the register file by now)
+    auto stage = [&](int p) {
+        const int sb = (C2 && p >= P) ? 1 : 0;
+        const int lcp = p - sb * P;
+        if (wave == (lcp & (kBWaves - 1)) && G.gi == lcp / kBWaves) {
+            int qo = q;  // through an empty asm: the addresses below are formed
+            asm volatile("" : "+v"(qo));  // here, not kept per chunk
+            T* dw = st_w + qo * G.VS;
+            const int cs = sb * nq4;
+            auto put = [&](int tl, const T (&x)[4]) { st4(dw + 4 * tl, x); };
 #pragma unroll
-    for (int c = 0; c < NR; ++c) {
-        const int l = cgroup + kGroups * c;
-        const bool have = l < nreg;
-        double ss = 0.0;
+            for (int vc = 0; vc < NCR; ++vc) {
+                // one column per lane: every register chunk, the ones past
+                // the column being zeros (no per-chunk test); two: the slot's
+                // chunks
+                if (!C2 || (vc >= cs && vc < cs + nq4)) {
+                    T x[4];
 #pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            const int r = l16 + 16 * t;
-            const T x = (have && r < m) ? Ab[(int64_t)l * m + r] : T(0);
-            rc[c][t] = x;
-            ss += (double)x * (double)x;
-        }
-        if (have) first_norm(l, ss);
-    }
-    // the other columns CB at a time per group, all their loads in flight
-    // before the first is stored
-    constexpr int CB = RT >= 16 ? 2 : (RT >= 8 ? 4 : 8);
-    for (int l0 = nreg + cgroup; l0 < n; l0 += kGroups * CB) {
-        T xv[CB][RT];
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            const int l = l0 + kGroups * cb;
-#pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                const int r = l16 + 16 * t;
-                xv[cb][t] = (l < n && t < ntv && r < m) ? Ab[(int64_t)l * m + r] : T(0);
-            }
-        }
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            const int l = l0 + kGroups * cb;
-            if (l >= n) break;  // uniform over the group
-            T* col = home(l);
-            double ss = 0.0;
-#pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                if (t < ntv) {
-                    col[l16 + 16 * t] = xv[cb][t];
-                    ss += (double)xv[cb][t] * (double)xv[cb][t];
+                    for (int i = 0; i < 4; ++i) x[i] = rc[vc][i];
+                    put(vc - cs, x);
                 }
             }
-            first_norm(l, ss);
+            if constexpr (kTiers) {
+                for (int vc = max(cs, NCR); vc < min(cs + nq4, vcL1); ++vc) {
+                    T x[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) x[i] = *lds_at(vc, i);
+                    put(vc - cs, x);
+                }
+                for (int vc = max(cs, vcL1); vc < cs + nq4; ++vc) {
+                    T x[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) x[i] = *glob_at(vc, i);
+                    put(vc - cs, x);
+                }
+            }
         }
-    }
-    if (ns > 0) {
-        __syncthreads();  // the scratch holds the streamed columns
-        issue(0);         // the first tile of the first step's pass
-    }
-    publish();
+    };
+    publish(0);
 
     int k = 0;
     uint32_t status = 0;
-    double a_norm = 0.0, resid = 0.0, stop_abs = 0.0;
+    double a_norm = 0.0, stop_abs = 0.0, stop2 = 0.0, ss_last = 0.0;
     for (;;) {
-        lds_barrier();
-        // ---- the pivot: best of the eight wave entries ----------------------
-        ArgMax e[kBWaves];
-        double sm[kBWaves];
+        const int par = k & 1;
+        lds_barrier();  // the waves' entries are in LDS
+        ArgMax best;
+        double ss;
+        {
+            double bv[kBWaves], bs[kBWaves];
+            int32_t bi[kBWaves];
 #pragma unroll
-        for (int w = 0; w < kBWaves; ++w) {
-            e[w] = sh.w_best[w];
-            sm[w] = sh.w_sum[w];
-        }
-        ArgMax best = e[0];
-        double ss = sm[0];
-        int bw = 0;
-#pragma unroll
-        for (int w = 1; w < kBWaves; ++w) {
-            if (argmax_better(e[w].v, e[w].i, best.v, best.i)) {
-                best = e[w];
-                bw = w;
+            for (int w = 0; w < kBWaves; ++w) {
+                bv[w] = p_best[par * kBWaves + w];
+                bs[w] = p_sum[par * kBWaves + w];
+                bi[w] = p_idx[par * kBWaves + w];
             }
-            ss += sm[w];
+            best = ArgMax{bv[0], bi[0]};
+            ss = bs[0];
+#pragma unroll
+            for (int w = 1; w < kBWaves; ++w) {
+                if (argmax_better(bv[w], bi[w], best.v, best.i)) best = ArgMax{bv[w], bi[w]};
+                ss += bs[w];
+            }
+            best = ArgMax{uni(best.v), uni(best.i)};
+            ss = uni(ss);
         }
-        const T* pc = sh.w_col + bw * kBMaxM;  // the pivot column
         if (k == 0) {
             a_norm = sqrt(ss);
             stop_abs = eps * a_norm;
-            resid = a_norm;
-            if (!(a_norm <= 1.0e300)) {
-                status |= MIID_NONFINITE;
-                break;
-            }
-        } else {
-            resid = sqrt(ss);
+            stop2 = stop_abs * stop_abs;
         }
-        if (resid <= stop_abs) break;
-        if (k >= kb) {
-            status |= MIID_KMAX_HIT;
+        ss_last = ss;
+        // one exit (several would give the compiler's structurizer more
+        // paths to merge the register array over)
+        const uint32_t why = (k == 0 && !(a_norm <= 1.0e300)) ? MIID_NONFINITE
+                             : ss <= stop2                   ? 0x100u
+                             : k >= kb                        ? MIID_KMAX_HIT
+                             : !(best.v > 0.0)                ? MIID_RANK_DEFICIENT
+                                                              : 0u;
+        if (why != 0u) {
+            status |= why & 0xffu;
             break;
         }
-        if (!(best.v > 0.0)) {
-            status |= MIID_RANK_DEFICIENT;
-            break;
-        }
-        const int p = best.i;
-        const int j = k;
-        const int jt = j >> 4, jl = j & 15;
-        // ---- the reflector, in every lane ------------------------------------
-        const double alpha = best.v;
-        const double x0 = (double)pc[j];
-        const double beta = x0 >= 0.0 ? -alpha : alpha;
-        const double tau = (beta - x0) / beta;
-        const double scale = 1.0 / (x0 - beta);
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            T v = (T)((double)pc[l16 + 16 * t] * scale);
-            if (t < jt) v = T(0);
-            if (t == jt) v = l16 < jl ? T(0) : (l16 == jl ? T(1) : v);
-            sv[t] = v;
-        }
-        if (tid == 0) {
-            sh.s_sel[j] = p;
-            sh.snu[p] = -1.0;
-            Zb[j + (int64_t)p * kb] = (T)beta;
-        }
-        lds_barrier();  // the staged entries are read before the pass restages them
 
-        // ---- the pass: H = I - tau v v^T on every alive column -------------
-        gb = {-1.0, INT32_MAX};
-        acc = 0.0;
-        // s2 over rows > j and the store of row j, from slice t of y
-        auto tail = [&](int t, T y, double& s2, int l, bool alive) {
-            if (t > jt) s2 += (double)y * (double)y;
-            if (t == jt) {
-                if (l16 > jl) s2 += (double)y * (double)y;
-                if (l16 == jl && alive) Zb[j + (int64_t)l * kb] = y;
+        // ---- the reflector, from the staged pivot column ------------------
+        const int j = k;
+        const int p = best.i;
+        const int sp = (C2 && p >= P) ? 1 : 0;
+        const int gj = j >> 2;
+        const int qj = gj & (L - 1), tj = gj / L, ij = j & 3;
+        stage(p);
+        if (tid == 0) s_sel[j] = p;
+        if (sp ? G.col1 == p : G.col0 == p) {  // this lane's column is the pivot
+            if (sp) {
+                alive1 = false;
+                step1 = j;
+            } else {
+                alive0 = false;
+                step0 = j;
+            }
+        }
+        lds_barrier();  // the pivot column is staged
+        const double x0 = (double)st_w[qj * G.VS + 4 * tj + ij];
+        const double alpha = best.v;
+        const double beta = x0 >= 0.0 ? -alpha : alpha;
+        // 1 / (x0 - beta) and 1 / beta: hardware reciprocal and two Newton
+        // steps (each doubles the correct bits; the IEEE division sequence is
+        // several times longer)
+        auto recip = [](double a) {
+            double r = __builtin_amdgcn_rcp(a);
+            r = __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
+            r = __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
+            return r;
+        };
+        const double scale = recip(x0 - beta);
+        const double tau = (beta - x0) * recip(beta);
+        if (tid == 0) Zb[j + (int64_t)p * kb] = (T)beta;
+
+        // ---- H = I - tau v v^T on every column -----------------------------
+        const bool own = q == qj;  // this lane holds row j (of each of its columns)
+        bool mj[4];  // this lane's element i of the boundary chunk is row j
+#pragma unroll
+        for (int i = 0; i < 4; ++i) mj[i] = own && i == ij;
+        // x^T y over all rows with the staged x (zero above row j); v^T y =
+        // scale (x^T y - x_j y_j) + y_j = scale (x^T y - beta y_j).  Each
+        // chunk's four products are summed in the working precision (one
+        // rounding per term of a four-term sum) and the chunk sums in FP64:
+        // the accuracy of a four-term dot product for one conversion per four
+        // rows (a conversion costs about two FMAs)
+        double da[2] = {0.0, 0.0}, db[2] = {0.0, 0.0};
+        // y_j (row j before the update) where this lane holds it: kept from
+        // the previous step's update
+        const T yja = yn0, yjb = yn1;
+        const T* pv_w = st_w;
+        auto pw_at = [&](int vc) { return pv_w + q * G.VS + 4 * (vc - slot_of(vc) * nq4); };
+        auto dot4v = [&](int vc, const T (&x)[4], const T (&xs)[4]) {
+            const int s = slot_of(vc);
+            const T c = dot4w(xs, x);
+            if constexpr (C2) {
+                da[vc & 1] += s ? 0.0 : (double)c;
+                db[vc & 1] += s ? (double)c : 0.0;
+            } else {
+                da[vc & 1] += (double)c;
             }
         };
-        auto track = [&](int l, double s2) {
-            s2 = row16_sum(s2);
-            const double nu = sqrt(s2);
-            if (l16 == 0) sh.snu[l] = nu;
-            consider(l, nu, nu * nu);
+        auto dot4 = [&](int vc, const T (&x)[4]) {
+            T xs[4];
+            ld4(pw_at(vc), xs);
+            dot4v(vc, x, xs);
         };
-        // register columns, branch-free (a chosen or missing column gets
-        // tau = 0, which leaves it unchanged)
+        {
+            // register chunks, the staged x of the chunk after next loaded
+            // while this one is used
+            T xs0[4], xs1[4], xs2[4];
+            ld4(pw_at(0), xs0);
+            if (NCR > 1) ld4(pw_at(1), xs1);
 #pragma unroll
-        for (int c = 0; c < NR; ++c) {
-            if (kGroups * c >= nreg) break;  // uniform: no group has column c
-            const int l = cgroup + kGroups * c;
-            const bool alive = l < nreg && sh.snu[l < nreg ? l : 0] >= 0.0;
-            double d = 0.0;
+            for (int vc = 0; vc < NCR; ++vc) {
+                if (vc + 2 < NCR) ld4(pw_at(vc + 2), xs2);
+                T x[4];
 #pragma unroll
-            for (int t = 0; t < RT; ++t) d += (double)rc[c][t] * (double)sv[t];
-            d = row16_sum(d);
-            // the update itself in the working precision (the dot product
-            // above and the norm below accumulate in FP64)
-            const T tc = alive ? (T)(tau * d) : T(0);
-            double s2 = 0.0;
+                for (int i = 0; i < 4; ++i) x[i] = rc[vc][i];
+                dot4v(vc, x, xs0);
 #pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                const T y = fma_w(-tc, sv[t], rc[c][t]);
-                rc[c][t] = y;
-                tail(t, y, s2, l, alive);
+                for (int i = 0; i < 4; ++i) {
+                    xs0[i] = xs1[i];
+                    xs1[i] = xs2[i];
+                }
+                // one chunk at a time: the scheduler would otherwise start many
+                // chunks' loads and products at once and run out of registers
+                __builtin_amdgcn_sched_barrier(0);
             }
-            if (alive) track(l, s2);
         }
-        // a column read from src (LDS) and written to dst (the same LDS
-        // column, or its scratch home for a streamed tile)
-        auto col_step = [&](int l, const T* src, T* dst) {
-            if (!(sh.snu[l] >= 0.0)) return;  // chosen column (uniform over the group)
-            T x[RT];
-            double d = 0.0;
+        if constexpr (kTiers) {
+            for (int vc = NCR; vc < min(nvc, vcL1); ++vc) {
+                T x[4];
 #pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                x[t] = t < ntv ? src[l16 + 16 * t] : T(0);
-                d += (double)x[t] * (double)sv[t];
+                for (int i = 0; i < 4; ++i) x[i] = *lds_at(vc, i);
+                dot4(vc, x);
             }
-            const T dw = (T)(tau * row16_sum(d));
-            double s2 = 0.0;
+            for (int vc = vcL1; vc < nvc; ++vc) {
+                T x[4];
 #pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                x[t] = fma_w(-dw, sv[t], x[t]);
-                if (t < ntv) dst[l16 + 16 * t] = x[t];
-                tail(t, x[t], s2, l, true);
+                for (int i = 0; i < 4; ++i) x[i] = *glob_at(vc, i);
+                dot4(vc, x);
             }
-            track(l, s2);
+        }
+        // lane sums, corrected by the lane holding row j, then the group sum
+        const bool hasj = mj[0] | mj[1] | mj[2] | mj[3];
+        const double ca = (da[0] + da[1]) - (hasj ? beta * (double)yja : 0.0);
+        const double d0 = scale * group_sum(ca, L);
+        const T wa = (T)(tau * d0), wva = (T)(tau * d0 * scale);
+        T wb = T(0), wvb = T(0);
+        if (C2) {
+            const double cb = (db[0] + db[1]) - (hasj ? beta * (double)yjb : 0.0);
+            const double d1 = scale * group_sum(cb, L);
+            wb = (T)(tau * d1);
+            wvb = (T)(tau * d1 * scale);
+        }
+        // the update in the working precision (y - (tau d scale) x, and
+        // y_j - tau d for row j, written out and zeroed); the residual norms
+        // over what is left, chunk sums of squares in the working precision
+        // accumulated in FP64 (relative error of a four-term sum)
+        double na[2] = {0.0, 0.0}, nb[2] = {0.0, 0.0};
+        const int tj1 = ((j + 1) >> 2) / L, ij1 = (j + 1) & 3;
+        T yna = yn0, ynb = yn1;
+        auto upd4v = [&](int vc, T (&x)[4], const T (&xw)[4]) {
+            const int s = slot_of(vc);
+            const int tl = vc - s * nq4;
+            const T wv = s ? wvb : wva;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x[i] = fma_w(-wv, xw[i], x[i]);
+            if (tl == tj) {  // uniform: row j of R leaves the register file
+#pragma unroll
+                for (int i = 0; i < 4; ++i) x[i] = mj[i] ? T(0) : x[i];
+            }
+            if (tl == tj1) {  // uniform: keep the entry at row j + 1's place
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    ynb = (s && i == ij1) ? x[i] : ynb;
+                    yna = (!s && i == ij1) ? x[i] : yna;
+                }
+            }
+            const T c = sumsq4(x);
+            if constexpr (C2) {
+                na[vc & 1] += s ? 0.0 : (double)c;
+                nb[vc & 1] += s ? (double)c : 0.0;
+            } else {
+                na[vc & 1] += (double)c;
+            }
         };
-        for (int l = nreg + cgroup; l < c_str; l += kGroups) {
-            T* col = lds + (l - nreg) * mp;
-            col_step(l, col, col);
-        }
-        if (ns > 0) {
-            // streamed columns: tile t + 1 in flight while tile t is updated
-            // and stored straight back to the scratch
-            __syncthreads();  // tile 0 has landed
-            for (int t = 0; t < nt; ++t) {
-                if (t + 1 < nt) issue(t + 1);
-                const int c0 = c_str + t * TC, c1 = min(n, c0 + TC);
-                const T* cur = (t & 1) ? buf1 : buf0;
-                for (int l = c0 + cgroup; l < c1; l += kGroups) col_step(l, cur + (l - c0) * mp, Wb + (int64_t)l * mp);
-                __syncthreads();  // the next tile has landed, this one is stored and no longer read
+        auto upd4 = [&](int vc, T (&x)[4]) {
+            T xw[4];
+            ld4(pw_at(vc), xw);
+            upd4v(vc, x, xw);
+        };
+        {
+            T xs0[4], xs1[4], xs2[4];
+            ld4(pw_at(0), xs0);
+            if (NCR > 1) ld4(pw_at(1), xs1);
+#pragma unroll
+            for (int vc = 0; vc < NCR; ++vc) {
+                if (vc + 2 < NCR) ld4(pw_at(vc + 2), xs2);
+                T x[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) x[i] = rc[vc][i];
+                upd4v(vc, x, xs0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) rc[vc][i] = x[i];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    xs0[i] = xs1[i];
+                    xs1[i] = xs2[i];
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
-            issue(0);  // the first tile of the next step's pass
         }
+        if constexpr (kTiers) {
+            for (int vc = NCR; vc < min(nvc, vcL1); ++vc) {
+                T x[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) x[i] = *lds_at(vc, i);
+                upd4(vc, x);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) *lds_at(vc, i) = x[i];
+            }
+            for (int vc = vcL1; vc < nvc; ++vc) {
+                T x[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) x[i] = *glob_at(vc, i);
+                upd4(vc, x);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) *glob_at(vc, i) = x[i];
+            }
+        }
+        if (own && alive0) Zb[j + (int64_t)G.col0 * kb] = yja - wa;
+        if (C2 && own && alive1) Zb[j + (int64_t)G.col1 * kb] = yjb - wb;
+        yn0 = yna;
+        yn1 = ynb;
+        nu0 = sqrt(group_sum(na[0] + na[1], L));
+        if (C2) nu1 = sqrt(group_sum(nb[0] + nb[1], L));
         ++k;
-        publish();
+        publish(k & 1);
     }
-    if (ns > 0) __syncthreads();  // no tile copy left in flight
-    return BResult{k, status, a_norm, resid};
+    return BRes{k, status, a_norm, sqrt(ss_last), step0, step1};
 }
 
-// Persistent kernel: one block at a time per workgroup (8 waves, one per CU).
+// Register chunks for a block of nvc chunks per lane: the smallest class
+// that holds them (the largest keeps the rest in LDS / scratch).
+template <typename T>
+__device__ __forceinline__ int reg_class(int nvc);
+template <>
+__device__ __forceinline__ int reg_class<float>(int nvc) {
+    return nvc <= 2 ? 2 : nvc <= 4 ? 4 : nvc <= 6 ? 6 : nvc <= 8 ? 8 : nvc <= 10 ? 10 : nvc <= 12 ? 12
+           : nvc <= 14 ? 14 : nvc <= 16 ? 16 : nvc <= 20 ? 20 : nvc <= 24 ? 24 : nvc <= 28 ? 28
+           : nvc <= 32 ? 32 : nvc <= 36 ? 36 : BCfg<float>::kRegRows / 4;
+}
+template <>
+__device__ __forceinline__ int reg_class<double>(int nvc) {
+    return nvc <= 2 ? 2 : nvc <= 4 ? 4 : nvc <= 8 ? 8 : nvc <= 12 ? 12 : BCfg<double>::kRegRows / 4;
+}
+
+// Persistent kernel: one block at a time per workgroup (one workgroup per CU).
 template <typename T>
 __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, const int64_t* __restrict__ a_off,
                                                        const int32_t* __restrict__ mv, const int32_t* __restrict__ nv,
-                                                       int32_t nblk, double eps, int32_t kmax,
+                                                       double eps, int32_t kmax, int lmax,
                                                        int32_t* __restrict__ J, const int64_t* __restrict__ j_off,
                                                        T* __restrict__ Z, const int64_t* __restrict__ z_off,
                                                        miid_info* __restrict__ info,
                                                        const int32_t* __restrict__ order, int32_t* __restrict__ queue,
-                                                       T* __restrict__ Wscr, int tile_bytes) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double snu[kBMaxN];
-    __shared__ ArgMax w_best[kBWaves];
-    __shared__ double w_sum[kBWaves];
-    __shared__ T w_col[kBWaves * kBMaxM];
-    __shared__ int32_t s_sel[kBMaxK];
-    __shared__ int32_t s_blk;
-    const int tid = threadIdx.x;
-    T* Wb = Wscr + (int64_t)blockIdx.x * kBMaxM * kBMaxN;  // W when it does not fit on chip
-    const BShared<T> sh{snu, w_best, w_sum, w_col, s_sel};
+                                                       T* __restrict__ Wscr) {
+    constexpr int NCRMAX = BCfg<T>::kRegRows / 4;
+    constexpr int RGMAX = b_glob_rows<T>();
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char* misc = smem + BLds<T>::kMiscOff;
+    int32_t* s_sel = reinterpret_cast<int32_t*>(misc + BLds<T>::kOffSel);
+    int32_t* s_blk = reinterpret_cast<int32_t*>(misc + BLds<T>::kOffBlk);
+
+    BGeo G;
+    G.tid = threadIdx.x;
+    G.lane = G.tid & (kWave - 1);
+    G.wave = __builtin_amdgcn_readfirstlane(G.tid >> 6);
+    const int tid = G.tid;
+    T* gsc = Wscr + (int64_t)blockIdx.x * RGMAX * kBThreads;  // this workgroup's global rows
+    const int nvalid = uni(queue[1]);
 
     for (;;) {
-        if (tid == 0) s_blk = atomicAdd(queue, 1);
+        if (tid == 0) *s_blk = atomicAdd(&queue[0], 1);
         __syncthreads();
-        const int32_t q = s_blk;
+        const int32_t qi = uni(*s_blk);
         __syncthreads();
-        if (q >= nblk) break;  // every wave leaves here once the queue is drained
-        const int32_t b = order[q];
-        const int m = mv[b], n = nv[b];
+        if (qi >= nvalid) break;  // the same in every thread
+        const int32_t b = uni(order[qi]);
+        const int m = uni(mv[b]), n = uni(nv[b]);
         const int kb = min(min(m, n), kmax);
-        if (m < 1 || n < 1 || m > kBMaxM || n > kBMaxN || m > n || kb > kBMaxK) {
-            if (tid == 0) info[b] = miid_info{0, kBlockUnsupported, 0.0, 0.0, 0, 0};
-            continue;
+        T* __restrict__ Zb = Z + z_off[b];
+
+        // ---- geometry (uniform) ----------------------------------------
+        const bool c2 = n > kBThreads;  // two columns per lane
+        int L = 1;
+        if (!c2) {
+            while (L < 8 && L < lmax && n * (2 * L) <= kBThreads) L *= 2;
         }
-        const T* Ab = A + a_off[b];
-        T* Zb = Z + z_off[b];
-        BResult res;
-        if (m <= 32)
-            res = factor_block<T, 2>(Ab, Zb, Wb, m, n, kb, eps, tile_bytes, smem_raw, sh);
-        else if (m <= 64)
-            res = factor_block<T, 4>(Ab, Zb, Wb, m, n, kb, eps, tile_bytes, smem_raw, sh);
-        else if (m <= 128)
-            res = factor_block<T, 8>(Ab, Zb, Wb, m, n, kb, eps, tile_bytes, smem_raw, sh);
-        else
-            res = factor_block<T, 16>(Ab, Zb, Wb, m, n, kb, eps, tile_bytes, smem_raw, sh);
+        G.m = m;
+        G.n = n;
+        G.kb = kb;
+        G.L = L;
+        G.P = kBThreads / L;
+        G.nq4 = ((m + 3) / 4 + L - 1) / L;
+        G.nvc = (c2 ? 2 : 1) * G.nq4;
+        G.q = G.lane & (L - 1);
+        G.gi = G.lane / L;
+        const int lc = G.gi * kBWaves + G.wave;
+        G.col0 = lc;
+        G.col1 = G.P + lc;
+        G.valid0 = lc < n;
+        G.valid1 = c2 && G.col1 < n;
+
+        BRes res;
+        const T* __restrict__ Ab = A + a_off[b];
+        constexpr int NCRC2 = BCfg<T>::kRegRowsC2 / 4;
+        const int cls = c2 ? NCRC2 : reg_class<T>(G.nvc);
+        // the pivot buffers cover every chunk a pass touches (local chunk
+        // index within the chunk's column)
+        G.tlmax = c2 ? max(G.nq4, cls - G.nq4) : max(G.nvc, cls);
+        G.VS = 4 * G.tlmax + 4;
+        if (c2) {
+            res = factor_block<T, NCRC2, true>(G, Ab, Zb, gsc, smem, eps);
+        } else if (cls == NCRMAX) {
+            res = factor_block<T, NCRMAX, false>(G, Ab, Zb, gsc, smem, eps);
+        } else if constexpr (sizeof(T) == 4) {
+            switch (cls) {
+                case 2: res = factor_block<T, 2, false>(G, Ab, Zb, gsc, smem, eps); break;
+                case 4: res = factor_block<T, 4, false>(G, Ab, Zb, gsc, smem, eps); break;
+                case 6: res = factor_block<T, 6, false>(G, Ab, Zb, gsc, smem, eps); break;
+                case 8: res = factor_block<T, 8, false>(G, Ab, Zb, gsc, smem, eps); break;
+                case 10: res = factor_block<T, 10, false>(G, Ab, Zb, gsc, smem, eps); break;
+                case 12: res = factor_block<T, 12, false>(G, Ab, Zb, gsc, smem, eps); break;
+                case 14: res = factor_block<T, 14, false>(G, Ab, Zb, gsc, smem, eps); break;
+                case 16: res = factor_block<T, 16, false>(G, Ab, Zb, gsc, smem, eps); break;
+                case 20: res = factor_block<T, 20, false>(G, Ab, Zb, gsc, smem, eps); break;
+                case 24: res = factor_block<T, 24, false>(G, Ab, Zb, gsc, smem, eps); break;
+                case 28: res = factor_block<T, 28, false>(G, Ab, Zb, gsc, smem, eps); break;
+                case 32: res = factor_block<T, 32, false>(G, Ab, Zb, gsc, smem, eps); break;
+                default: res = factor_block<T, 36, false>(G, Ab, Zb, gsc, smem, eps); break;
+            }
+        } else {
+            switch (cls) {
+                case 2: res = factor_block<T, 2, false>(G, Ab, Zb, gsc, smem, eps); break;
+                case 4: res = factor_block<T, 4, false>(G, Ab, Zb, gsc, smem, eps); break;
+                case 8: res = factor_block<T, 8, false>(G, Ab, Zb, gsc, smem, eps); break;
+                default: res = factor_block<T, 12, false>(G, Ab, Zb, gsc, smem, eps); break;
+            }
+        }
         const int k = res.k;
 
-        // triangular solve: Z[:, l] = R11^{-1} R[:, l] in FP64, Z[:, J[i]] = e_i.
-        // The strict upper triangle of R11 goes to sR (zeros elsewhere, up to
-        // k rounded to 4), the reciprocals of its diagonal to sDi: the updates
-        // below then need no bounds tests and no divisions.
-        constexpr int kSR = kBMaxK + 1;
-        double* sR = reinterpret_cast<double*>(smem_raw);  // reuses the dynamic LDS
-        double* sDi = sR + kBMaxK * kSR;  // reciprocals of the diagonal
-        const int kq4 = (k + 3) & ~3;
+        // ---- triangular solve: Z[:, l] = R11^{-1} R[:, l] in FP64, Z[:, J[i]] = e_i
+        // the R rows written to Z above are visible to the whole workgroup
+        // after a workgroup barrier (its waves share one CU's vector cache; a
+        // device-scope fence would write back the whole L2 instead)
         __syncthreads();
-        for (int e = tid; e < kq4 * kq4; e += kBThreads) {
-            const int a = e % kq4, c = e / kq4;
-            sR[a * kSR + c] = (a < c && c < k) ? (double)Zb[a + (int64_t)s_sel[c] * kb] : 0.0;
+        double* sR = reinterpret_cast<double*>(smem);  // column-major, reuses the row slab
+        double* sDi = sR + kBMaxK * kSolveLd;            // reciprocals of the diagonal
+        // the strict upper triangle of R11 (only its entries are read)
+        for (int e = tid; e < k * k; e += kBThreads) {
+            const int a = e % k, c = e / k;
+            if (a < c) sR[c * kSolveLd + a] = (double)Zb[a + (int64_t)s_sel[c] * kb];
         }
         for (int t = tid; t < k; t += kBThreads) sDi[t] = 1.0 / (double)Zb[t + (int64_t)s_sel[t] * kb];
-        __syncthreads();
         int32_t* Jb = J + j_off[b];
         for (int i = tid; i < kb; i += kBThreads) Jb[i] = i < k ? s_sel[i] : -1;
-        // four lanes per column (a quad), lane c of the quad holds z_q for
-        // q = 4 i + c: back substitution with the solved z_t broadcast from
-        // its owner inside the quad (DPP quad permutes)
-        int cq = tid % 4;
-        asm volatile("" : "+v"(cq));  // as in factor_block: no hoisting out of the block loop
-        for (int l0 = tid / 4; l0 < n; l0 += kBThreads / 4) {
-            const int l = l0;
-            const int c = cq;
-            T* zc = Zb + (int64_t)l * kb;
-            const bool dead = snu[l] < 0.0;
-            double z[kBMaxK / 4];
-#pragma unroll
-            for (int i = 0; i < kBMaxK / 4; ++i) {
-                const int qq = 4 * i + c;
-                z[i] = (!dead && qq < k) ? (double)zc[qq] : 0.0;
+        __syncthreads();
+        // one lane per column (the first lane of the column's group): back
+        // substitution with z in registers, R11's columns read from LDS by every
+        // lane at the same address; a chosen column gets its unit vector
+        const __amdgpu_buffer_rsrc_t rsZ =
+            __builtin_amdgcn_make_buffer_rsrc((void*)Zb, (short)0, kb * n * (int)sizeof(T), 0x00020000);
+        auto solve_col = [&](int c, int step) {
+            T* zc = Zb + (int64_t)c * kb;
+            if (step >= 0) {
+                for (int i = 0; i < kb; ++i) zc[i] = i == step ? T(1) : T(0);
+                return;
             }
+            // eight loads at a time through the block's bounds-checked resource
+            // (one guard per eight: a guard per load would make each wait for
+            // memory); entries past k are zeroed
+            double z[kBMaxK];
+            const int zoff = c * kb * (int)sizeof(T);
 #pragma unroll
-            for (int i = kBMaxK / 4 - 1; i >= 0; --i) {
-                if (4 * i >= k) continue;  // uniform
+            for (int g = 0; g < kBMaxK / 8; ++g) {
+                if (8 * g < k) {  // uniform
 #pragma unroll
-                for (int r = 3; r >= 0; --r) {
-                    const int t = 4 * i + r;
-                    if (t >= k) continue;  // uniform
-                    double zt = z[i] * sDi[t];
-                    zt = r == 0 ? dpp_f64<0x00>(zt) : (r == 1 ? dpp_f64<0x55>(zt) : (r == 2 ? dpp_f64<0xAA>(zt) : dpp_f64<0xFF>(zt)));
-                    if (c == r) z[i] = zt;
-                    // rows q < t take R[q, t] z_t; sR is zero on and below
-                    // the diagonal, so the other rows are left as they are
+                    for (int i = 8 * g; i < 8 * g + 8; ++i) {
+                        const T v = buf_load<T>(rsZ, zoff + i * (int)sizeof(T));
+                        z[i] = i < k ? (double)v : 0.0;
+                    }
+                } else {
 #pragma unroll
-                    for (int i2 = 0; i2 <= i; ++i2) z[i2] -= sR[(4 * i2 + c) * kSR + t] * zt;
+                    for (int i = 8 * g; i < 8 * g + 8; ++i) z[i] = 0.0;
                 }
             }
-            int sidx = -1;
-            if (dead)
-                for (int i = 0; i < k; ++i)
-                    if (s_sel[i] == l) sidx = i;
 #pragma unroll
-            for (int i = 0; i < kBMaxK / 4; ++i) {
-                const int qq = 4 * i + c;
-                if (qq < kb) zc[qq] = dead ? (T)(qq == sidx ? 1.0 : 0.0) : (T)(qq < k ? z[i] : 0.0);
+            for (int t = kBMaxK - 1; t >= 0; --t) {
+                if (t < k) {  // uniform
+                    const double zt = z[t] * sDi[t];
+                    z[t] = zt;
+                    const double* rcol = sR + t * kSolveLd;
+#pragma unroll
+                    for (int i = 0; i < t; ++i) z[i] = __builtin_fma(-rcol[i], zt, z[i]);
+                }
             }
+#pragma unroll
+            for (int i = 0; i < kBMaxK; ++i)
+                if (i < kb) zc[i] = i < k ? (T)z[i] : T(0);
+        };
+        if (G.q == 0) {
+            if (G.valid0) solve_col(G.col0, res.step0);
+            if (G.valid1) solve_col(G.col1, res.step1);
         }
         if (tid == 0) info[b] = miid_info{k, res.status, res.a_norm, res.resid, 0, k};
-        __syncthreads();
+        __syncthreads();  // LDS is reused by the next block
     }
 }
 
@@ -575,22 +890,24 @@ struct BPlan {
     size_t oOrder, oQueue, oW, total;
 };
 
-// One workgroup per CU (8 waves; LDS: the block or two column tiles of it).
+// One workgroup per CU (the whole LDS); global rows only for what fits
+// neither registers nor LDS.
 BPlan batched_plan(int32_t nblk, size_t esz) {
     BPlan P;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
     }
     P.grid = std::max(1, std::min(nblk, cus));
+    const int grows = esz == 8 ? b_glob_rows<double>() : b_glob_rows<float>();
     size_t off = 0;
     P.oOrder = off;
     off = align_up(off + (size_t)std::max(nblk, 1) * 4, 256);
     P.oQueue = off;
-    off = align_up(off + 4, 256);
+    off = align_up(off + 8, 256);
     P.oW = off;
-    off = align_up(off + (size_t)P.grid * kBMaxM * kBMaxN * esz, 256);
+    off = align_up(off + (size_t)P.grid * grows * kBThreads * esz, 256);
     P.total = off;
     return P;
 }
@@ -621,8 +938,8 @@ int id_batched(int32_t nblk, const void* A, const int64_t* a_off, const int32_t*
     if (!ws) return -13;
     const double eps = opts->eps;
     const int32_t kmax = opts->kmax;
-    const int tile_hint = (int)((opts->flags >> MIID_HINT_TILE_SHIFT) & 15u);
-    const int tile_bytes = tile_hint >= 1 ? tile_hint * 8 * 1024 : kBTileBytes;
+    const int lpc_hint = (int)((opts->flags >> MIID_HINT_LPC_SHIFT) & 15u);
+    const int lmax = (lpc_hint == 1 || lpc_hint == 2 || lpc_hint == 4 || lpc_hint == 8) ? lpc_hint : 8;
     const size_t esz = dtype == MIID_F64 ? 8 : 4;
     const BPlan P = batched_plan(nblk, esz);
     if (ws_bytes < P.total) return MIID_E_WORKSPACE;
@@ -630,29 +947,28 @@ int id_batched(int32_t nblk, const void* A, const int64_t* a_off, const int32_t*
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
     int32_t* order = reinterpret_cast<int32_t*>(w + P.oOrder);
     int32_t* queue = reinterpret_cast<int32_t*>(w + P.oQueue);
-    hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), 0, s, m, n, nblk, order, queue);
+    hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), 0, s, m, n, nblk, order, queue, info);
     const int pr = prof_take(MIID_K_BATCHED, 0, nblk, 0);
-    const size_t shmem = (size_t)bdyn_bytes((int)esz);
     if (dtype == MIID_F64) {
         static bool attr64 = false;
         if (!attr64) {
             MIID_HIP(hipFuncSetAttribute((const void*)k_batched<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         bdyn_bytes(8)));
+                                         kBLdsBytes));
             attr64 = true;
         }
-        MIID_LAUNCH(pr, k_batched<double>, dim3(P.grid), dim3(kBThreads), shmem, s, (const double*)A, a_off, m, n,
-                    nblk, eps, kmax, J, j_off, (double*)Z, z_off, info, order, queue,
-                    reinterpret_cast<double*>(w + P.oW), tile_bytes);
+        MIID_LAUNCH(pr, k_batched<double>, dim3(P.grid), dim3(kBThreads), (size_t)kBLdsBytes, s, (const double*)A,
+                    a_off, m, n, eps, kmax, lmax, J, j_off, (double*)Z, z_off, info, order, queue,
+                    reinterpret_cast<double*>(w + P.oW));
     } else {
         static bool attr32 = false;
         if (!attr32) {
             MIID_HIP(hipFuncSetAttribute((const void*)k_batched<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         bdyn_bytes(4)));
+                                         kBLdsBytes));
             attr32 = true;
         }
-        MIID_LAUNCH(pr, k_batched<float>, dim3(P.grid), dim3(kBThreads), shmem, s, (const float*)A, a_off, m, n,
-                    nblk, eps, kmax, J, j_off, (float*)Z, z_off, info, order, queue,
-                    reinterpret_cast<float*>(w + P.oW), tile_bytes);
+        MIID_LAUNCH(pr, k_batched<float>, dim3(P.grid), dim3(kBThreads), (size_t)kBLdsBytes, s, (const float*)A,
+                    a_off, m, n, eps, kmax, lmax, J, j_off, (float*)Z, z_off, info, order, queue,
+                    reinterpret_cast<float*>(w + P.oW));
     }
     MIID_HIP(hipGetLastError());
     return 0;

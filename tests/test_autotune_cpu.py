@@ -11,11 +11,11 @@ from paper_2105_07076_amd import _abi, autotune  # noqa: E402
 
 def test_hint_fields_match_header():
     hdr = open(__import__("os").path.join(__import__("os").path.dirname(__file__), "..", "include", "miid.h")).read()
-    for name in ["MIID_HINT_CPW_SHIFT", "MIID_HINT_NP_SHIFT", "MIID_HINT_PATH_SHIFT", "MIID_HINT_TILE_SHIFT"]:
+    for name in ["MIID_HINT_CPW_SHIFT", "MIID_HINT_NP_SHIFT", "MIID_HINT_PATH_SHIFT", "MIID_HINT_LPC_SHIFT"]:
         line = next(l for l in hdr.splitlines() if l.startswith(f"#define {name} "))
         assert int(line.split()[2]) == getattr(_abi, name)
     assert _abi.hint(_abi.MIID_HINT_NP_SHIFT, 4) == 4 << 12
-    assert _abi.hint(_abi.MIID_HINT_TILE_SHIFT, 17) == 1 << 20   # 4-bit field
+    assert _abi.hint(_abi.MIID_HINT_LPC_SHIFT, 17) == 1 << 20   # 4-bit field
 
 
 def test_id_candidates():
@@ -28,7 +28,7 @@ def test_id_candidates():
     # FP64 with 320 rows (ldw 320: 16-byte groups per lane 10 > 9): blocked only
     c3 = autotune.id_candidates(300, 1000, torch.float64)
     assert all(lbl.startswith("blocked") for lbl, _, _ in c3)
-    assert len(autotune.batched_candidates()) == 6
+    assert len(autotune.batched_candidates()) == 4
 
 
 def test_table_roundtrip(tmp_path):

@@ -50,16 +50,18 @@ def test_tune_rid_paths_agree():
         assert rel(to_np(r.Z).astype(np.float64), to_np(ref.Z).astype(np.float64)) <= 1e-5, label
 
 
-def test_tune_batched_tiles_identical():
-    """The streamed tile size changes the launch only: every candidate's
-    output is bit-identical."""
+def test_tune_batched_lane_caps_same_ids():
+    """The lanes-per-column cap changes the launch shape and the order of
+    the partial sums only: in FP64 every candidate selects the same columns
+    and its Z agrees to rounding."""
     miid, autotune, api = _mods()
     blocks = idgen.batched_blocks(seed=46, nblk=200)
-    A = torch.tensor(blocks.A, dtype=torch.float32, device="cuda")
+    A = torch.tensor(blocks.A, dtype=torch.float64, device="cuda")
     ch = autotune.tune_batched(A, blocks.a_off, blocks.m, blocks.n, 1e-6, 64, reps=2)
     assert len(ch.timings) == len(autotune.batched_candidates())
     ref = miid.batched(A, blocks.a_off, blocks.m, blocks.n, 1e-6, 64)
     for label, _, hints in autotune.batched_candidates():
         r = miid.batched(A, blocks.a_off, blocks.m, blocks.n, 1e-6, 64, hints=hints)
         assert np.array_equal(r.k, ref.k), label
-        assert torch.equal(r.J, ref.J) and torch.equal(r.Z, ref.Z), label
+        assert torch.equal(r.J, ref.J), label
+        assert rel(to_np(r.Z), to_np(ref.Z)) <= 1e-10, label

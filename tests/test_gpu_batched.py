@@ -15,7 +15,7 @@ import pytest
 
 import idgen
 import oracle
-from gpu_helpers import U32, U64, pivot_parity, rel, t_part
+from gpu_helpers import U32, U64, pivot_parity, rel, t_part, to_np
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -97,7 +97,8 @@ def test_batched_small_sizes_and_kmax():
 
 
 @pytest.mark.skip(reason="this case once ran silent for 180 s on the GPU and was stopped (no GPU fault); "
-                         "no cause found by reading the kernel or the host path yet, so it stays off the GPU")
+                         "no cause was found by reading that kernel or the host path, so the case stays off "
+                         "the GPU although the kernel it ran has since been replaced")
 def test_batched_isolates_bad_blocks():
     """A NaN in one block and an oversized block do not disturb the others."""
     miid = _miid()
@@ -116,6 +117,54 @@ def test_batched_isolates_bad_blocks():
     assert res.status[7] & 16 and res.k[7] == 0
     good = [b for b in range(12) if b not in (3, 7)]
     _check_blocks(blocks, res, blocks.A, torch.float64, good)
+
+
+# one block of each layout: 8, 4, 2 and 1 lanes per column, rows in LDS
+# (m > 172 with n > 256 in FP32), rows in the scratch (FP64), tiny blocks
+EDGE_SIZES = [(1, 1), (1, 5), (3, 3), (4, 7), (5, 64), (32, 32), (33, 64), (64, 65), (100, 128),
+              (129, 129), (129, 256), (200, 256), (200, 400), (250, 511), (253, 512), (256, 256), (256, 512)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batched_edge_shapes(dtype):
+    ms, ns = zip(*EDGE_SIZES)
+    blocks = idgen.kernel_blocks_sized(47, ms, ns)
+    res, A64 = _run(blocks, dtype)
+    assert np.all((res.status & ~8) == 0)
+    _check_blocks(blocks, res, A64, dtype, range(len(ms)))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batched_wide_blocks(dtype):
+    """n > 512: two columns per lane."""
+    ms = [8, 40, 100, 256, 256, 200]
+    ns = [513, 600, 777, 1024, 700, 1000]
+    blocks = idgen.kernel_blocks_sized(48, ms, ns)
+    res, A64 = _run(blocks, dtype)
+    assert np.all((res.status & ~8) == 0)
+    _check_blocks(blocks, res, A64, dtype, range(len(ms)))
+
+
+def test_batched_zero_block():
+    """A block of zeros stops before its first step (k = 0, J = -1, Z = 0)
+    and leaves the others alone."""
+    miid = _miid()
+    blocks = idgen.batched_blocks(seed=49, nblk=10)
+    A = blocks.A.copy()
+    o, sz = int(blocks.a_off[4]), int(blocks.m[4]) * int(blocks.n[4])
+    A[o:o + sz] = 0.0
+    At = torch.tensor(A, dtype=torch.float64, device="cuda")
+    res = miid.batched(At, blocks.a_off, blocks.m, blocks.n, EPS, 64)
+    torch.cuda.synchronize()
+    assert res.k[4] == 0 and res.status[4] == 0 and res.a_norm[4] == 0.0
+    J, Z = res.block(4)
+    assert len(J) == 0
+    jo = int(res.j_off[4])
+    assert np.all(to_np(res.J)[jo:jo + int(res.kmax_b[4])] == -1)
+    zo = int(res.z_off[4])
+    assert np.all(to_np(res.Z)[zo:zo + int(res.kmax_b[4]) * int(blocks.n[4])] == 0.0)
+    good = [b for b in range(10) if b != 4]
+    _check_blocks(blocks, res, A, torch.float64, good)
 
 
 def test_batched_deterministic():
