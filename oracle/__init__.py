@@ -201,11 +201,12 @@ def rid_sample(A: np.ndarray, idx: np.ndarray, k: int) -> tuple[np.ndarray, np.n
     indices) an input: A_S = A[:, idx]; the column-pivoted QR of A_S,
     truncated after k steps (Section 4.1), selects k of its columns (no
     transpose, A_S is usually tall); cols = idx[selected], C = A[:, cols];
-    R_k is the leading k x k triangle of A_S's factor, and Z solves the
-    symmetric system R_k^T R_k Z = C^T A (eq. final_eq, over the full A),
-    here by numpy's LAPACK solve (the paper calls a symmetric-indefinite
-    solver; the solution is the same).  Returns (cols, Z, the ID result of
-    A_S)."""
+    R_k is the leading k x k triangle of A_S's factor, and Z solves
+    R_k^T R_k Z = C^T A (eq. final_eq, over the full A): a forward
+    substitution with the lower triangle R_k^T, then a back substitution with
+    R_k (the paper hands R_k^T R_k to a symmetric-indefinite solver; the
+    solution is the same).  Returns (cols, Z, the ID result of A_S)."""
+    import scipy.linalg as sla
     A = np.asarray(A, dtype=np.float64)
     idx = np.asarray(idx, dtype=np.int64)
     AS = np.asfortranarray(A[:, idx])
@@ -213,31 +214,34 @@ def rid_sample(A: np.ndarray, idx: np.ndarray, k: int) -> tuple[np.ndarray, np.n
     cols = idx[res.J]
     Rk = res.R[:, res.J]          # R holds the rows in original order: R[:, J] = R11
     C = np.asfortranarray(A[:, cols])
-    Z = np.linalg.solve(matmul(Rk.T, Rk), matmul(C.T, A))
+    Y = sla.solve_triangular(Rk, matmul(C.T, A), trans="T", lower=False)   # R_k^T Y = C^T A
+    Z = sla.solve_triangular(Rk, Y, lower=False)                           # R_k Z = Y
     return cols.astype(np.int32), Z, res
 
 
-def two_sided(A: np.ndarray, k: int):
+def two_sided(A: np.ndarray, k: int, force_J: np.ndarray | None = None, force_I: np.ndarray | None = None):
     """Two-sided ID, A ~ W A[I, J] Z (the variant the paper credits to Cheng
     et al. in its footnote to the ID's definition, Section 1.2): the column ID
     of A (Section 2.1, a column ID whatever the shape) gives J and Z; the row
     ID of its skeleton C = A[:, J] -- the paper's dual ID (Section 2's
     footnote), i.e. the column ID of C^T -- gives I and W = Z_2^T (m x k,
-    W[I, :] = I_k).  Returns (I, J, W, Z, column-stage result, row-stage
-    result)."""
+    W[I, :] = I_k).  ``force_J`` / ``force_I`` fix the pivots of the two
+    stages (as ``force`` does for :func:`id`).  Returns (I, J, W, Z,
+    column-stage result, row-stage result)."""
     A = np.asarray(A, dtype=np.float64)
-    cres = _id_of(np.asfortranarray(A), False, k, None, None, None)
+    cres = _id_of(np.asfortranarray(A), False, k, None, None, force_J)
     C = A[:, cres.J]
-    rres = _id_of(np.asfortranarray(C.T), False, k, None, None, None)
+    rres = _id_of(np.asfortranarray(C.T), False, k, None, None, force_I)
     return rres.J.copy(), cres.J.copy(), np.asfortranarray(rres.Z.T), cres.Z, cres, rres
 
 
-def cur(A: np.ndarray, k: int):
+def cur(A: np.ndarray, k: int, force_J: np.ndarray | None = None, force_I: np.ndarray | None = None):
     """CUR form of the two-sided ID: C = A[:, J], R = A[I, :] and U = Z R^+
     (the k x k matrix with U R closest to Z in the Frobenius norm, so that
     C U R ~ C Z), from the normal equations (R R^T) U^T = R Z^T solved by
-    numpy's LAPACK solve.  Returns (I, J, U)."""
-    I, J, _, Z, _, _ = two_sided(A, k)
+    numpy's LAPACK solve.  ``force_J`` / ``force_I`` fix the two stages'
+    pivots.  Returns (I, J, U)."""
+    I, J, _, Z, _, _ = two_sided(A, k, force_J, force_I)
     R = np.asarray(A, dtype=np.float64)[I, :]
     Ut = np.linalg.solve(matmul(R, R.T), matmul(R, Z.T))
     return I, J, Ut.T

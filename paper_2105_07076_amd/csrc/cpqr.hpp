@@ -25,12 +25,8 @@ struct IdPlan {
     // columns per wave, fnpart workgroups
     bool fused;
     int fnp, fnpart, fgl;  // fgl: 16-byte row groups per lane (5, 9 or 16)
-    // resident path (few rows): rows per lane, grid, columns per workgroup
-    bool res_ok;
-    int res_rpl, res_grid, res_cpb;
     int kpad;  // kmax rounded up to the triangular solve's diagonal block
     size_t oS, oV, oF, ou, onu, onuref, oR, osel, opart, opartA, oR11, oDinv, ostate, orec, total;
-    size_t oPart2, oPartF, oSlots, oBar;
 };
 
 // Validates the shape/options and lays out the workspace (returns 0 or a

@@ -1275,292 +1275,28 @@ __global__ void k_finalize(const DevState* __restrict__ st, const ColPartial* __
 }
 
 // ---------------------------------------------------------------------------
-// Resident CPQR for a matrix with few rows (the sketch Y of the randomized
-// ID): one cooperative launch, every workgroup keeps its cpb columns in LDS
-// for the whole factorisation and applies each Householder step eagerly,
-// recomputing its columns' residual norms exactly (FP64 accumulation).  One
-// grid barrier per step: before it each workgroup publishes its best column
-// (norm, index, data); after it every workgroup reduces the same partials in
-// the same order, rebuilds the same reflector from the winning column and
-// updates its own columns.
-// ---------------------------------------------------------------------------
-constexpr int kResMaxCols = 128;
-constexpr size_t kResLdsBytes = 140 * 1024;
-constexpr unsigned kResSpinLimit = 1u << 24;
-
-// Grid-wide barrier for a cooperative launch.  The spin is bounded: after
-// kResSpinLimit polls (or once another workgroup gave up) it flags *err and
-// returns false, so every wave of the grid leaves the kernel in all cases.
-__device__ bool res_grid_sync(unsigned int* bar, unsigned int target, int* err) {
-    __shared__ int s_ok;
-    // the workgroup barrier makes every wave's stores reach the CU's L2; one
-    // wave then releases them device-wide, arrives, waits and acquires
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        atomicAdd(bar, 1u);
-        int ok = 1;
-        unsigned spins = 0;
-        // relaxed polling (an acquire load would invalidate the caches on
-        // every poll); the fence after the loop is the acquire
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                ok = 0;
-                break;
-            }
-            if (++spins > kResSpinLimit) {
-                atomicExch(err, 1);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
-        __threadfence();
-        s_ok = ok;
-    }
-    __syncthreads();
-    return s_ok != 0;
-}
-
-template <typename T, int RPL>
-__global__ void __launch_bounds__(kThreads) k_cpqr_resident(const T* __restrict__ S, int64_t ldw, int m, int64_t n,
-                                                            int kmax, int tol_mode, double eps, int cpb,
-                                                            T* __restrict__ R, int32_t* __restrict__ J,
-                                                            int32_t* __restrict__ sel, ColPartial* __restrict__ part2,
-                                                            ColPartial* __restrict__ part_final,
-                                                            int32_t* __restrict__ recomp, double* __restrict__ slots,
-                                                            DevState* __restrict__ st, unsigned int* __restrict__ bar,
-                                                            int* __restrict__ err) {
-    constexpr int LDL = kWave * RPL;
-    // the columns are held in FP64 (m rows each): eager updates at every step
-    // would otherwise round them to the working precision k times
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* W = reinterpret_cast<double*>(smem_raw);  // [cpb][m]
-    __shared__ double s_nu[kResMaxCols];
-    __shared__ double s_x[LDL];
-    __shared__ double w_best[4], w_sum[4];
-    __shared__ int32_t w_idx[4], w_nf[4];
-    const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
-    const int G = gridDim.x, wg = blockIdx.x;
-    const int64_t c0 = (int64_t)wg * cpb;
-    const int nc = (int)max((int64_t)0, min((int64_t)cpb, n - c0));
-
-    // stage this workgroup's columns and their exact norms
-    for (int c = wave; c < nc; c += 4) {
-        double s = 0.0;
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-            const int r = lane + kWave * t;
-            const double x = r < m ? (double)S[(c0 + c) * ldw + r] : 0.0;
-            if (r < m) W[c * m + r] = x;
-            s += x * x;
-        }
-        s = wave_sum(s);
-        if (lane == 0) s_nu[c] = sqrt(s);
-    }
-    __syncthreads();
-
-    double a_norm = 0.0;
-    for (int j = 0;; ++j) {
-        // local best column, sum of squared residual norms
-        ArgMax best{-1.0, INT32_MAX};
-        double ss = 0.0;
-        int nf = 0;
-        for (int c = tid; c < nc; c += kThreads) {
-            const double v = s_nu[c];
-            if (!is_finite_d(v)) nf = 1;
-            if (v >= 0.0) {
-                if (argmax_better(v, (int32_t)(c0 + c), best.v, best.i)) best = {v, (int32_t)(c0 + c)};
-                ss += v * v;
-            }
-        }
-        best = wave_argmax(best);
-        ss = wave_sum(ss);
-        nf = __any(nf) ? 1 : 0;
-        if (lane == 0) {
-            w_best[wave] = best.v;
-            w_idx[wave] = best.i;
-            w_sum[wave] = ss;
-            w_nf[wave] = nf;
-        }
-        __syncthreads();
-        best = ArgMax{w_best[0], w_idx[0]};
-        ss = w_sum[0];
-        nf = w_nf[0];
-        for (int w = 1; w < 4; ++w) {
-            if (argmax_better(w_best[w], w_idx[w], best.v, best.i)) best = {w_best[w], w_idx[w]};
-            ss += w_sum[w];
-            nf |= w_nf[w];
-        }
-        const int ph = j & 1;
-        if (tid == 0) part2[(int64_t)ph * G + wg] = ColPartial{best.v, best.i, nf, ss, 0.0};
-        if (best.i != INT32_MAX) {
-            double* sl = slots + ((int64_t)ph * G + wg) * LDL;
-            const int cl = (int)(best.i - c0);
-            for (int r = tid; r < m; r += kThreads) sl[r] = W[cl * m + r];
-        }
-        if (!res_grid_sync(bar, (unsigned)G * (unsigned)(j + 1), err)) return;
-
-        // the same global reduction in every workgroup
-        ArgMax gb{-1.0, INT32_MAX};
-        double gs = 0.0;
-        int gnf = 0;
-        for (int q = tid; q < G; q += kThreads) {
-            const ColPartial cp = part2[(int64_t)ph * G + q];
-            if (argmax_better(cp.best, cp.idx, gb.v, gb.i)) gb = {cp.best, cp.idx};
-            gs += cp.sumsq;
-            gnf |= cp.nonfinite;
-        }
-        gb = wave_argmax(gb);
-        gs = wave_sum(gs);
-        gnf = __any(gnf) ? 1 : 0;
-        __syncthreads();
-        if (lane == 0) {
-            w_best[wave] = gb.v;
-            w_idx[wave] = gb.i;
-            w_sum[wave] = gs;
-            w_nf[wave] = gnf;
-        }
-        __syncthreads();
-        gb = ArgMax{w_best[0], w_idx[0]};
-        gs = w_sum[0];
-        gnf = w_nf[0];
-        for (int w = 1; w < 4; ++w) {
-            if (argmax_better(w_best[w], w_idx[w], gb.v, gb.i)) gb = {w_best[w], w_idx[w]};
-            gs += w_sum[w];
-            gnf |= w_nf[w];
-        }
-        if (j == 0) a_norm = sqrt(gs);
-        uint32_t status = 0;
-        bool stop = false;
-        if (gnf) {
-            stop = true;
-            status = MIID_NONFINITE;
-        } else if (j >= kmax) {
-            stop = true;
-        } else if (!(gb.v > 0.0) || gb.i == INT32_MAX) {
-            stop = true;
-            status = MIID_RANK_DEFICIENT;
-        } else if (tol_mode && sqrt(gs) <= eps * a_norm) {
-            stop = true;
-        }
-        // pivot column from its owner's slot
-        const int64_t p = gb.i;
-        if (!stop) {
-            const double* ps = slots + ((int64_t)ph * G + p / cpb) * LDL;
-            for (int r = tid; r < LDL; r += kThreads) s_x[r] = (r >= j && r < m) ? ps[r] : 0.0;
-        }
-        __syncthreads();
-        double alpha = 0.0;
-        if (!stop) {
-            double xs = 0.0;
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) {
-                const int r = lane + kWave * t;
-                if (r > j) xs += s_x[r] * s_x[r];
-            }
-            xs = wave_sum(xs);
-            const double x0 = s_x[j];
-            alpha = sqrt(x0 * x0 + xs);
-            if (!(alpha > 0.0)) {
-                stop = true;
-                status = MIID_RANK_DEFICIENT;
-            }
-        }
-        if (stop) {
-            if (tid == 0) {
-                part_final[wg] = ColPartial{best.v, best.i, nf, ss, 0.0};
-                recomp[wg] = 0;
-                if (wg == 0) {
-                    st->a_norm = a_norm;
-                    if (j < kmax) {
-                        st->k_out = j;
-                        st->status |= status;
-                        st->stop = 1;
-                    }
-                }
-            }
-            return;
-        }
-        const double x0 = s_x[j];
-        const double beta = x0 >= 0.0 ? -alpha : alpha;
-        const double tau = (beta - x0) / beta;
-        const double scale = 1.0 / (x0 - beta);
-        __syncthreads();
-        for (int r = tid; r < LDL; r += kThreads) s_x[r] = r < j ? 0.0 : (r == j ? 1.0 : s_x[r] * scale);
-        if (wg == 0 && tid == 0) {
-            J[j] = (int32_t)p;
-            sel[p] = j;
-            R[(int64_t)j * n + p] = (T)beta;
-        }
-        if (tid == 0 && p / cpb == wg) s_nu[p - c0] = -1.0;
-        __syncthreads();
-        // apply H = I - tau v v^T to the alive columns, exact new norms
-        for (int c = wave; c < nc; c += 4) {
-            if (s_nu[c] < 0.0) continue;
-            double* wc = W + c * m;
-            double xv[RPL];
-            double d = 0.0;
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) {
-                const int r = lane + kWave * t;
-                xv[t] = (r >= j && r < m) ? wc[r] : 0.0;
-                d += xv[t] * s_x[r];
-            }
-            d = tau * wave_sum(d);
-            double s2 = 0.0;
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) {
-                const int r = lane + kWave * t;
-                if (r >= j && r < m) {
-                    const double y = xv[t] - d * s_x[r];
-                    wc[r] = y;
-                    if (r == j) R[(int64_t)j * n + c0 + c] = (T)y;
-                    if (r > j) s2 += y * y;
-                }
-            }
-            s2 = wave_sum(s2);
-            if (lane == 0) s_nu[c] = sqrt(s2);
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 
-// Columns per wave of the F-GEMV (1, 2 or 4): the CPW hint, else
-// MIID_GEMV_CPW, else one in FP64 and two in FP32 (timed fastest for
-// 4096-row matrices).
+// Columns per wave of the F-GEMV (1, 2 or 4): the CPW hint, else one in FP64
+// and two in FP32 (timed fastest for 4096-row matrices).
 static int gemv_cols_per_wave(uint32_t flags, size_t esz) {
     const int h = (int)((flags >> MIID_HINT_CPW_SHIFT) & 15u);
     if (h == 1 || h == 2 || h == 4) return h;
-    const char* e = std::getenv("MIID_GEMV_CPW");
-    const int v = e ? std::atoi(e) : (esz == 4 ? 2 : 1);
-    return (v == 2 || v == 4) ? v : 1;
+    return esz == 4 ? 2 : 1;
 }
 
 // The fused path is taken where eligible unless the PATH hint asks for the
-// blocked one (or, without a hint, MIID_FUSED=0); the NP hint, else
-// MIID_FUSED_NP, else one workgroup per CU sets the column passes per wave.
+// blocked one; the NP hint, else one workgroup per CU, sets the column passes
+// per wave.
 static bool fused_enabled(uint32_t flags) {
     const int h = (int)((flags >> MIID_HINT_PATH_SHIFT) & 15u);
-    if (h == 1) return false;
-    if (h == 2) return true;
-    const char* e = std::getenv("MIID_FUSED");
-    return !(e && e[0] == '0');
+    return h != 1;
 }
 
 static int fused_np(int64_t n, uint32_t flags) {
     const int h = (int)((flags >> MIID_HINT_NP_SHIFT) & 15u);
     if (h == 1 || h == 2 || h == 4) return h;
-    const char* e = std::getenv("MIID_FUSED_NP");
-    if (e) {
-        const int v = std::atoi(e);
-        if (v == 1 || v == 2 || v == 4) return v;
-    }
     for (int v = 1; v <= 4; v *= 2)
         if (n <= (int64_t)256 * 32 * v) return v;  // one workgroup per CU
     return 4;
@@ -1624,79 +1360,8 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
     P->oDinv = take((size_t)P->kpad * kTB * 8);
     P->ostate = take(sizeof(DevState));
     P->orec = take((size_t)std::max(P->npart, 8 * P->fnpart) * 4);
-    // resident path: every workgroup holds ceil(n / grid) columns in LDS
-    P->res_ok = false;
-    P->res_rpl = P->m <= 320 ? 5 : (P->m <= 576 ? 9 : (P->m <= 1024 ? 16 : 0));
-    P->res_grid = 256;
-    {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            P->res_grid = prop.multiProcessorCount;
-    }
-    P->res_cpb = (int)((P->n + P->res_grid - 1) / P->res_grid);
-    if (P->res_rpl > 0 && P->res_cpb <= kResMaxCols && (size_t)P->res_cpb * P->m * 8 <= kResLdsBytes &&
-        P->npart >= P->res_grid) {
-        P->res_ok = true;
-        P->oPart2 = take((size_t)2 * P->res_grid * sizeof(ColPartial));
-        P->oPartF = take((size_t)P->res_grid * sizeof(ColPartial));
-        P->oSlots = take((size_t)2 * P->res_grid * kWave * P->res_rpl * 8);
-        P->oBar = take(256);
-    }
     P->total = off;
     return 0;
-}
-
-// The resident path is used when MIID_RESIDENT=1 (off by default: on
-// MI355X its per-step grid barrier costs more than the two launches of the
-// blocked path).
-static bool resident_enabled() {
-    const char* e = std::getenv("MIID_RESIDENT");
-    return e && e[0] == '1';
-}
-
-template <typename T, int RPL>
-static hipError_t launch_resident_rpl(const IdPlan& P, T* S, T* R, int32_t* J, int32_t* sel, unsigned char* ws,
-                                      DevState* st, hipStream_t stream) {
-    const void* f = (const void*)k_cpqr_resident<T, RPL>;
-    const size_t shmem = (size_t)P.res_cpb * P.m * 8;
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kResLdsBytes);
-    if (e != hipSuccess) return e;
-    int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, shmem);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) return hipErrorCooperativeLaunchTooLarge;
-    int64_t ldw = P.ldw, n = P.n;
-    int m = (int)P.m, kmax = P.kmax, tol_mode = (int)P.tol, cpb = P.res_cpb;
-    double eps = P.eps;
-    ColPartial* part2 = reinterpret_cast<ColPartial*>(ws + P.oPart2);
-    ColPartial* partF = reinterpret_cast<ColPartial*>(ws + P.oPartF);
-    int32_t* recomp = reinterpret_cast<int32_t*>(ws + P.orec);
-    double* slots = reinterpret_cast<double*>(ws + P.oSlots);
-    unsigned int* bar = reinterpret_cast<unsigned int*>(ws + P.oBar);
-    int* err = reinterpret_cast<int*>(ws + P.oBar + 64);
-    const T* Sc = S;
-    hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(256), 0, stream, ws + P.oBar, (int64_t)256,
-                       (unsigned char)0);
-    hipLaunchKernelGGL(k_fill<int32_t>, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0,
-                       stream, sel, n, (int32_t)-1);
-    void* args[] = {(void*)&Sc,    (void*)&ldw,   (void*)&m,      (void*)&n,      (void*)&kmax, (void*)&tol_mode,
-                    (void*)&eps,   (void*)&cpb,   (void*)&R,      (void*)&J,      (void*)&sel,  (void*)&part2,
-                    (void*)&partF, (void*)&recomp, (void*)&slots, (void*)&st,     (void*)&bar,  (void*)&err};
-    return hipLaunchCooperativeKernel(f, dim3(P.res_grid), dim3(kThreads), args, (unsigned)shmem, stream);
-}
-
-template <typename T>
-static hipError_t launch_resident(const IdPlan& P, T* S, T* R, int32_t* J, int32_t* sel, unsigned char* ws,
-                                  DevState* st, hipStream_t stream) {
-    switch (P.res_rpl) {
-        case 5:
-            return launch_resident_rpl<T, 5>(P, S, R, J, sel, ws, st, stream);
-        case 9:
-            return launch_resident_rpl<T, 9>(P, S, R, J, sel, ws, st, stream);
-        default:
-            return launch_resident_rpl<T, 16>(P, S, R, J, sel, ws, st, stream);
-    }
 }
 
 template <typename T, int NP, int GL>
@@ -1819,18 +1484,7 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
     ColPartial* fin_part = part;
     int fin_npart = P.npart;
     int fin_alt = 0;
-    bool resident_done = false;
-    if (staged && P.res_ok && resident_enabled()) {
-        hipError_t e = launch_resident<T>(P, S, R, J, sel, ws, st, stream);
-        if (e == hipSuccess) {
-            resident_done = true;
-            fin_part = reinterpret_cast<ColPartial*>(ws + P.oPartF);
-            fin_npart = P.res_grid;
-        } else {
-            (void)hipGetLastError();  // not co-resident: take the blocked path
-        }
-    }
-    if (!resident_done && P.fused) {
+    if (P.fused) {
     // the norm pass writes 8 fnpart partials (four-wave workgroups of NP
     // columns per wave) into buffer 0; the steps write fnpart
     fin_npart = P.fnpart;
@@ -1866,7 +1520,7 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
             }
         }
     }
-    } else if (!resident_done) {
+    } else {
     launch_norms(P.npart, P.cpw);
     for (int j = 0; j < P.kmax; ++j) {
         const int jb = (j / nb) * nb;
