@@ -19,7 +19,8 @@
  *    synchronises the stream a few times to stop early.
  *  - The return value only reports problems the host can see at call time:
  *      0                 success (launches enqueued)
- *      -i                argument i (1-based) is invalid (LAPACK convention)
+ *      -i                argument i (1-based; the handle is argument 1) is
+ *                        invalid (LAPACK convention)
  *      MIID_E_WORKSPACE  ws_bytes is smaller than the workspace query
  *      MIID_E_HIP        a HIP call failed (miid_last_hip_error() tells which)
  *      MIID_E_UNSUPPORTED shape or option outside the documented limits
@@ -128,6 +129,45 @@ const char *miid_version(void);
 int miid_last_hip_error(void);
 
 /* ------------------------------------------------------------------------
+ * Library handle, the first argument of every entry point below.
+ *
+ * A handle belongs to the device that is current when miid_create runs and
+ * holds a read-only table of tuned launch shapes.  Passing it while another
+ * device is current returns -1 (argument 1 invalid).  NULL is accepted
+ * everywhere and means "no table".  The facts the library keeps per device
+ * -- its compute-unit count, the kernels whose LDS limit has been raised --
+ * are queried once per device whether or not a handle is used.  A handle
+ * created with no visible device serves the workspace queries only.  The
+ * paper's problem statement (Section 2) fixes the arguments, A, k (or a
+ * tolerance), J and Z; the handle only changes launch shapes, never what is
+ * computed.
+ *
+ *  out            receives the handle (release it with miid_destroy)
+ *  autotune_path  nullable: a text file with one row per line ('#' starts a
+ *                 comment line):
+ *                     routine dtype m n k nb hints
+ *                 routine  id | rid | rid_sample | two_sided | cur | batched
+ *                 dtype    f32 | f64 (rid: f32)
+ *                 m n k    the call's m, n and opts.k (batched: nblk, 0 and
+ *                          opts.kmax); 0 matches any value
+ *                 nb       panel width (0 = the library's)
+ *                 hints    MIID_HINT fields, decimal or 0x hex
+ *                 A call whose opts leave nb = 0 and every hint field 0
+ *                 runs with the most specific matching row; the workspace
+ *                 queries apply the same rule.
+ * Returns 0; -1 if out is NULL; -2 if the file cannot be read or a row is
+ * malformed (no handle is created); MIID_E_UNSUPPORTED if host memory for
+ * the handle cannot be allocated.
+ * ---------------------------------------------------------------------- */
+typedef struct miid_handle_s *miid_handle;
+int miid_create(miid_handle *out, const char *autotune_path);
+void miid_destroy(miid_handle h);
+/* device ordinal the handle belongs to (-1: none visible at creation) */
+int miid_handle_device(miid_handle h);
+/* number of rows in the handle's tuning table */
+int miid_handle_rows(miid_handle h);
+
+/* ------------------------------------------------------------------------
  * Deterministic ID (Section 2.1; truncated QR of Section 4.1).
  *
  * Column-pivoted Householder QR A P = Q R with Businger-Golub pivoting on the
@@ -139,21 +179,21 @@ int miid_last_hip_error(void);
  * indexes rows of A, Z is k x m and A ~ Z^T A[J, :]; status gets
  * MIID_TRANSPOSED.
  *
- *  A     (1)  m x n, leading dimension lda >= m, read only
- *  J     (7)  kmax int32 (kmax = opts.k when k > 0): selected indices in
+ *  A     (2)  m x n, leading dimension lda >= m, read only
+ *  J     (8)  kmax int32 (kmax = opts.k when k > 0): selected indices in
  *             pivot order; entries >= k_out are -1
- *  Z     (8)  kmax x N (N = max(m, n)), ldz >= kmax, dtype: Z[:, J[c]] is
+ *  Z     (9)  kmax x N (N = max(m, n)), ldz >= kmax, dtype: Z[:, J[c]] is
  *             exactly the c-th unit vector, the other columns hold T, rows
  *             >= k_out are zero; columns in ORIGINAL order
- *  R11   (10) nullable, kmax x kmax FP64, ldr >= kmax: the triangular factor
+ *  R11   (11) nullable, kmax x kmax FP64, ldr >= kmax: the triangular factor
  *             in pivot order (upper triangle; needed by id_backward)
- *  C     (12) nullable, M x kmax (M = min(m, n)), ldc >= M, dtype: A[:, J]
+ *  C     (13) nullable, M x kmax (M = min(m, n)), ldc >= M, dtype: A[:, J]
  *             (or A[J, :]^T when transposed); columns >= k_out unspecified
- *  info  (14) device pointer to one miid_info
+ *  info  (15) device pointer to one miid_info
  * Limits: 1 <= kmax <= min(m, n, 1024); nb in [1, 64].
  * ---------------------------------------------------------------------- */
-size_t miid_id_workspace(int64_t m, int64_t n, miid_dtype dtype, const miid_opts *opts);
-int id_cpqr(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
+size_t miid_id_workspace(miid_handle h, int64_t m, int64_t n, miid_dtype dtype, const miid_opts *opts);
+int id_cpqr(miid_handle h, const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
             const miid_opts *opts, int32_t *J, void *Z, int64_t ldz,
             double *R11, int64_t ldr, void *C, int64_t ldc, miid_info *info,
             void *ws, size_t ws_bytes, void *stream);
@@ -165,13 +205,13 @@ int id_cpqr(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
  * with FP32 accumulation.  The CPQR of Y (FP32, FP64 norms, FP64 triangular
  * solve) gives J and T; C = A[:, J].
  *
- *  A      (1)  m x n FP32, lda >= m, m <= n (else MIID_E_UNSUPPORTED)
- *  Omega  (5)  l x m bfloat16 bit patterns, column-major, ldo >= l
- *  mode   (8)  0: A rounded once to bfloat16 (one matrix-core pass);
+ *  A      (2)  m x n FP32, lda >= m, m <= n (else MIID_E_UNSUPPORTED)
+ *  Omega  (6)  l x m bfloat16 bit patterns, column-major, ldo >= l
+ *  mode   (9)  0: A rounded once to bfloat16 (one matrix-core pass);
  *              1: A split as hi + lo, both bfloat16 (two passes, error
  *                 ~ 2^-16 relative in Y)
  *  J, Z, C, R11, info: as in id_cpqr with dtype FP32; Z is kmax x n
- *  Y      (15) nullable, l x n FP32, ldy >= l: the sketch
+ *  Y      (16) nullable, l x n FP32, ldy >= l: the sketch
  * With MIID_LSTSQ_Z in opts.flags (fixed rank, k <= m) Z is instead the
  * least-squares coefficient matrix over the full A, Z = C^+ A, the paper's
  * way of forming the randomized ID's Z (Section 2.2, eq. final_eq), for the
@@ -181,8 +221,8 @@ int id_cpqr(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
  * describes the CPQR of Y, plus MIID_LSTSQ_BREAKDOWN.
  * Limits: k <= l <= min(n, 1024) (kmax <= l in tolerance mode), m <= n.
  * ---------------------------------------------------------------------- */
-size_t miid_rid_workspace(int64_t m, int64_t n, int32_t l, const miid_opts *opts);
-int rid_sketch_cpqr(const float *A, int64_t m, int64_t n, int64_t lda,
+size_t miid_rid_workspace(miid_handle h, int64_t m, int64_t n, int32_t l, const miid_opts *opts);
+int rid_sketch_cpqr(miid_handle h, const float *A, int64_t m, int64_t n, int64_t lda,
                     const uint16_t *Omega, int32_t l, int64_t ldo, int32_t mode,
                     const miid_opts *opts, int32_t *J, float *Z, int64_t ldz,
                     float *C, int64_t ldc, float *Y, int64_t ldy,
@@ -200,24 +240,24 @@ int rid_sketch_cpqr(const float *A, int64_t m, int64_t n, int64_t lda,
  * (C^T A) in FP64 (C^T A on the matrix cores in the working precision).
  * Z[:, J[c]] is set to the c-th unit vector exactly (Definition 1).
  *
- *  A     (1)  m x n, lda >= m, dtype, read only
- *  idx   (6)  device int32[p]: the sampled column indices (distinct, in
+ *  A     (2)  m x n, lda >= m, dtype, read only
+ *  idx   (7)  device int32[p]: the sampled column indices (distinct, in
  *             [0, n); an index outside gives a zero column of A_S)
- *  p     (7)  1 <= p <= n
- *  opts  (8)  fixed rank only: k >= 1, k <= min(m, p, 1024); nb, flags as
+ *  p     (8)  1 <= p <= n
+ *  opts  (9)  fixed rank only: k >= 1, k <= min(m, p, 1024); nb, flags as
  *             for id_cpqr (MIID_KEEP_COLUMNS is implied, MIID_NO_REFINE has
  *             no effect on the least-squares solve)
- *  J     (9)  k int32; entries >= k_out are -1
- *  Z     (10) k x n, ldz >= k, dtype, columns in original order; rows
+ *  J     (10) k int32; entries >= k_out are -1
+ *  Z     (11) k x n, ldz >= k, dtype, columns in original order; rows
  *             >= k_out zero
- *  R11   (12) nullable: R_k, k x k FP64, ldr >= k
- *  C     (14) nullable: m x k, ldc >= m, dtype: A[:, J]
- *  info  (16) device miid_info of the CPQR of A_S (a_norm, r22_norm refer to
+ *  R11   (13) nullable: R_k, k x k FP64, ldr >= k
+ *  C     (15) nullable: m x k, ldc >= m, dtype: A[:, J]
+ *  info  (17) device miid_info of the CPQR of A_S (a_norm, r22_norm refer to
  *             A_S)
  * ---------------------------------------------------------------------- */
-size_t miid_rid_sample_workspace(int64_t m, int64_t n, int32_t p, miid_dtype dtype,
+size_t miid_rid_sample_workspace(miid_handle h, int64_t m, int64_t n, int32_t p, miid_dtype dtype,
                                  const miid_opts *opts);
-int rid_sample_cpqr(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
+int rid_sample_cpqr(miid_handle h, const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
                     const int32_t *idx, int32_t p, const miid_opts *opts,
                     int32_t *J, void *Z, int64_t ldz, double *R11, int64_t ldr,
                     void *C, int64_t ldc, miid_info *info,
@@ -231,19 +271,19 @@ int rid_sample_cpqr(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype
  * the dual ID of Section 2's footnote, the column ID of C^T -- gives I and
  * W.  Both stages are the blocked CPQR + triangular solve of id_cpqr.
  *
- *  A          (1)  m x n, lda >= m, dtype, read only
- *  opts       (6)  fixed rank only: 1 <= k <= min(m, n, 1024); nb, flags as
+ *  A          (2)  m x n, lda >= m, dtype, read only
+ *  opts       (7)  fixed rank only: 1 <= k <= min(m, n, 1024); nb, flags as
  *                  for id_cpqr (else MIID_E_UNSUPPORTED)
- *  J          (7)  k int32: skeleton columns; entries >= k_out are -1
- *  Z          (8)  k x n, ldz >= k, dtype: Z[:, J[c]] = e_c
- *  I          (10) k int32: skeleton rows (of the skeleton C, i.e. of A);
+ *  J          (8)  k int32: skeleton columns; entries >= k_out are -1
+ *  Z          (9)  k x n, ldz >= k, dtype: Z[:, J[c]] = e_c
+ *  I          (11) k int32: skeleton rows (of the skeleton C, i.e. of A);
  *                  entries >= the row stage's k_out are -1
- *  W          (11) m x k, ldw >= m, dtype: W[I[c], :] = e_c^T
- *  info       (13) device miid_info of the column stage (norms refer to A)
- *  info_rows  (14) device miid_info of the row stage (norms refer to C)
+ *  W          (12) m x k, ldw >= m, dtype: W[I[c], :] = e_c^T
+ *  info       (14) device miid_info of the column stage (norms refer to A)
+ *  info_rows  (15) device miid_info of the row stage (norms refer to C)
  * ---------------------------------------------------------------------- */
-size_t miid_two_sided_workspace(int64_t m, int64_t n, miid_dtype dtype, const miid_opts *opts);
-int id_two_sided(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
+size_t miid_two_sided_workspace(miid_handle h, int64_t m, int64_t n, miid_dtype dtype, const miid_opts *opts);
+int id_two_sided(miid_handle h, const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
                  const miid_opts *opts, int32_t *J, void *Z, int64_t ldz,
                  int32_t *I, void *W, int64_t ldw, miid_info *info, miid_info *info_rows,
                  void *ws, size_t ws_bytes, void *stream);
@@ -255,13 +295,13 @@ int id_two_sided(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dt
  * of rid_sketch_cpqr (FP64 Gram of R, Cholesky, two-sided solve).  Not in
  * the paper; it completes the two-sided form.
  *
- *  A, opts, J, I: as for id_two_sided; U (9) k x k, ldu >= k, dtype
+ *  A, opts, J, I: as for id_two_sided; U (10) k x k, ldu >= k, dtype
  *  info, info_rows: as for id_two_sided; info_rows also gets
  *                   MIID_LSTSQ_BREAKDOWN if R R^T is not positive definite in
  *                   FP64
  * ---------------------------------------------------------------------- */
-size_t miid_cur_workspace(int64_t m, int64_t n, miid_dtype dtype, const miid_opts *opts);
-int id_cur(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
+size_t miid_cur_workspace(miid_handle h, int64_t m, int64_t n, miid_dtype dtype, const miid_opts *opts);
+int id_cur(miid_handle h, const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
            const miid_opts *opts, int32_t *J, int32_t *I, void *U, int64_t ldu,
            miid_info *info, miid_info *info_rows, void *ws, size_t ws_bytes, void *stream);
 
@@ -273,22 +313,22 @@ int id_cur(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
  * ||R22||_F <= eps ||A_b||_F (exact residual norms), at most
  * kmax_b = min(m[b], n[b], kmax).
  *
- *  A      (2)  packed blocks, dtype
- *  a_off, m, n (3-5) device int64 / int32 / int32 arrays of length nblk
- *  opts   (7)  host: eps, kmax and flags (MIID_HINT(MIID_HINT_LPC_SHIFT, l));
+ *  A      (3)  packed blocks, dtype
+ *  a_off, m, n (4-6) device int64 / int32 / int32 arrays of length nblk
+ *  opts   (8)  host: eps, kmax and flags (MIID_HINT(MIID_HINT_LPC_SHIFT, l));
  *              k and nb are ignored
- *  J      (8)  packed int32: block b owns kmax_b entries at j_off[b]
- *  Z      (10) packed dtype: block b owns a kmax_b x n[b] column-major
+ *  J      (9)  packed int32: block b owns kmax_b entries at j_off[b]
+ *  Z      (11) packed dtype: block b owns a kmax_b x n[b] column-major
  *              matrix (leading dimension kmax_b) at z_off[b]; rows >= k_out
  *              are zero
- *  info   (12) nblk miid_info entries
+ *  info   (13) nblk miid_info entries
  * Limits: 1 <= m[b] <= 256, m[b] <= n[b] <= 1024, 1 <= kmax <= 64.  A block
  * outside them is skipped with k_out = 0 and status MIID_BLOCK_UNSUPPORTED;
  * the others are unaffected (likewise a block holding a NaN only gets its
  * own MIID_NONFINITE).  Blocks are processed largest first (by m n).
  * ---------------------------------------------------------------------- */
-size_t miid_batched_workspace(int32_t nblk, miid_dtype dtype);
-int id_batched(int32_t nblk, const void *A, const int64_t *a_off, const int32_t *m,
+size_t miid_batched_workspace(miid_handle h, int32_t nblk, miid_dtype dtype);
+int id_batched(miid_handle h, int32_t nblk, const void *A, const int64_t *a_off, const int32_t *m,
                const int32_t *n, miid_dtype dtype, const miid_opts *opts,
                int32_t *J, const int64_t *j_off, void *Z, const int64_t *z_off,
                miid_info *info, void *ws, size_t ws_bytes, void *stream);
@@ -301,15 +341,15 @@ int id_batched(int32_t nblk, const void *A, const int64_t *a_off, const int32_t 
  *     gA          = C M
  *     gA[:, J]   += gC + A M^T - C (Z M^T + M Z^T)
  *
- *  A   (1)   m x n, lda, dtype (the forward input; m <= n)
- *  J   (6)   k int32, R11 (8): k x k FP64 from id_cpqr, ldr
- *  Z   (10)  k x n, ldz, dtype, from id_cpqr
- *  gC  (12)  nullable m x k, ldgc;  gZ (14) nullable k x n, ldgz
- *  gA  (16)  m x n, ldga, written (not accumulated)
+ *  A   (2)   m x n, lda, dtype (the forward input; m <= n)
+ *  J   (7)   k int32, R11 (9): k x k FP64 from id_cpqr, ldr
+ *  Z   (11)  k x n, ldz, dtype, from id_cpqr
+ *  gC  (13)  nullable m x k, ldgc;  gZ (15) nullable k x n, ldgz
+ *  gA  (17)  m x n, ldga, written (not accumulated)
  * Limits: 1 <= k <= min(m, n, 1024).
  * ---------------------------------------------------------------------- */
-size_t miid_backward_workspace(int64_t m, int64_t n, int32_t k, miid_dtype dtype);
-int id_backward(const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
+size_t miid_backward_workspace(miid_handle h, int64_t m, int64_t n, int32_t k, miid_dtype dtype);
+int id_backward(miid_handle h, const void *A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
                 const int32_t *J, int32_t k, const double *R11, int64_t ldr,
                 const void *Z, int64_t ldz, const void *gC, int64_t ldgc,
                 const void *gZ, int64_t ldgz, void *gA, int64_t ldga,

@@ -10,7 +10,8 @@ memory and the stream).
 """
 from ._abi import MiidError, load  # noqa: F401
 from .api import (IDResult, BatchedResult, TwoSidedResult, id, rid, rid_sample, two_sided, cur,  # noqa: F401
-                  batched, id_backward, IDFunction)
+                  batched, id_backward, IDFunction, handle, set_tuning_table)
 from . import autotune  # noqa: F401
 
-__all__ = ["IDResult", "id", "rid", "batched", "id_backward", "IDFunction", "MiidError", "load", "autotune"]
+__all__ = ["IDResult", "id", "rid", "batched", "id_backward", "IDFunction", "MiidError", "load", "autotune",
+           "handle", "set_tuning_table"]

@@ -30,6 +30,7 @@ MIID_LSTSQ_Z = 4
 # every symbol declared in include/miid.h
 EXPORTED = [
     "miid_version", "miid_last_hip_error",
+    "miid_create", "miid_destroy", "miid_handle_device", "miid_handle_rows",
     "miid_id_workspace", "id_cpqr",
     "miid_rid_workspace", "rid_sketch_cpqr",
     "miid_rid_sample_workspace", "rid_sample_cpqr",
@@ -84,42 +85,81 @@ def load(path: str = LIB_PATH):
     lib.miid_version.argtypes = []
     lib.miid_last_hip_error.restype = ctypes.c_int
     lib.miid_last_hip_error.argtypes = []
+    H = ctypes.c_void_p  # miid_handle, the first argument of every entry point
+    lib.miid_create.restype = ctypes.c_int
+    lib.miid_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_char_p]
+    lib.miid_destroy.restype = None
+    lib.miid_destroy.argtypes = [H]
+    lib.miid_handle_device.restype = ctypes.c_int
+    lib.miid_handle_device.argtypes = [H]
+    lib.miid_handle_rows.restype = ctypes.c_int
+    lib.miid_handle_rows.argtypes = [H]
     lib.miid_id_workspace.restype = SZ
-    lib.miid_id_workspace.argtypes = [I64, I64, ctypes.c_int, OPTS]
+    lib.miid_id_workspace.argtypes = [H, I64, I64, ctypes.c_int, OPTS]
     lib.id_cpqr.restype = ctypes.c_int
-    lib.id_cpqr.argtypes = [P, I64, I64, I64, ctypes.c_int, OPTS, P, P, I64, P, I64, P, I64, P, P, SZ, P]
+    lib.id_cpqr.argtypes = [H, P, I64, I64, I64, ctypes.c_int, OPTS, P, P, I64, P, I64, P, I64, P, P, SZ, P]
     lib.miid_rid_sample_workspace.restype = SZ
-    lib.miid_rid_sample_workspace.argtypes = [I64, I64, I32, ctypes.c_int, OPTS]
+    lib.miid_rid_sample_workspace.argtypes = [H, I64, I64, I32, ctypes.c_int, OPTS]
     lib.rid_sample_cpqr.restype = ctypes.c_int
-    lib.rid_sample_cpqr.argtypes = [P, I64, I64, I64, ctypes.c_int, P, I32, OPTS, P, P, I64, P, I64, P, I64, P, P,
-                                    SZ, P]
+    lib.rid_sample_cpqr.argtypes = [H, P, I64, I64, I64, ctypes.c_int, P, I32, OPTS, P, P, I64, P, I64, P, I64, P,
+                                    P, SZ, P]
     lib.miid_two_sided_workspace.restype = SZ
-    lib.miid_two_sided_workspace.argtypes = [I64, I64, ctypes.c_int, OPTS]
+    lib.miid_two_sided_workspace.argtypes = [H, I64, I64, ctypes.c_int, OPTS]
     lib.id_two_sided.restype = ctypes.c_int
-    lib.id_two_sided.argtypes = [P, I64, I64, I64, ctypes.c_int, OPTS, P, P, I64, P, P, I64, P, P, P, SZ, P]
+    lib.id_two_sided.argtypes = [H, P, I64, I64, I64, ctypes.c_int, OPTS, P, P, I64, P, P, I64, P, P, P, SZ, P]
     lib.miid_cur_workspace.restype = SZ
-    lib.miid_cur_workspace.argtypes = [I64, I64, ctypes.c_int, OPTS]
+    lib.miid_cur_workspace.argtypes = [H, I64, I64, ctypes.c_int, OPTS]
     lib.id_cur.restype = ctypes.c_int
-    lib.id_cur.argtypes = [P, I64, I64, I64, ctypes.c_int, OPTS, P, P, P, I64, P, P, P, SZ, P]
-    if hasattr(lib, "rid_sketch_cpqr"):
-        lib.miid_rid_workspace.restype = SZ
-        lib.miid_rid_workspace.argtypes = [I64, I64, I32, OPTS]
-        lib.rid_sketch_cpqr.restype = ctypes.c_int
-        lib.rid_sketch_cpqr.argtypes = [P, I64, I64, I64, P, I32, I64, I32, OPTS, P, P, I64, P, I64, P, I64,
-                                        P, I64, P, P, SZ, P]
-    if hasattr(lib, "id_batched"):
-        lib.miid_batched_workspace.restype = SZ
-        lib.miid_batched_workspace.argtypes = [I32, ctypes.c_int]
-        lib.id_batched.restype = ctypes.c_int
-        lib.id_batched.argtypes = [I32, P, P, P, P, ctypes.c_int, ctypes.POINTER(MiidOpts), P, P, P, P, P, P, SZ, P]
-    if hasattr(lib, "id_backward"):
-        lib.miid_backward_workspace.restype = SZ
-        lib.miid_backward_workspace.argtypes = [I64, I64, I32, ctypes.c_int]
-        lib.id_backward.restype = ctypes.c_int
-        lib.id_backward.argtypes = [P, I64, I64, I64, ctypes.c_int, P, I32, P, I64, P, I64, P, I64, P, I64,
-                                    P, I64, P, SZ, P]
+    lib.id_cur.argtypes = [H, P, I64, I64, I64, ctypes.c_int, OPTS, P, P, P, I64, P, P, P, SZ, P]
+    lib.miid_rid_workspace.restype = SZ
+    lib.miid_rid_workspace.argtypes = [H, I64, I64, I32, OPTS]
+    lib.rid_sketch_cpqr.restype = ctypes.c_int
+    lib.rid_sketch_cpqr.argtypes = [H, P, I64, I64, I64, P, I32, I64, I32, OPTS, P, P, I64, P, I64, P, I64,
+                                    P, I64, P, P, SZ, P]
+    lib.miid_batched_workspace.restype = SZ
+    lib.miid_batched_workspace.argtypes = [H, I32, ctypes.c_int]
+    lib.id_batched.restype = ctypes.c_int
+    lib.id_batched.argtypes = [H, I32, P, P, P, P, ctypes.c_int, OPTS, P, P, P, P, P, P, SZ, P]
+    lib.miid_backward_workspace.restype = SZ
+    lib.miid_backward_workspace.argtypes = [H, I64, I64, I32, ctypes.c_int]
+    lib.id_backward.restype = ctypes.c_int
+    lib.id_backward.argtypes = [H, P, I64, I64, I64, ctypes.c_int, P, I32, P, I64, P, I64, P, I64, P, I64,
+                                P, I64, P, SZ, P]
     _lib = lib
     return lib
+
+
+class Handle:
+    """A miid_handle: the device current at creation and, optionally, a
+    tuning table (text rows "routine dtype m n k nb hints")."""
+
+    def __init__(self, autotune_path: str | None = None):
+        lib = load()
+        h = ctypes.c_void_p()
+        rc = lib.miid_create(ctypes.byref(h), autotune_path.encode() if autotune_path else None)
+        if rc != 0:
+            raise MiidError(f"miid_create: rc={rc}" + (f" (cannot read {autotune_path})" if rc == -2 else ""))
+        self.ptr = h.value
+        self.path = autotune_path
+
+    @property
+    def device(self) -> int:
+        return load().miid_handle_device(self.ptr)
+
+    @property
+    def rows(self) -> int:
+        return load().miid_handle_rows(self.ptr)
+
+    def close(self) -> None:
+        if self.ptr:
+            load().miid_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def check(rc: int, what: str) -> None:

@@ -78,6 +78,36 @@ class Workspace:
 
 _WS = Workspace()
 
+# one miid_handle per device, all created with the same tuning table
+_HANDLES: dict = {}
+_TABLE_PATH: str | None = None
+
+
+def set_tuning_table(path: str | None) -> None:
+    """Run later calls with the native tuning table at ``path`` (rows
+    "routine dtype m n k nb hints", as written by autotune.Table.export_native);
+    None drops it.  Calls that pass nb or hints themselves are unaffected."""
+    global _TABLE_PATH
+    for h in _HANDLES.values():
+        h.close()
+    _HANDLES.clear()
+    _TABLE_PATH = path
+
+
+def handle(device: int | None = None) -> _abi.Handle:
+    """The miid_handle of ``device`` (default: the current device)."""
+    dev = torch.cuda.current_device() if device is None else int(device)
+    h = _HANDLES.get(dev)
+    if h is None:
+        with torch.cuda.device(dev):
+            h = _abi.Handle(_TABLE_PATH)
+        _HANDLES[dev] = h
+    return h
+
+
+def _h():
+    return ctypes.c_void_p(handle().ptr)
+
 
 def _read_info(info_dev: torch.Tensor) -> _abi.MiidInfo:
     host = info_dev.cpu().numpy().tobytes()
@@ -113,7 +143,7 @@ def id_raw(A: torch.Tensor, k: int | None = None, eps: float | None = None, kmax
     kk = k if k is not None else kmax
     opts = _opts(k, eps, kmax, nb, refine, hints)
     dt = _DT[A.dtype]
-    ws_bytes = lib.miid_id_workspace(M, N, dt, ctypes.byref(opts))
+    ws_bytes = lib.miid_id_workspace(_h(), M, N, dt, ctypes.byref(opts))
     if ws_bytes == 0:
         _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_id_workspace")
     ws = _WS.get("id", ws_bytes, A.device)
@@ -127,7 +157,7 @@ def id_raw(A: torch.Tensor, k: int | None = None, eps: float | None = None, kmax
             "info": torch.empty(ctypes.sizeof(_abi.MiidInfo), dtype=torch.uint8, device=dev),
         }
     Z, C, R11 = out["Z"], out["C"], out["R11"]
-    rc = lib.id_cpqr(_ptr(A), M, N, _ld(A), dt, ctypes.byref(opts), _ptr(out["J"]), _ptr(Z), _ld(Z),
+    rc = lib.id_cpqr(_h(), _ptr(A), M, N, _ld(A), dt, ctypes.byref(opts), _ptr(out["J"]), _ptr(Z), _ld(Z),
                      _ptr(R11), _ld(R11) if R11 is not None else 1, _ptr(C), _ld(C) if C is not None else 1,
                      _ptr(out["info"]), _ptr(ws), ws_bytes, _stream())
     _abi.check(rc, "id_cpqr")
@@ -170,7 +200,7 @@ def rid_sample_raw(A: torch.Tensor, idx, k: int, nb: int = 0, want_C: bool = Tru
     p = int(idx_t.numel())
     opts = _opts(k, None, k, nb, True, hints)
     dt = _DT[A.dtype]
-    ws_bytes = lib.miid_rid_sample_workspace(m, n, p, dt, ctypes.byref(opts))
+    ws_bytes = lib.miid_rid_sample_workspace(_h(), m, n, p, dt, ctypes.byref(opts))
     if ws_bytes == 0:
         _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_rid_sample_workspace")
     ws = _WS.get("rid_sample", ws_bytes, A.device)
@@ -185,7 +215,7 @@ def rid_sample_raw(A: torch.Tensor, idx, k: int, nb: int = 0, want_C: bool = Tru
         }
     out["idx"] = idx_t
     Z, C, R11 = out["Z"], out["C"], out["R11"]
-    rc = lib.rid_sample_cpqr(_ptr(A), m, n, _ld(A), dt, _ptr(idx_t), p, ctypes.byref(opts), _ptr(out["J"]),
+    rc = lib.rid_sample_cpqr(_h(), _ptr(A), m, n, _ld(A), dt, _ptr(idx_t), p, ctypes.byref(opts), _ptr(out["J"]),
                              _ptr(Z), _ld(Z), _ptr(R11), _ld(R11) if R11 is not None else 1, _ptr(C),
                              _ld(C) if C is not None else 1, _ptr(out["info"]), _ptr(ws), ws_bytes, _stream())
     _abi.check(rc, "rid_sample_cpqr")
@@ -229,7 +259,7 @@ def two_sided_raw(A: torch.Tensor, k: int, nb: int = 0, out: dict | None = None,
     m, n = A.shape
     opts = _opts(k, None, k, nb, True, hints)
     dt = _DT[A.dtype]
-    ws_bytes = lib.miid_two_sided_workspace(m, n, dt, ctypes.byref(opts))
+    ws_bytes = lib.miid_two_sided_workspace(_h(), m, n, dt, ctypes.byref(opts))
     if ws_bytes == 0:
         _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_two_sided_workspace")
     ws = _WS.get("two_sided", ws_bytes, A.device)
@@ -244,7 +274,7 @@ def two_sided_raw(A: torch.Tensor, k: int, nb: int = 0, out: dict | None = None,
             "info": torch.empty(isz, dtype=torch.uint8, device=dev),
             "info_rows": torch.empty(isz, dtype=torch.uint8, device=dev),
         }
-    rc = lib.id_two_sided(_ptr(A), m, n, _ld(A), dt, ctypes.byref(opts), _ptr(out["J"]), _ptr(out["Z"]),
+    rc = lib.id_two_sided(_h(), _ptr(A), m, n, _ld(A), dt, ctypes.byref(opts), _ptr(out["J"]), _ptr(out["Z"]),
                           _ld(out["Z"]), _ptr(out["I"]), _ptr(out["W"]), _ld(out["W"]), _ptr(out["info"]),
                           _ptr(out["info_rows"]), _ptr(ws), ws_bytes, _stream())
     _abi.check(rc, "id_two_sided")
@@ -271,7 +301,7 @@ def cur_raw(A: torch.Tensor, k: int, nb: int = 0, out: dict | None = None, hints
     m, n = A.shape
     opts = _opts(k, None, k, nb, True, hints)
     dt = _DT[A.dtype]
-    ws_bytes = lib.miid_cur_workspace(m, n, dt, ctypes.byref(opts))
+    ws_bytes = lib.miid_cur_workspace(_h(), m, n, dt, ctypes.byref(opts))
     if ws_bytes == 0:
         _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_cur_workspace")
     ws = _WS.get("cur", ws_bytes, A.device)
@@ -285,7 +315,7 @@ def cur_raw(A: torch.Tensor, k: int, nb: int = 0, out: dict | None = None, hints
             "info": torch.empty(isz, dtype=torch.uint8, device=dev),
             "info_rows": torch.empty(isz, dtype=torch.uint8, device=dev),
         }
-    rc = lib.id_cur(_ptr(A), m, n, _ld(A), dt, ctypes.byref(opts), _ptr(out["J"]), _ptr(out["I"]), _ptr(out["U"]),
+    rc = lib.id_cur(_h(), _ptr(A), m, n, _ld(A), dt, ctypes.byref(opts), _ptr(out["J"]), _ptr(out["I"]), _ptr(out["U"]),
                     _ld(out["U"]), _ptr(out["info"]), _ptr(out["info_rows"]), _ptr(ws), ws_bytes, _stream())
     _abi.check(rc, "id_cur")
     return out
@@ -324,7 +354,7 @@ def rid_raw(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: flo
         if k is None:
             raise ValueError("lstsq needs a fixed rank k")
         opts.flags |= _abi.MIID_LSTSQ_Z
-    ws_bytes = lib.miid_rid_workspace(m, n, l, ctypes.byref(opts))
+    ws_bytes = lib.miid_rid_workspace(_h(), m, n, l, ctypes.byref(opts))
     if ws_bytes == 0:
         _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_rid_workspace")
     ws = _WS.get("rid", ws_bytes, A.device)
@@ -339,7 +369,7 @@ def rid_raw(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: flo
             "info": torch.empty(ctypes.sizeof(_abi.MiidInfo), dtype=torch.uint8, device=dev),
         }
     Z, C, Y, R11 = out["Z"], out["C"], out["Y"], out["R11"]
-    rc = lib.rid_sketch_cpqr(_ptr(A), m, n, _ld(A), _ptr(om), l, _ld(om), int(mode), ctypes.byref(opts),
+    rc = lib.rid_sketch_cpqr(_h(), _ptr(A), m, n, _ld(A), _ptr(om), l, _ld(om), int(mode), ctypes.byref(opts),
                              _ptr(out["J"]), _ptr(Z), _ld(Z), _ptr(C), _ld(C) if C is not None else 1,
                              _ptr(Y), _ld(Y) if Y is not None else 1, _ptr(R11), _ld(R11) if R11 is not None else 1,
                              _ptr(out["info"]), _ptr(ws), ws_bytes, _stream())
@@ -417,11 +447,11 @@ def batched_raw(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, out: d
             "info": torch.empty(nblk * ctypes.sizeof(_abi.MiidInfo), dtype=torch.uint8, device=dev),
         }
     dt = _DT[A.dtype]
-    ws_bytes = lib.miid_batched_workspace(out["nblk"], dt)
+    ws_bytes = lib.miid_batched_workspace(_h(), out["nblk"], dt)
     ws = _WS.get("batched", ws_bytes, dev)
     opts = _abi.MiidOpts()
     opts.k, opts.kmax, opts.eps, opts.nb, opts.flags = 0, int(kmax), float(eps), 0, int(hints)
-    rc = lib.id_batched(out["nblk"], _ptr(A), _ptr(out["a_off"]), _ptr(out["m"]), _ptr(out["n"]), dt,
+    rc = lib.id_batched(_h(), out["nblk"], _ptr(A), _ptr(out["a_off"]), _ptr(out["m"]), _ptr(out["n"]), dt,
                         ctypes.byref(opts), _ptr(out["J"]), _ptr(out["j_off"]), _ptr(out["Z"]),
                         _ptr(out["z_off"]), _ptr(out["info"]), _ptr(ws), ws_bytes, _stream())
     _abi.check(rc, "id_batched")
@@ -460,12 +490,12 @@ def id_backward(A: torch.Tensor, J: torch.Tensor, R11: torch.Tensor, Z: torch.Te
     gCc = colmajor(gC.to(A.dtype)) if gC is not None else None
     gZc = colmajor(gZ.to(A.dtype)) if gZ is not None else None
     dt = _DT[A.dtype]
-    ws_bytes = lib.miid_backward_workspace(m, n, k, dt)
+    ws_bytes = lib.miid_backward_workspace(_h(), m, n, k, dt)
     if ws_bytes == 0:
         _abi.check(_abi.MIID_E_UNSUPPORTED, "miid_backward_workspace")
     ws = _WS.get("bwd", ws_bytes, A.device)
     gA = empty_colmajor(m, n, A.dtype, A.device)
-    rc = lib.id_backward(_ptr(A), m, n, _ld(A), dt, _ptr(J), k, _ptr(R11), _ld(R11), _ptr(Z), _ld(Z),
+    rc = lib.id_backward(_h(), _ptr(A), m, n, _ld(A), dt, _ptr(J), k, _ptr(R11), _ld(R11), _ptr(Z), _ld(Z),
                          _ptr(gCc), _ld(gCc) if gCc is not None else 1, _ptr(gZc), _ld(gZc) if gZc is not None else 1,
                          _ptr(gA), _ld(gA), _ptr(ws), ws_bytes, _stream())
     _abi.check(rc, "id_backward")

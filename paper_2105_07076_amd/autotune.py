@@ -8,7 +8,8 @@ batched kernel).  :func:`tune_id` and :func:`tune_batched` time every
 candidate on the caller's own data (or a seeded synthetic matrix of the given
 shape) with HIP events and return the fastest; :class:`Table` keeps results
 in a JSON file keyed by device, routine, dtype and shape, so a tuned shape is
-looked up instead of re-timed.
+looked up instead of re-timed, and exports them as the library's own tuning
+table, which a miid_handle applies to calls that leave the knobs at 0.
 """
 from __future__ import annotations
 
@@ -165,6 +166,28 @@ class Table:
         with open(tmp, "w") as f:
             json.dump(self.entries, f, indent=1, sort_keys=True)
         os.replace(tmp, p)
+
+    def export_native(self, path: str, device: str | None = None) -> int:
+        """Write the entries of ``device`` (default: the current GPU's name)
+        as the library's own tuning table -- rows "routine dtype m n k nb
+        hints" that miid_create reads (api.set_tuning_table) -- and return
+        the number of rows.  A batched entry's shape is (nblk, 0, kmax)."""
+        if device is None:
+            device = torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
+        dts = {"float32": "f32", "float64": "f64"}
+        rows = []
+        for k, e in sorted(self.entries.items()):
+            dev, routine, dt, shape = k.split("|")
+            if dev != device or dt not in dts:
+                continue
+            dims = [int(v) for v in shape.split("x")] + [0, 0, 0]
+            rows.append(f"{routine} {dts[dt]} {dims[0]} {dims[1]} {dims[2]} {int(e['nb'])} {int(e['hints']):#x}")
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            f.write("# routine dtype m n k nb hints\n")
+            f.writelines(r + "\n" for r in rows)
+        os.replace(tmp, path)
+        return len(rows)
 
     def id_config(self, m: int, n: int, k: int, dtype, tune_if_missing: bool = False, **kw) -> Choice | None:
         """The stored choice for an ID of this shape; tuned (and stored) on a

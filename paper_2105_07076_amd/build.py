@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmiid.so")
-SOURCES = ["abi.hip", "id_cpqr.hip", "rid.hip", "batched.hip", "backward.hip", "two_sided.hip"]
+SOURCES = ["abi.hip", "handle.hip", "id_cpqr.hip", "rid.hip", "batched.hip", "backward.hip", "two_sided.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

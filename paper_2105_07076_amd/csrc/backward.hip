@@ -16,6 +16,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "handle.hpp"
 #include "cpqr.hpp"
 #include "prof.hpp"
 
@@ -277,13 +278,13 @@ using namespace miid;
 
 extern "C" {
 
-size_t miid_backward_workspace(int64_t m, int64_t n, int32_t k, miid_dtype dtype) {
+static size_t backward_workspace_body(int64_t m, int64_t n, int32_t k, miid_dtype dtype) {
     if (m < 1 || n < 1 || k < 1 || k > kBwMaxK || k > m || k > n) return 0;
     if (dtype != MIID_F32 && dtype != MIID_F64) return 0;
     return bw_plan(m, n, k, dtype == MIID_F64 ? 8 : 4).total;
 }
 
-int id_backward(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const int32_t* J, int32_t k,
+static int backward_body(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const int32_t* J, int32_t k,
                 const double* R11, int64_t ldr, const void* Z, int64_t ldz, const void* gC, int64_t ldgc,
                 const void* gZ, int64_t ldgz, void* gA, int64_t ldga, void* ws, size_t ws_bytes, void* stream) {
     if (!A) return -1;
@@ -312,6 +313,20 @@ int id_backward(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dty
                               ldgc, (const double*)gZ, ldgz, (double*)gA, ldga, w, B, s);
     return run_bw<float>((const float*)A, m, n, lda, J, k, R11, ldr, (const float*)Z, ldz, (const float*)gC, ldgc,
                          (const float*)gZ, ldgz, (float*)gA, ldga, w, B, s);
+}
+
+// ---- entry points: the handle checked, then the bodies above ------------
+size_t miid_backward_workspace(miid_handle h, int64_t m, int64_t n, int32_t k, miid_dtype dtype) {
+    if (check_handle(h) != 0) return 0;
+    return backward_workspace_body(m, n, k, dtype);
+}
+
+int id_backward(miid_handle h, const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const int32_t* J,
+                int32_t k, const double* R11, int64_t ldr, const void* Z, int64_t ldz, const void* gC, int64_t ldgc,
+                const void* gZ, int64_t ldgz, void* gA, int64_t ldga, void* ws, size_t ws_bytes, void* stream) {
+    if (check_handle(h) != 0) return -1;
+    return shift_arg(backward_body(A, m, n, lda, dtype, J, k, R11, ldr, Z, ldz, gC, ldgc, gZ, ldgz, gA, ldga, ws,
+                                   ws_bytes, stream));
 }
 
 }  // extern "C"

@@ -46,6 +46,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "handle.hpp"
 #include "cpqr.hpp"
 #include "prof.hpp"
 
@@ -894,12 +895,7 @@ struct BPlan {
 // neither registers nor LDS.
 BPlan batched_plan(int32_t nblk, size_t esz) {
     BPlan P;
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
-    }
-    P.grid = std::max(1, std::min(nblk, cus));
+    P.grid = std::max(1, std::min(nblk, dev_info().cus));
     const int grows = esz == 8 ? b_glob_rows<double>() : b_glob_rows<float>();
     size_t off = 0;
     P.oOrder = off;
@@ -915,14 +911,14 @@ BPlan batched_plan(int32_t nblk, size_t esz) {
 
 extern "C" {
 
-size_t miid_batched_workspace(int32_t nblk, miid_dtype dtype) {
+static size_t batched_workspace_body(int32_t nblk, miid_dtype dtype) {
     if (nblk < 1 || (dtype != MIID_F32 && dtype != MIID_F64)) return 0;
     return batched_plan(nblk, dtype == MIID_F64 ? 8 : 4).total;
 }
 
-int id_batched(int32_t nblk, const void* A, const int64_t* a_off, const int32_t* m, const int32_t* n,
-               miid_dtype dtype, const miid_opts* opts, int32_t* J, const int64_t* j_off, void* Z,
-               const int64_t* z_off, miid_info* info, void* ws, size_t ws_bytes, void* stream) {
+static int batched_body(int32_t nblk, const void* A, const int64_t* a_off, const int32_t* m, const int32_t* n,
+                        miid_dtype dtype, const miid_opts* opts, int32_t* J, const int64_t* j_off, void* Z,
+                        const int64_t* z_off, miid_info* info, void* ws, size_t ws_bytes, void* stream) {
     if (nblk < 1) return -1;
     if (!A) return -2;
     if (!a_off) return -3;
@@ -950,28 +946,33 @@ int id_batched(int32_t nblk, const void* A, const int64_t* a_off, const int32_t*
     hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), 0, s, m, n, nblk, order, queue, info);
     const int pr = prof_take(MIID_K_BATCHED, 0, nblk, 0);
     if (dtype == MIID_F64) {
-        static bool attr64 = false;
-        if (!attr64) {
-            MIID_HIP(hipFuncSetAttribute((const void*)k_batched<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         kBLdsBytes));
-            attr64 = true;
-        }
+        MIID_HIP(lds_limit_once((const void*)k_batched<double>, kBLdsBytes));
         MIID_LAUNCH(pr, k_batched<double>, dim3(P.grid), dim3(kBThreads), (size_t)kBLdsBytes, s, (const double*)A,
                     a_off, m, n, eps, kmax, lmax, J, j_off, (double*)Z, z_off, info, order, queue,
                     reinterpret_cast<double*>(w + P.oW));
     } else {
-        static bool attr32 = false;
-        if (!attr32) {
-            MIID_HIP(hipFuncSetAttribute((const void*)k_batched<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         kBLdsBytes));
-            attr32 = true;
-        }
+        MIID_HIP(lds_limit_once((const void*)k_batched<float>, kBLdsBytes));
         MIID_LAUNCH(pr, k_batched<float>, dim3(P.grid), dim3(kBThreads), (size_t)kBLdsBytes, s, (const float*)A,
                     a_off, m, n, eps, kmax, lmax, J, j_off, (float*)Z, z_off, info, order, queue,
                     reinterpret_cast<float*>(w + P.oW));
     }
     MIID_HIP(hipGetLastError());
     return 0;
+}
+
+// ---- entry points: the handle resolved, then the bodies above -----------
+size_t miid_batched_workspace(miid_handle h, int32_t nblk, miid_dtype dtype) {
+    if (check_handle(h) != 0) return 0;
+    return batched_workspace_body(nblk, dtype);
+}
+
+int id_batched(miid_handle h, int32_t nblk, const void* A, const int64_t* a_off, const int32_t* m, const int32_t* n,
+               miid_dtype dtype, const miid_opts* opts, int32_t* J, const int64_t* j_off, void* Z,
+               const int64_t* z_off, miid_info* info, void* ws, size_t ws_bytes, void* stream) {
+    miid_opts o;
+    if (resolve_opts(h, kTuneBatched, dtype, nblk, 0, opts ? opts->kmax : 0, opts, &o) != 0) return -1;
+    return shift_arg(batched_body(nblk, A, a_off, m, n, dtype, opts ? &o : nullptr, J, j_off, Z, z_off, info, ws,
+                                  ws_bytes, stream));
 }
 
 }  // extern "C"

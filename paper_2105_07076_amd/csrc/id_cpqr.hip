@@ -36,6 +36,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "handle.hpp"
 #include "cpqr.hpp"
 #include "prof.hpp"
 
@@ -1368,14 +1369,11 @@ template <typename T, int NP, int GL>
 static hipError_t launch_fused_k(const IdPlan& P, int pr, hipStream_t stream, T* S, T* V, T* F, ColPartial* pin,
                                  ColPartial* pout, int npin, DevState* st, int32_t* J, T* R, double* nu,
                                  double* nuref, int32_t* sel, int32_t* recomp, int j, int i, double tol) {
-    static bool attr = false;
     const size_t shmem = (size_t)P.ldw * kFusedMaxNb * P.esz;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_step_fused<T, NP, GL>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           kFusedMaxRows * kFusedMaxNb * (int)sizeof(T));
+    {
+        const hipError_t e = lds_limit_once((const void*)k_step_fused<T, NP, GL>,
+                                            kFusedMaxRows * kFusedMaxNb * (int)sizeof(T));
         if (e != hipSuccess) return e;
-        attr = true;
     }
     MIID_LAUNCH(pr, (k_step_fused<T, NP, GL>), dim3(P.fnpart), dim3(kFusedThreads), shmem, stream, S, P.ldw, P.m,
                 P.n, V, F, P.nb, pin, pout, npin, st, J, R, nu, nuref, sel, recomp, j, i, (int)P.tol, P.eps, tol);
@@ -1430,27 +1428,16 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
     const int64_t m = P.m, n = P.n, ldw = P.ldw;
     const int nb = P.nb;
 
-    static bool attr_done = false;
-    if (!attr_done) {
-        // dynamic LDS above 64 KB: the right-hand sides of the solve
-        // (the largest kpad of each variant: 256, 512, 1024 rows of NC + 1 doubles)
-        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 64>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     256 * 65 * 8));
-        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 32>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     512 * 33 * 8));
-        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     1024 * 17 * 8));
-        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 64, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     256 * 65 * 8));
-        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 32, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     512 * 33 * 8));
-        MIID_HIP(hipFuncSetAttribute((const void*)k_trsm_blk<T, 16, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     1024 * 17 * 8));
-        // and the pivot kernel's per-row products (kThreads x (nb + 1))
-        MIID_HIP(hipFuncSetAttribute((const void*)k_pivot_col<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     kThreads * (kMaxNb + 1) * 8));
-        attr_done = true;
-    }
+    // dynamic LDS above 64 KB (once per device): the right-hand sides of the
+    // solve (the largest kpad of each variant: 256, 512, 1024 rows of NC + 1
+    // doubles) and the pivot kernel's per-row products (kThreads x (nb + 1))
+    MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 64>, 256 * 65 * 8));
+    MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 32>, 512 * 33 * 8));
+    MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 16>, 1024 * 17 * 8));
+    MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 64, true>, 256 * 65 * 8));
+    MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 32, true>, 512 * 33 * 8));
+    MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 16, true>, 1024 * 17 * 8));
+    MIID_HIP(lds_limit_once((const void*)k_pivot_col<T>, kThreads * (kMaxNb + 1) * 8));
 
     // control block, R rows
     hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(64), 0, stream, reinterpret_cast<unsigned char*>(st),
@@ -1872,18 +1859,11 @@ size_t semi_solve_workspace(int k) {
 
 template <typename T, int JMODE>
 static hipError_t semi_solve_attr() {
-    static bool done = false;
-    if (!done) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_trsm_blk<T, 64, true, JMODE>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 256 * 65 * 8);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_trsm_blk<T, 32, true, JMODE>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 512 * 33 * 8);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_trsm_blk<T, 16, true, JMODE>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 1024 * 17 * 8);
+    {
+        hipError_t e = lds_limit_once((const void*)k_trsm_blk<T, 64, true, JMODE>, 256 * 65 * 8);
+        if (e == hipSuccess) e = lds_limit_once((const void*)k_trsm_blk<T, 32, true, JMODE>, 512 * 33 * 8);
+        if (e == hipSuccess) e = lds_limit_once((const void*)k_trsm_blk<T, 16, true, JMODE>, 1024 * 17 * 8);
         if (e != hipSuccess) return e;
-        done = true;
     }
     return hipSuccess;
 }
@@ -2196,13 +2176,13 @@ using namespace miid;
 
 extern "C" {
 
-size_t miid_rid_sample_workspace(int64_t m, int64_t n, int32_t p, miid_dtype dtype, const miid_opts* opts) {
+static size_t rid_sample_workspace_body(int64_t m, int64_t n, int32_t p, miid_dtype dtype, const miid_opts* opts) {
     RsPlan Q;
     if (m < 1 || n < 1 || rs_plan(m, n, p, dtype, opts, &Q) != 0) return 0;
     return Q.total;
 }
 
-int rid_sample_cpqr(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const int32_t* idx, int32_t p,
+static int rid_sample_body(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const int32_t* idx, int32_t p,
                     const miid_opts* opts, int32_t* J, void* Z, int64_t ldz, double* R11, int64_t ldr, void* C,
                     int64_t ldc, miid_info* info, void* ws, size_t ws_bytes, void* stream) {
     if (!A) return -1;
@@ -2232,13 +2212,13 @@ int rid_sample_cpqr(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype
                                  info, w, s);
 }
 
-size_t miid_id_workspace(int64_t m, int64_t n, miid_dtype dtype, const miid_opts* opts) {
+static size_t id_workspace_body(int64_t m, int64_t n, miid_dtype dtype, const miid_opts* opts) {
     IdPlan P;
     if (make_plan(m, n, dtype, opts, &P) != 0) return 0;
     return P.total;
 }
 
-int id_cpqr(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const miid_opts* opts, int32_t* J,
+static int id_cpqr_body(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const miid_opts* opts, int32_t* J,
             void* Z, int64_t ldz, double* R11, int64_t ldr, void* C, int64_t ldc, miid_info* info, void* ws,
             size_t ws_bytes, void* stream) {
     if (!A) return -1;
@@ -2261,6 +2241,39 @@ int id_cpqr(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, 
                               (const double*)A, lda, P.m);
     return run_id<float>(P, (const float*)A, lda, J, (float*)Z, ldz, R11, ldr, (float*)C, ldc, info, w, s, false,
                          (const float*)A, lda, P.m);
+}
+
+// ---- entry points: the handle resolved, then the bodies above -----------
+size_t miid_rid_sample_workspace(miid_handle h, int64_t m, int64_t n, int32_t p, miid_dtype dtype,
+                                 const miid_opts* opts) {
+    miid_opts o;
+    if (resolve_opts(h, kTuneRidSample, dtype, m, n, opts ? opts->k : 0, opts, &o) != 0) return 0;
+    return rid_sample_workspace_body(m, n, p, dtype, opts ? &o : nullptr);
+}
+
+int rid_sample_cpqr(miid_handle h, const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
+                    const int32_t* idx, int32_t p, const miid_opts* opts, int32_t* J, void* Z, int64_t ldz,
+                    double* R11, int64_t ldr, void* C, int64_t ldc, miid_info* info, void* ws, size_t ws_bytes,
+                    void* stream) {
+    miid_opts o;
+    if (resolve_opts(h, kTuneRidSample, dtype, m, n, opts ? opts->k : 0, opts, &o) != 0) return -1;
+    return shift_arg(rid_sample_body(A, m, n, lda, dtype, idx, p, opts ? &o : nullptr, J, Z, ldz, R11, ldr, C, ldc,
+                                     info, ws, ws_bytes, stream));
+}
+
+size_t miid_id_workspace(miid_handle h, int64_t m, int64_t n, miid_dtype dtype, const miid_opts* opts) {
+    miid_opts o;
+    if (resolve_opts(h, kTuneId, dtype, m, n, opts ? opts->k : 0, opts, &o) != 0) return 0;
+    return id_workspace_body(m, n, dtype, opts ? &o : nullptr);
+}
+
+int id_cpqr(miid_handle h, const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const miid_opts* opts,
+            int32_t* J, void* Z, int64_t ldz, double* R11, int64_t ldr, void* C, int64_t ldc, miid_info* info,
+            void* ws, size_t ws_bytes, void* stream) {
+    miid_opts o;
+    if (resolve_opts(h, kTuneId, dtype, m, n, opts ? opts->k : 0, opts, &o) != 0) return -1;
+    return shift_arg(id_cpqr_body(A, m, n, lda, dtype, opts ? &o : nullptr, J, Z, ldz, R11, ldr, C, ldc, info, ws,
+                                  ws_bytes, stream));
 }
 
 }  // extern "C"

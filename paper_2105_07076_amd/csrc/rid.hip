@@ -14,6 +14,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "handle.hpp"
 #include "cpqr.hpp"
 #include "prof.hpp"
 
@@ -185,13 +186,10 @@ template <bool SPLIT, bool VEC, int MTB, int KC>
 static hipError_t launch_sketch(int pr, hipStream_t s, int64_t n, int mt_total, const float* A, int64_t lda, int64_t m,
                                 const uint16_t* Wt, int64_t mpad, float* S, int64_t ldw, float* Y, int64_t ldy,
                                 int l) {
-    static bool attr = false;
     constexpr size_t lds = sketch_lds(MTB, KC);
-    if (!attr) {
-        const hipError_t e = hipFuncSetAttribute((const void*)k_sketch<SPLIT, VEC, MTB, KC>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    {
+        const hipError_t e = lds_limit_once((const void*)k_sketch<SPLIT, VEC, MTB, KC>, (int)lds);
         if (e != hipSuccess) return e;
-        attr = true;
     }
     dim3 grid((unsigned)((n + kSkCols - 1) / kSkCols), (unsigned)((mt_total + MTB - 1) / MTB));
     MIID_LAUNCH(pr, (k_sketch<SPLIT, VEC, MTB, KC>), grid, dim3(kSkThreads), lds, s, A, lda, m, n, Wt, mpad,
@@ -265,13 +263,13 @@ using namespace miid;
 
 extern "C" {
 
-size_t miid_rid_workspace(int64_t m, int64_t n, int32_t l, const miid_opts* opts) {
+static size_t rid_workspace_body(int64_t m, int64_t n, int32_t l, const miid_opts* opts) {
     RidPlan R;
     if (make_rid_plan(m, n, l, opts, &R) != 0) return 0;
     return R.total;
 }
 
-int rid_sketch_cpqr(const float* A, int64_t m, int64_t n, int64_t lda, const uint16_t* Omega, int32_t l, int64_t ldo,
+static int rid_body(const float* A, int64_t m, int64_t n, int64_t lda, const uint16_t* Omega, int32_t l, int64_t ldo,
                     int32_t mode, const miid_opts* opts, int32_t* J, float* Z, int64_t ldz, float* C, int64_t ldc,
                     float* Y, int64_t ldy, double* R11, int64_t ldr, miid_info* info, void* ws, size_t ws_bytes,
                     void* stream) {
@@ -332,6 +330,23 @@ int rid_sketch_cpqr(const float* A, int64_t m, int64_t n, int64_t lda, const uin
     hipLaunchKernelGGL(k_ls_status, dim3(1), dim3(64), 0, s, info, reinterpret_cast<const uint32_t*>(wl + R.ls.oFlag));
     MIID_HIP(hipGetLastError());
     return 0;
+}
+
+// ---- entry points: the handle resolved, then the bodies above -----------
+size_t miid_rid_workspace(miid_handle h, int64_t m, int64_t n, int32_t l, const miid_opts* opts) {
+    miid_opts o;
+    if (resolve_opts(h, kTuneRid, MIID_F32, m, n, opts ? opts->k : 0, opts, &o) != 0) return 0;
+    return rid_workspace_body(m, n, l, opts ? &o : nullptr);
+}
+
+int rid_sketch_cpqr(miid_handle h, const float* A, int64_t m, int64_t n, int64_t lda, const uint16_t* Omega,
+                    int32_t l, int64_t ldo, int32_t mode, const miid_opts* opts, int32_t* J, float* Z, int64_t ldz,
+                    float* C, int64_t ldc, float* Y, int64_t ldy, double* R11, int64_t ldr, miid_info* info,
+                    void* ws, size_t ws_bytes, void* stream) {
+    miid_opts o;
+    if (resolve_opts(h, kTuneRid, MIID_F32, m, n, opts ? opts->k : 0, opts, &o) != 0) return -1;
+    return shift_arg(rid_body(A, m, n, lda, Omega, l, ldo, mode, opts ? &o : nullptr, J, Z, ldz, C, ldc, Y, ldy, R11,
+                              ldr, info, ws, ws_bytes, stream));
 }
 
 }  // extern "C"

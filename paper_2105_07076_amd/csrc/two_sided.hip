@@ -12,6 +12,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "handle.hpp"
 #include "cpqr.hpp"
 
 namespace miid {
@@ -200,13 +201,13 @@ using namespace miid;
 
 extern "C" {
 
-size_t miid_two_sided_workspace(int64_t m, int64_t n, miid_dtype dtype, const miid_opts* opts) {
+static size_t two_sided_workspace_body(int64_t m, int64_t n, miid_dtype dtype, const miid_opts* opts) {
     TsPlan P;
     if (m < 1 || n < 1 || ts_plan(m, n, dtype, opts, &P) != 0) return 0;
     return P.total;
 }
 
-int id_two_sided(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const miid_opts* opts,
+static int two_sided_body(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const miid_opts* opts,
                  int32_t* J, void* Z, int64_t ldz, int32_t* I, void* W, int64_t ldw, miid_info* info,
                  miid_info* info_rows, void* ws, size_t ws_bytes, void* stream) {
     if (!A) return -1;
@@ -237,13 +238,13 @@ int id_two_sided(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dt
                                 w, s);
 }
 
-size_t miid_cur_workspace(int64_t m, int64_t n, miid_dtype dtype, const miid_opts* opts) {
+static size_t cur_workspace_body(int64_t m, int64_t n, miid_dtype dtype, const miid_opts* opts) {
     CurPlan P;
     if (m < 1 || n < 1 || cur_plan(m, n, dtype, opts, &P) != 0) return 0;
     return P.total;
 }
 
-int id_cur(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const miid_opts* opts, int32_t* J,
+static int cur_body(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const miid_opts* opts, int32_t* J,
            int32_t* I, void* U, int64_t ldu, miid_info* info, miid_info* info_rows, void* ws, size_t ws_bytes,
            void* stream) {
     if (!A) return -1;
@@ -268,6 +269,37 @@ int id_cur(const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, c
     if (dtype == MIID_F64)
         return run_cur<double>(P, (const double*)A, m, n, lda, J, I, (double*)U, ldu, info, info_rows, w, s);
     return run_cur<float>(P, (const float*)A, m, n, lda, J, I, (float*)U, ldu, info, info_rows, w, s);
+}
+
+// ---- entry points: the handle resolved, then the bodies above -----------
+size_t miid_two_sided_workspace(miid_handle h, int64_t m, int64_t n, miid_dtype dtype, const miid_opts* opts) {
+    miid_opts o;
+    if (resolve_opts(h, kTuneTwoSided, dtype, m, n, opts ? opts->k : 0, opts, &o) != 0) return 0;
+    return two_sided_workspace_body(m, n, dtype, opts ? &o : nullptr);
+}
+
+int id_two_sided(miid_handle h, const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype,
+                 const miid_opts* opts, int32_t* J, void* Z, int64_t ldz, int32_t* I, void* W, int64_t ldw,
+                 miid_info* info, miid_info* info_rows, void* ws, size_t ws_bytes, void* stream) {
+    miid_opts o;
+    if (resolve_opts(h, kTuneTwoSided, dtype, m, n, opts ? opts->k : 0, opts, &o) != 0) return -1;
+    return shift_arg(two_sided_body(A, m, n, lda, dtype, opts ? &o : nullptr, J, Z, ldz, I, W, ldw, info, info_rows,
+                                    ws, ws_bytes, stream));
+}
+
+size_t miid_cur_workspace(miid_handle h, int64_t m, int64_t n, miid_dtype dtype, const miid_opts* opts) {
+    miid_opts o;
+    if (resolve_opts(h, kTuneCur, dtype, m, n, opts ? opts->k : 0, opts, &o) != 0) return 0;
+    return cur_workspace_body(m, n, dtype, opts ? &o : nullptr);
+}
+
+int id_cur(miid_handle h, const void* A, int64_t m, int64_t n, int64_t lda, miid_dtype dtype, const miid_opts* opts,
+           int32_t* J, int32_t* I, void* U, int64_t ldu, miid_info* info, miid_info* info_rows, void* ws,
+           size_t ws_bytes, void* stream) {
+    miid_opts o;
+    if (resolve_opts(h, kTuneCur, dtype, m, n, opts ? opts->k : 0, opts, &o) != 0) return -1;
+    return shift_arg(cur_body(A, m, n, lda, dtype, opts ? &o : nullptr, J, I, U, ldu, info, info_rows, ws, ws_bytes,
+                              stream));
 }
 
 }  // extern "C"

@@ -42,3 +42,32 @@ def test_table_roundtrip(tmp_path):
     t2 = autotune.Table(str(tmp_path / "tune.json"))
     c = t2.get(k)
     assert c.nb == 32 and c.hints == 1 << 8 and c.label == "x"
+
+
+def test_table_exports_the_native_rows(tmp_path):
+    """The JSON table's entries for one device become rows the library's
+    miid_create accepts; the exported panel width reaches the workspace."""
+    import ctypes
+    t = autotune.Table()
+    t.put(autotune.key("id", torch.float64, (100, 300, 4), device="dev0"),
+          autotune.Choice(nb=64, hints=autotune.H(_abi.MIID_HINT_PATH_SHIFT, 1), ms=1.0, label="x"))
+    t.put(autotune.key("batched", torch.float32, (4096, 0, 64), device="dev0"),
+          autotune.Choice(nb=0, hints=autotune.H(_abi.MIID_HINT_LPC_SHIFT, 4), ms=1.0, label="y"))
+    t.put(autotune.key("id", torch.float64, (8, 8, 2), device="other"),
+          autotune.Choice(nb=16, hints=0, ms=1.0, label="z"))
+    path = str(tmp_path / "native.txt")
+    assert t.export_native(path, device="dev0") == 2
+    text = open(path).read()
+    assert "id f64 100 300 4 64 0x10000" in text
+    assert "batched f32 4096 0 64 0 0x400000" in text
+    lib = _abi.load()
+    h = _abi.Handle(path)
+    assert h.rows == 2
+    o = _abi.MiidOpts()
+    o.k = 4
+    o64 = _abi.MiidOpts()
+    o64.k, o64.nb = 4, 64
+    hp = ctypes.c_void_p(h.ptr)
+    assert (lib.miid_id_workspace(hp, 100, 300, 1, ctypes.byref(o))
+            == lib.miid_id_workspace(None, 100, 300, 1, ctypes.byref(o64)))
+    h.close()

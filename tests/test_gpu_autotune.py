@@ -65,3 +65,28 @@ def test_tune_batched_lane_caps_same_ids():
         assert np.array_equal(r.k, ref.k), label
         assert torch.equal(r.J, ref.J), label
         assert rel(to_np(r.Z), to_np(ref.Z)) <= 1e-10, label
+
+
+def test_native_table_applies_to_calls(tmp_path):
+    """A handle created with a tuning table runs a call that leaves nb and the
+    hints at 0 with the matching row's launch shape: the same bits as the
+    call that passes that shape itself."""
+    miid, autotune, api = _mods()
+    from paper_2105_07076_amd import _abi
+    A = idgen.lowrank_plus_noise_device(22, 512, 3000, np.exp(-np.arange(512) / 64.0), 1e-8,
+                                        dtype=torch.float64)
+    hints = _abi.hint(_abi.MIID_HINT_PATH_SHIFT, 1) | _abi.hint(_abi.MIID_HINT_CPW_SHIFT, 4)
+    path = tmp_path / "tune.txt"
+    path.write_text(f"id f64 512 3000 96 16 {hints:#x}\n")
+    try:
+        api.set_tuning_table(str(path))
+        h = api.handle()
+        assert h.rows == 1 and h.device == torch.cuda.current_device()
+        r_tab = miid.id(A, k=96)
+    finally:
+        api.set_tuning_table(None)
+    r_exp = miid.id(A, k=96, nb=16, hints=hints)
+    r_def = miid.id(A, k=96)
+    assert torch.equal(r_tab.J, r_exp.J) and torch.equal(r_tab.Z, r_exp.Z)
+    assert torch.equal(r_tab.J, r_def.J)
+    assert rel(t_part(to_np(r_tab.Z), to_np(r_tab.J)), t_part(to_np(r_def.Z), to_np(r_def.J))) <= 1e-12

@@ -99,7 +99,7 @@ def test_two_sided_rejects_tolerance_mode():
     from paper_2105_07076_amd import _abi, api
     lib = _abi.load()
     opts = api._opts(None, 1e-3, 8, 0, True)
-    assert lib.miid_two_sided_workspace(16, 40, _abi.MIID_F64, ctypes.byref(opts)) == 0
+    assert lib.miid_two_sided_workspace(None, 16, 40, _abi.MIID_F64, ctypes.byref(opts)) == 0
 
 
 def test_two_sided_4096x16384_k256():
