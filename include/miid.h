@@ -334,6 +334,34 @@ int id_batched(miid_handle h, int32_t nblk, const void *A, const int64_t *a_off,
                miid_info *info, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * id_batched for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * The same kernels and the same results as id_batched (arguments 1-13 as
+ * there; no workspace), with the library's own static scratch instead of
+ * `ws`: 64 MiB of device memory per GPU, reserved when the library is
+ * loaded and held until the process ends.  This call allocates nothing;
+ * the scratch's address is looked up once per device, by miid_create or by
+ * the first call on that device.
+ * Limits: nblk <= 262144 (else MIID_E_UNSUPPORTED).  Rows of a block that
+ * fit neither the registers nor the LDS get
+ *     rg = min(floor((64 MiB - 1 MiB - 256 B) / (G * 512 * esz)) rounded
+ *              down to a multiple of 4, the most any block needs)
+ * rows per lane, G = min(nblk, compute units), esz = 4 (FP32) or 8 (FP64);
+ * a block that needs more gets k_out = 0 and MIID_BLOCK_UNSUPPORTED like a
+ * block outside the size limits.  With 256 compute units every FP32 block
+ * with n <= 512 fits, and in FP64 those with n <= 256; the blocks that can
+ * exceed rg are the widest and tallest ones (n > 256 in FP64 or n > 512 in
+ * FP32, m near 256).
+ * Every call on a GPU uses that GPU's one copy of the scratch: calls that
+ * overlap in time on one GPU (two streams, two threads) race and must not
+ * be issued; calls in stream order are fine.
+ * ---------------------------------------------------------------------- */
+int id_batched_noalloc(miid_handle h, int32_t nblk, const void *A, const int64_t *a_off,
+                       const int32_t *m, const int32_t *n, miid_dtype dtype,
+                       const miid_opts *opts, int32_t *J, const int64_t *j_off, void *Z,
+                       const int64_t *z_off, miid_info *info, void *stream);
+
+/* ------------------------------------------------------------------------
  * Adjoint of the ID with the pivots held fixed (the paper has no
  * derivatives; this is the derivative of T = C^+ A_rest, C = A[:, J]).
  * Given upstream gradients gC (of C) and gZ (of Z), with M = (C^T C)^{-1} Gz

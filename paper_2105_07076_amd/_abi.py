@@ -36,7 +36,7 @@ EXPORTED = [
     "miid_rid_sample_workspace", "rid_sample_cpqr",
     "miid_two_sided_workspace", "id_two_sided",
     "miid_cur_workspace", "id_cur",
-    "miid_batched_workspace", "id_batched",
+    "miid_batched_workspace", "id_batched", "id_batched_noalloc",
     "miid_backward_workspace", "id_backward",
 ]
 
@@ -120,6 +120,8 @@ def load(path: str = LIB_PATH):
     lib.miid_batched_workspace.argtypes = [H, I32, ctypes.c_int]
     lib.id_batched.restype = ctypes.c_int
     lib.id_batched.argtypes = [H, I32, P, P, P, P, ctypes.c_int, OPTS, P, P, P, P, P, P, SZ, P]
+    lib.id_batched_noalloc.restype = ctypes.c_int
+    lib.id_batched_noalloc.argtypes = [H, I32, P, P, P, P, ctypes.c_int, OPTS, P, P, P, P, P, P]
     lib.miid_backward_workspace.restype = SZ
     lib.miid_backward_workspace.argtypes = [H, I64, I64, I32, ctypes.c_int]
     lib.id_backward.restype = ctypes.c_int

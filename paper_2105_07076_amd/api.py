@@ -420,9 +420,11 @@ class BatchedResult:
 
 
 def batched_raw(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, out: dict | None = None,
-                hints: int = 0):
+                hints: int = 0, noalloc: bool = False):
     """Enqueue id_batched without synchronising.  ``A`` is the packed blocks
-    (1-D float32/float64 CUDA tensor), ``a_off``/``m``/``n`` host sequences."""
+    (1-D float32/float64 CUDA tensor), ``a_off``/``m``/``n`` host sequences.
+    ``noalloc`` calls id_batched_noalloc, which uses the library's static
+    scratch instead of a workspace."""
     import numpy as np
     lib = _abi.load()
     if A.dtype not in _DT or not A.is_cuda:
@@ -447,10 +449,16 @@ def batched_raw(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, out: d
             "info": torch.empty(nblk * ctypes.sizeof(_abi.MiidInfo), dtype=torch.uint8, device=dev),
         }
     dt = _DT[A.dtype]
-    ws_bytes = lib.miid_batched_workspace(_h(), out["nblk"], dt)
-    ws = _WS.get("batched", ws_bytes, dev)
     opts = _abi.MiidOpts()
     opts.k, opts.kmax, opts.eps, opts.nb, opts.flags = 0, int(kmax), float(eps), 0, int(hints)
+    if noalloc:
+        rc = lib.id_batched_noalloc(_h(), out["nblk"], _ptr(A), _ptr(out["a_off"]), _ptr(out["m"]), _ptr(out["n"]),
+                                    dt, ctypes.byref(opts), _ptr(out["J"]), _ptr(out["j_off"]), _ptr(out["Z"]),
+                                    _ptr(out["z_off"]), _ptr(out["info"]), _stream())
+        _abi.check(rc, "id_batched_noalloc")
+        return out
+    ws_bytes = lib.miid_batched_workspace(_h(), out["nblk"], dt)
+    ws = _WS.get("batched", ws_bytes, dev)
     rc = lib.id_batched(_h(), out["nblk"], _ptr(A), _ptr(out["a_off"]), _ptr(out["m"]), _ptr(out["n"]), dt,
                         ctypes.byref(opts), _ptr(out["J"]), _ptr(out["j_off"]), _ptr(out["Z"]),
                         _ptr(out["z_off"]), _ptr(out["info"]), _ptr(ws), ws_bytes, _stream())
@@ -458,12 +466,14 @@ def batched_raw(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, out: d
     return out
 
 
-def batched(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, hints: int = 0) -> BatchedResult:
+def batched(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, hints: int = 0,
+            noalloc: bool = False) -> BatchedResult:
     """Tolerance-mode IDs of many independent blocks in one launch: block b is
     m[b] x n[b] (column-major) at A[a_off[b]:]; its rank is the smallest k with
-    ||R22||_F <= eps ||A_b||_F, at most min(m_b, n_b, kmax)."""
+    ||R22||_F <= eps ||A_b||_F, at most min(m_b, n_b, kmax).  ``noalloc``: the
+    allocation-free entry point (id_batched_noalloc)."""
     import numpy as np
-    out = batched_raw(A, a_off, m, n, eps, kmax, hints=hints)
+    out = batched_raw(A, a_off, m, n, eps, kmax, hints=hints, noalloc=noalloc)
     raw = out["info"].cpu().numpy().tobytes()
     sz = ctypes.sizeof(_abi.MiidInfo)
     infos = [_abi.MiidInfo.from_buffer_copy(raw[i * sz:(i + 1) * sz]) for i in range(out["nblk"])]

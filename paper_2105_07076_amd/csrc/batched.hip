@@ -43,6 +43,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "common.hpp"
@@ -111,7 +112,8 @@ constexpr int b_glob_rows() {
 // first): a counting sort of one workgroup on the coarse key m n / 256 (1024
 // buckets cover every admissible block; the order inside a bucket is
 // whatever the LDS atomics give -- it only affects which workgroup takes a
-// block, not its result).  A block outside the limits gets its info here
+// block, not its result).  A block outside the limits, or one that needs more
+// scratch rows per lane than the rg each workgroup has, gets its info here
 // (k_out = 0, MIID_BLOCK_UNSUPPORTED) and is left out of the order; queue[1]
 // receives the number of admissible blocks, queue[0] the queue head (0).
 constexpr int kLptBuckets = 1024;
@@ -120,12 +122,47 @@ __device__ __forceinline__ bool block_ok(int m, int n) {
     return m >= 1 && n >= 1 && m <= kBMaxM && n <= kBMaxN && m <= n;
 }
 
+// How an admissible m x n block is spread over the workgroup: two columns
+// per lane when n > 512, else L lanes per column (as many as n L <= 512 and
+// the cap lmax allow); nq4 chunks of four rows per lane and column, nvc
+// chunks per lane in all.
+struct BShape {
+    bool c2;
+    int L, nq4, nvc;
+};
+__device__ __forceinline__ BShape b_shape(int m, int n, int lmax) {
+    BShape s;
+    s.c2 = n > kBThreads;
+    s.L = 1;
+    if (!s.c2) {
+        while (s.L < 8 && s.L < lmax && n * (2 * s.L) <= kBThreads) s.L *= 2;
+    }
+    s.nq4 = ((m + 3) / 4 + s.L - 1) / s.L;
+    s.nvc = (s.c2 ? 2 : 1) * s.nq4;
+    return s;
+}
+
+// Rows per lane of such a block that fit neither the registers nor the LDS
+// and go to the workgroup's scratch rows (at most b_glob_rows<T>()).
+template <typename T>
+__device__ __forceinline__ int b_block_glob_rows(int m, int n, int lmax) {
+    const BShape s = b_shape(m, n, lmax);
+    const int ncr = (s.c2 ? BCfg<T>::kRegRowsC2 : BCfg<T>::kRegRows) / 4;
+    const int chunks = s.nvc - ncr - b_lds_rows<T>() / 4;
+    return chunks > 0 ? 4 * chunks : 0;
+}
+
+template <typename T>
 __global__ void __launch_bounds__(1024) k_lpt_order(const int32_t* __restrict__ m, const int32_t* __restrict__ n,
-                                                    int32_t nblk, int32_t* __restrict__ order,
+                                                    int32_t nblk, int lmax, int rg, int32_t* __restrict__ order,
                                                     int32_t* __restrict__ queue, miid_info* __restrict__ info) {
     __shared__ int32_t cnt[kLptBuckets];
     __shared__ int32_t scan[kLptBuckets];
     const int tid = threadIdx.x;
+    auto admissible = [&](int i) {
+        const int mi = m[i], ni = n[i];
+        return block_ok(mi, ni) && b_block_glob_rows<T>(mi, ni, lmax) <= rg;
+    };
     auto bucket = [&](int i) {
         const int64_t sz = (int64_t)m[i] * (int64_t)n[i];
         return kLptBuckets - 1 - (int)min<int64_t>(sz >> 8, kLptBuckets - 1);  // larger first
@@ -133,7 +170,7 @@ __global__ void __launch_bounds__(1024) k_lpt_order(const int32_t* __restrict__ 
     for (int b = tid; b < kLptBuckets; b += blockDim.x) cnt[b] = 0;
     __syncthreads();
     for (int i = tid; i < nblk; i += blockDim.x) {
-        if (block_ok(m[i], n[i]))
+        if (admissible(i))
             atomicAdd(&cnt[bucket(i)], 1);
         else
             info[i] = miid_info{0, MIID_BLOCK_UNSUPPORTED, 0.0, 0.0, 0, 0};
@@ -156,7 +193,7 @@ __global__ void __launch_bounds__(1024) k_lpt_order(const int32_t* __restrict__ 
     }
     __syncthreads();
     for (int i = tid; i < nblk; i += blockDim.x)
-        if (block_ok(m[i], n[i])) order[atomicAdd(&cnt[bucket(i)], 1)] = i;
+        if (admissible(i)) order[atomicAdd(&cnt[bucket(i)], 1)] = i;
 }
 
 // a * b + c with one rounding, in the working precision
@@ -727,9 +764,8 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
                                                        T* __restrict__ Z, const int64_t* __restrict__ z_off,
                                                        miid_info* __restrict__ info,
                                                        const int32_t* __restrict__ order, int32_t* __restrict__ queue,
-                                                       T* __restrict__ Wscr) {
+                                                       T* __restrict__ Wscr, int rg) {
     constexpr int NCRMAX = BCfg<T>::kRegRows / 4;
-    constexpr int RGMAX = b_glob_rows<T>();
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* misc = smem + BLds<T>::kMiscOff;
     int32_t* s_sel = reinterpret_cast<int32_t*>(misc + BLds<T>::kOffSel);
@@ -740,7 +776,7 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
     G.lane = G.tid & (kWave - 1);
     G.wave = __builtin_amdgcn_readfirstlane(G.tid >> 6);
     const int tid = G.tid;
-    T* gsc = Wscr + (int64_t)blockIdx.x * RGMAX * kBThreads;  // this workgroup's global rows
+    T* gsc = Wscr + (int64_t)blockIdx.x * rg * kBThreads;  // this workgroup's rg scratch rows per lane
     const int nvalid = uni(queue[1]);
 
     for (;;) {
@@ -755,18 +791,16 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
         T* __restrict__ Zb = Z + z_off[b];
 
         // ---- geometry (uniform) ----------------------------------------
-        const bool c2 = n > kBThreads;  // two columns per lane
-        int L = 1;
-        if (!c2) {
-            while (L < 8 && L < lmax && n * (2 * L) <= kBThreads) L *= 2;
-        }
+        const BShape sh = b_shape(m, n, lmax);
+        const bool c2 = sh.c2;  // two columns per lane
+        const int L = sh.L;
         G.m = m;
         G.n = n;
         G.kb = kb;
         G.L = L;
         G.P = kBThreads / L;
-        G.nq4 = ((m + 3) / 4 + L - 1) / L;
-        G.nvc = (c2 ? 2 : 1) * G.nq4;
+        G.nq4 = sh.nq4;
+        G.nvc = sh.nvc;
         G.q = G.lane & (L - 1);
         G.gi = G.lane / L;
         const int lc = G.gi * kBWaves + G.wave;
@@ -885,6 +919,17 @@ __global__ void __launch_bounds__(kBThreads) k_batched(const T* __restrict__ A, 
 
 using namespace miid;
 
+// Scratch of the allocation-free entry point, one copy per GPU (each GPU the
+// library runs on holds it until the process ends): the queue order of at
+// most kNaMaxBlocks blocks, the queue head and count, then the scratch rows
+// of the workgroups.  Host code uses the address hipGetSymbolAddress gives
+// for the current device, never the array's name.
+constexpr size_t kNaBytes = size_t(64) << 20;
+constexpr int kNaMaxBlocks = 1 << 18;
+constexpr size_t kNaOffQueue = size_t(kNaMaxBlocks) * 4;
+constexpr size_t kNaOffRows = kNaOffQueue + 256;
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
 namespace {
 struct BPlan {
     int grid;
@@ -907,18 +952,12 @@ BPlan batched_plan(int32_t nblk, size_t esz) {
     P.total = off;
     return P;
 }
-}  // namespace
 
-extern "C" {
-
-static size_t batched_workspace_body(int32_t nblk, miid_dtype dtype) {
-    if (nblk < 1 || (dtype != MIID_F32 && dtype != MIID_F64)) return 0;
-    return batched_plan(nblk, dtype == MIID_F64 ? 8 : 4).total;
-}
-
-static int batched_body(int32_t nblk, const void* A, const int64_t* a_off, const int32_t* m, const int32_t* n,
-                        miid_dtype dtype, const miid_opts* opts, int32_t* J, const int64_t* j_off, void* Z,
-                        const int64_t* z_off, miid_info* info, void* ws, size_t ws_bytes, void* stream) {
+// The checks shared by id_batched and id_batched_noalloc (argument numbers
+// counted from nblk); returns 0 or the code.
+int batched_args(int32_t nblk, const void* A, const int64_t* a_off, const int32_t* m, const int32_t* n,
+                 miid_dtype dtype, const miid_opts* opts, int32_t* J, const int64_t* j_off, void* Z,
+                 const int64_t* z_off, miid_info* info) {
     if (nblk < 1) return -1;
     if (!A) return -2;
     if (!a_off) return -3;
@@ -931,11 +970,81 @@ static int batched_body(int32_t nblk, const void* A, const int64_t* a_off, const
     if (!Z) return -10;
     if (!z_off) return -11;
     if (!info) return -12;
+    return 0;
+}
+
+int lanes_cap(const miid_opts* opts) {
+    const int h = (int)((opts->flags >> MIID_HINT_LPC_SHIFT) & 15u);
+    return (h == 1 || h == 2 || h == 4 || h == 8) ? h : 8;
+}
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (with that device current) and kept.
+constexpr int kNaDevices = 64;
+std::mutex g_na_mu;
+void* g_na_ptr[kNaDevices] = {};
+
+int na_scratch(void** out) {
+    int dev = -1;
+    MIID_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaDevices) return MIID_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void* p = nullptr;
+        MIID_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_na_ptr[dev] = p;
+    }
+    *out = g_na_ptr[dev];
+    return 0;
+}
+
+// Scratch rows per lane each of `grid` workgroups gets from the static
+// scratch (a multiple of 4, at most what any admissible block needs).
+template <typename T>
+int na_rows(int grid) {
+    const size_t per = (size_t)grid * kBThreads * sizeof(T);
+    const size_t r = ((kNaBytes - kNaOffRows) / per) & ~size_t(3);
+    return (int)std::min<size_t>(r, (size_t)b_glob_rows<T>());
+}
+
+// The ordering kernel, then the persistent kernel on `grid` workgroups with
+// rg scratch rows per lane each at Wscr (order, queue and Wscr: device
+// memory of the caller's workspace or of the static scratch).
+template <typename T>
+int enqueue_batched(int32_t nblk, const T* A, const int64_t* a_off, const int32_t* m, const int32_t* n,
+                    const miid_opts* opts, int32_t* J, const int64_t* j_off, T* Z, const int64_t* z_off,
+                    miid_info* info, int32_t* order, int32_t* queue, T* Wscr, int grid, int rg, hipStream_t s) {
+    const int lmax = lanes_cap(opts);
+    hipLaunchKernelGGL(k_lpt_order<T>, dim3(1), dim3(1024), 0, s, m, n, nblk, lmax, rg, order, queue, info);
+    MIID_HIP(hipGetLastError());
+    MIID_HIP(lds_limit_once((const void*)k_batched<T>, kBLdsBytes));
+    const int pr = prof_take(MIID_K_BATCHED, 0, nblk, 0);
+    MIID_LAUNCH(pr, k_batched<T>, dim3(grid), dim3(kBThreads), (size_t)kBLdsBytes, s, A, a_off, m, n, opts->eps,
+                opts->kmax, lmax, J, j_off, Z, z_off, info, order, queue, Wscr, rg);
+    MIID_HIP(hipGetLastError());
+    return 0;
+}
+}  // namespace
+
+namespace miid {
+int batched_noalloc_setup() {
+    void* p = nullptr;
+    return na_scratch(&p);
+}
+}  // namespace miid
+
+extern "C" {
+
+static size_t batched_workspace_body(int32_t nblk, miid_dtype dtype) {
+    if (nblk < 1 || (dtype != MIID_F32 && dtype != MIID_F64)) return 0;
+    return batched_plan(nblk, dtype == MIID_F64 ? 8 : 4).total;
+}
+
+static int batched_body(int32_t nblk, const void* A, const int64_t* a_off, const int32_t* m, const int32_t* n,
+                        miid_dtype dtype, const miid_opts* opts, int32_t* J, const int64_t* j_off, void* Z,
+                        const int64_t* z_off, miid_info* info, void* ws, size_t ws_bytes, void* stream) {
+    if (const int rc = batched_args(nblk, A, a_off, m, n, dtype, opts, J, j_off, Z, z_off, info)) return rc;
     if (!ws) return -13;
-    const double eps = opts->eps;
-    const int32_t kmax = opts->kmax;
-    const int lpc_hint = (int)((opts->flags >> MIID_HINT_LPC_SHIFT) & 15u);
-    const int lmax = (lpc_hint == 1 || lpc_hint == 2 || lpc_hint == 4 || lpc_hint == 8) ? lpc_hint : 8;
     const size_t esz = dtype == MIID_F64 ? 8 : 4;
     const BPlan P = batched_plan(nblk, esz);
     if (ws_bytes < P.total) return MIID_E_WORKSPACE;
@@ -943,21 +1052,12 @@ static int batched_body(int32_t nblk, const void* A, const int64_t* a_off, const
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
     int32_t* order = reinterpret_cast<int32_t*>(w + P.oOrder);
     int32_t* queue = reinterpret_cast<int32_t*>(w + P.oQueue);
-    hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), 0, s, m, n, nblk, order, queue, info);
-    const int pr = prof_take(MIID_K_BATCHED, 0, nblk, 0);
-    if (dtype == MIID_F64) {
-        MIID_HIP(lds_limit_once((const void*)k_batched<double>, kBLdsBytes));
-        MIID_LAUNCH(pr, k_batched<double>, dim3(P.grid), dim3(kBThreads), (size_t)kBLdsBytes, s, (const double*)A,
-                    a_off, m, n, eps, kmax, lmax, J, j_off, (double*)Z, z_off, info, order, queue,
-                    reinterpret_cast<double*>(w + P.oW));
-    } else {
-        MIID_HIP(lds_limit_once((const void*)k_batched<float>, kBLdsBytes));
-        MIID_LAUNCH(pr, k_batched<float>, dim3(P.grid), dim3(kBThreads), (size_t)kBLdsBytes, s, (const float*)A,
-                    a_off, m, n, eps, kmax, lmax, J, j_off, (float*)Z, z_off, info, order, queue,
-                    reinterpret_cast<float*>(w + P.oW));
-    }
-    MIID_HIP(hipGetLastError());
-    return 0;
+    if (dtype == MIID_F64)
+        return enqueue_batched<double>(nblk, (const double*)A, a_off, m, n, opts, J, j_off, (double*)Z, z_off, info,
+                                       order, queue, reinterpret_cast<double*>(w + P.oW), P.grid,
+                                       b_glob_rows<double>(), s);
+    return enqueue_batched<float>(nblk, (const float*)A, a_off, m, n, opts, J, j_off, (float*)Z, z_off, info, order,
+                                  queue, reinterpret_cast<float*>(w + P.oW), P.grid, b_glob_rows<float>(), s);
 }
 
 // ---- entry points: the handle resolved, then the bodies above -----------
@@ -973,6 +1073,29 @@ int id_batched(miid_handle h, int32_t nblk, const void* A, const int64_t* a_off,
     if (resolve_opts(h, kTuneBatched, dtype, nblk, 0, opts ? opts->kmax : 0, opts, &o) != 0) return -1;
     return shift_arg(batched_body(nblk, A, a_off, m, n, dtype, opts ? &o : nullptr, J, j_off, Z, z_off, info, ws,
                                   ws_bytes, stream));
+}
+
+int id_batched_noalloc(miid_handle h, int32_t nblk, const void* A, const int64_t* a_off, const int32_t* m,
+                       const int32_t* n, miid_dtype dtype, const miid_opts* opts, int32_t* J, const int64_t* j_off,
+                       void* Z, const int64_t* z_off, miid_info* info, void* stream) {
+    miid_opts o;
+    if (resolve_opts(h, kTuneBatched, dtype, nblk, 0, opts ? opts->kmax : 0, opts, &o) != 0) return -1;
+    const miid_opts* op = opts ? &o : nullptr;
+    if (const int rc = batched_args(nblk, A, a_off, m, n, dtype, op, J, j_off, Z, z_off, info)) return shift_arg(rc);
+    if (nblk > kNaMaxBlocks) return MIID_E_UNSUPPORTED;
+    void* base = nullptr;
+    if (const int rc = na_scratch(&base)) return rc;
+    unsigned char* w = reinterpret_cast<unsigned char*>(base);
+    int32_t* order = reinterpret_cast<int32_t*>(w);
+    int32_t* queue = reinterpret_cast<int32_t*>(w + kNaOffQueue);
+    const int grid = std::max(1, std::min(nblk, dev_info().cus));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (dtype == MIID_F64)
+        return enqueue_batched<double>(nblk, (const double*)A, a_off, m, n, op, J, j_off, (double*)Z, z_off, info,
+                                       order, queue, reinterpret_cast<double*>(w + kNaOffRows), grid,
+                                       na_rows<double>(grid), s);
+    return enqueue_batched<float>(nblk, (const float*)A, a_off, m, n, op, J, j_off, (float*)Z, z_off, info, order,
+                                  queue, reinterpret_cast<float*>(w + kNaOffRows), grid, na_rows<float>(grid), s);
 }
 
 }  // extern "C"

@@ -150,6 +150,11 @@ int miid_create(miid_handle* out, const char* autotune_path) {
         if (!ok) return -2;
     }
     const DevInfo d = dev_info();  // fills the device record once
+    // the set-up of this device's allocation-free scratch (its address)
+    if (d.device >= 0) {
+        const int rc = batched_noalloc_setup();
+        if (rc != 0) return rc;
+    }
     miid_handle h = new (std::nothrow) miid_handle_s;
     if (!h) return MIID_E_UNSUPPORTED;
     h->device = d.device;

@@ -47,6 +47,10 @@ hipError_t lds_limit_once(const void* fn, int bytes);
 int resolve_opts(miid_handle h, int routine, miid_dtype dtype, int64_t m, int64_t n, int64_t k,
                  const miid_opts* in, miid_opts* out);
 
+// Looks up the current device's copy of the allocation-free entry point's
+// static scratch (once per device); 0 or a negative MIID code.
+int batched_noalloc_setup();
+
 // Checks only that the handle belongs to the current device (0 or -1).
 int check_handle(miid_handle h);
 
