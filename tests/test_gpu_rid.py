@@ -147,14 +147,17 @@ def test_rid_cfg2_full_size():
     assert abs(e_gpu - e_ora) <= 1e-5 * e_ora
 
 
-@pytest.mark.timeout(170)
+@pytest.mark.timeout(900)
 def test_rid_16384x65536_k512():
     """The large randomized workload: A 16384 x 65536 FP32 (s_i = exp(-i/128),
     4096 singular triplets, noise 1e-8), Omega 522 x 16384, k = 512, split
-    sketch.  Checked by properties that hold at this size: sampled sketch
-    entries against FP64 dot products; the CPQR stage against the oracle on
-    the GPU's own Y; the error on sampled columns between the spectrum's tail
-    (Eckart-Young) and a small multiple of it."""
+    sketch.  Sampled sketch entries against FP64 dot products; the CPQR stage
+    against the oracle on the GPU's own Y; end to end against the exact-sketch
+    oracle: Y64 = Omega A in FP64 built on the host in column chunks (the
+    oracle's randomized ID is the ID of that Y), pivots margin-aware at the
+    sketch's error level, and the error on 256 sampled columns within 1e-5
+    (relative) of the oracle's."""
+    import time
     miid = _miid()
     m, n, l, k = 16384, 65536, 522, 512
     A_t = idgen.lowrank_plus_noise_device(3, m, n, np.exp(-np.arange(4096) / 128.0), 1e-8, r=4096,
@@ -168,8 +171,8 @@ def test_rid_16384x65536_k512():
     g = idgen.rng(79)
     cols = np.sort(g.choice(n, 256, replace=False))
     Acols = A_t[:, torch.tensor(cols, device="cuda")].double().cpu().numpy()
-    Ys = Om.astype(np.float64) @ Acols
-    assert rel(Y[:, cols], Ys) <= SKETCH_TOL[1]
+    Om64 = Om.astype(np.float64)
+    assert rel(Y[:, cols], Om64 @ Acols) <= SKETCH_TOL[1]
     J = to_np(r.J)
     Z = to_np(r.Z).astype(np.float64)
     ref, ties = pivot_parity(Y, J, k, U32)
@@ -180,6 +183,24 @@ def test_rid_16384x65536_k512():
     err = np.linalg.norm(Acols - C @ Z[:, cols]) / np.linalg.norm(Acols)
     tail = np.exp(-k / 128.0)
     assert 0.5 * tail <= err <= 10.0 * tail, f"sampled relative error {err:.3e}, tail {tail:.3e}"
+    # the exact sketch: Omega's entries are bfloat16 and A's FP32, so each
+    # product is exact in FP64; numpy's product (pinned to oracle.matmul)
+    t0 = time.time()
+    Y64 = np.empty((l, n))
+    for c0 in range(0, n, 4096):
+        Y64[:, c0:c0 + 4096] = Om64 @ A_t[:, c0:c0 + 4096].double().cpu().numpy()
+    ora = oracle.id(Y64, k=k)
+    t1 = time.time()
+    # pivots: margin-aware against the exact sketch, at the split sketch's
+    # error level (its normwise bound stands in for the working precision)
+    _, ties64 = pivot_parity(Y64, J, k, SKETCH_TOL[1])
+    Co = A_t[:, torch.tensor(ora.J.astype(np.int64), device="cuda")].double().cpu().numpy()
+    e_ora = np.linalg.norm(Acols - Co @ ora.Z[:, cols]) / np.linalg.norm(Acols)
+    same = len(set(int(x) for x in J) & set(int(x) for x in ora.J))
+    print(f"\n[cfg3] sampled error gpu {err:.6e} oracle {e_ora:.6e} (rel diff {abs(err - e_ora) / e_ora:.2e}); "
+          f"{same}/{k} columns shared, {ties64} declared near-ties vs the exact sketch; host oracle "
+          f"{t1 - t0:.1f} s", flush=True)
+    assert abs(err - e_ora) <= 1e-5 * e_ora, f"sampled error {err:.6e} vs oracle {e_ora:.6e}"
 
 
 # --------------------------------------------------------------------------
