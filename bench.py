@@ -122,6 +122,157 @@ def gemv_roofline(recs, esz):
             "avg_algorithmic_bytes": int(byts / len(g))}
 
 
+# ---------------------------------------------------------------------------
+# The CPU-baseline leg: the oracle timed on the host, and the GPU results
+# checked against it (the only part of this script that runs the oracle).
+# ---------------------------------------------------------------------------
+def _pivot_report(ref, J, u):
+    """Pivots of a GPU result against the oracle's own on the same matrix:
+    identical, or the first step where they differ and whether the oracle's
+    margin there is within the declared near-tie bar 16 u / rho^2."""
+    import numpy as np
+    Jo = [int(x) for x in ref.J]
+    Jg = [int(x) for x in J]
+    first = next((j for j in range(min(len(Jg), len(Jo))) if Jg[j] != Jo[j]), None)
+    rep = {"identical": first is None and len(Jg) == len(Jo), "shared_columns": len(set(Jg) & set(Jo)),
+           "k": len(Jg)}
+    if first is not None:
+        mu, rho = float(ref.margins[first]), float(ref.rho[first])
+        rep["first_mismatch_step"] = first
+        rep["first_mismatch_near_tie"] = bool(mu <= 16.0 * u / (rho * rho))
+        rep["first_mismatch_margin"] = float(f"{mu:.3e}")
+    return rep
+
+
+def _t_rel(Z, Zo, J):
+    import numpy as np
+    mask = np.ones(Z.shape[1], dtype=bool)
+    mask[np.asarray(J)] = False
+    T, To = Z[:, mask], Zo[:, mask]
+    return (float(f"{np.linalg.norm(T - To) / np.linalg.norm(To):.3e}"),
+            float(f"{np.max(np.abs(T - To)) / np.max(np.abs(To)):.3e}"))
+
+
+def _id_checks(oracle, A_h, J, Z, ref, u):
+    """Pivot parity, T against the oracle's T for the GPU's pivots, the
+    error ||A - C Z||_F against the oracle's own, and max |Z|."""
+    import numpy as np
+    rep = _pivot_report(ref, J, u)
+    forced = ref if rep["identical"] else oracle.id(A_h, k=len(J), force=np.asarray(J, dtype=np.int32))
+    rep["T_rel_err"], rep["T_max_err_rel"] = _t_rel(Z, forced.Z, J)
+    a = np.linalg.norm(A_h)
+    e_gpu = oracle.error(A_h, np.asarray(J), Z) / a
+    e_ora = oracle.error(A_h, ref.J, ref.Z) / a
+    rep["err_rel"] = float(f"{e_gpu:.6e}")
+    rep["err_rel_oracle"] = float(f"{e_ora:.6e}")
+    rep["err_vs_oracle"] = float(f"{abs(e_gpu - e_ora) / e_ora:.3e}")
+    rep["max_abs_Z"] = float(f"{np.max(np.abs(Z)):.4f}")
+    return rep
+
+
+def cpu_baseline_leg(args, A64, out64, k, A32, out32, rid, big, bat):
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2105_07076_amd import api as miid_api
+    log("[bench] oracle on the host: the FP64 ID, all threads, median of 3")
+    A_host = np.asfortranarray(A64.cpu().numpy())
+    all_threads = oracle.threads()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        ref = oracle.id(A_host, k=k)
+        times.append((time.perf_counter() - t0) * 1000.0)
+    ms_all = float(np.median(times))
+    log(f"[bench] oracle {ms_all:.1f} ms on {all_threads} threads; one thread, 16 of 256 steps, median of 3")
+    oracle.set_threads(1)
+    t1s = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.id(A_host, k=16)
+        t1s.append((time.perf_counter() - t0) * 1000.0)
+    oracle.set_threads(all_threads)
+    ms_one = float(np.median(t1s)) * (k / 16)
+    J = out64["J"].cpu().numpy()
+    cpu = {"value": round(ms_all, 1), "unit": "ms per 4096x16384 k=256 FP64 ID", "cores": all_threads,
+           "kind": "oracle",
+           "sample": "the complete 4096x16384 k=256 FP64 ID of the same input, median of 3 (input generation and "
+                     "the host copy excluded): unblocked Householder CPQR with exact per-step column norms + back "
+                     "substitution, OpenMP over columns",
+           "single_thread": {"value": round(ms_one, 1), "cores": 1,
+                             "sample": "the first 16 of the 256 steps (with the initial norms and the back "
+                                       "substitution of that rank-16 ID), median of 3, scaled x16: the later "
+                                       "steps touch up to 6% fewer rows, so the figure overstates by a few %"},
+           "pivots_match_gpu": bool(np.array_equal(J, ref.J))}
+    log(f"[bench] oracle on one thread: {ms_one:.0f} ms per ID (scaled)")
+
+    checks = {}
+    Z64 = out64["Z"].cpu().numpy()[:k].astype(np.float64)
+    checks["id_fp64"] = _id_checks(oracle, A_host, J, Z64, ref, 2.0 ** -53)
+    if out32 is not None:
+        log("[bench] FP32 ID against the oracle")
+        A32_h = np.asfortranarray(A32.double().cpu().numpy())
+        ref32 = oracle.id(A32_h, k=k)
+        checks["id_fp32"] = _id_checks(oracle, A32_h, out32["J"].cpu().numpy(),
+                                       out32["Z"].cpu().numpy()[:k].astype(np.float64), ref32, 2.0 ** -24)
+    if rid is not None:
+        log("[bench] mixed RID against the exact-sketch oracle")
+        A32_h = np.asfortranarray(A32.double().cpu().numpy())
+        ora, Y64 = oracle.rid(A32_h, rid["Om"].astype(np.float64), k)
+        Jr = rid["out"]["J"].cpu().numpy()
+        Zr = rid["out"]["Z"].cpu().numpy()[:k].astype(np.float64)
+        rep = _pivot_report(ora, Jr, 3e-5)
+        forced = ora if rep["identical"] else oracle.id(Y64, k=k, force=Jr.astype(np.int32))
+        rep["T_rel_err"], rep["T_max_err_rel"] = _t_rel(Zr, forced.Z, Jr)
+        a = np.linalg.norm(A32_h)
+        e_gpu, e_ora = oracle.error(A32_h, Jr, Zr) / a, oracle.error(A32_h, ora.J, ora.Z) / a
+        rep.update({"err_rel": float(f"{e_gpu:.6e}"), "err_rel_oracle": float(f"{e_ora:.6e}"),
+                    "err_vs_oracle": float(f"{abs(e_gpu - e_ora) / e_ora:.3e}"),
+                    "max_abs_Z": float(f"{np.max(np.abs(Zr)):.4f}"),
+                    "note": "oracle = the ID of the exact FP64 sketch Omega A; u = 3e-5 (the split sketch's error)"})
+        checks["rid_mixed"] = rep
+    if big is not None:
+        log("[bench] large RID against the exact-sketch oracle (sampled columns)")
+        A3, k3 = big["A"], big["k"]
+        l3, n3 = big["Om"].shape[0], A3.shape[1]
+        Om64 = big["Om"].astype(np.float64)
+        Y64 = np.empty((l3, n3))
+        for c0 in range(0, n3, 4096):
+            Y64[:, c0:c0 + 4096] = Om64 @ A3[:, c0:c0 + 4096].double().cpu().numpy()
+        ora = oracle.id(Y64, k=k3)
+        J3 = big["out"]["J"].cpu().numpy()
+        Z3 = big["out"]["Z"].cpu().numpy()[:k3].astype(np.float64)
+        cols = np.sort(np.random.default_rng(79).choice(n3, 256, replace=False))
+        Ac = A3[:, torch.tensor(cols, device="cuda")].double().cpu().numpy()
+        C = A3[:, torch.tensor(J3.astype(np.int64), device="cuda")].double().cpu().numpy()
+        Co = A3[:, torch.tensor(ora.J.astype(np.int64), device="cuda")].double().cpu().numpy()
+        a = np.linalg.norm(Ac)
+        e_gpu = np.linalg.norm(Ac - C @ Z3[:, cols]) / a
+        e_ora = np.linalg.norm(Ac - Co @ ora.Z[:, cols]) / a
+        rep = _pivot_report(ora, J3, 3e-5)
+        rep.update({"err_rel_256_cols": float(f"{e_gpu:.6e}"), "err_rel_oracle_256_cols": float(f"{e_ora:.6e}"),
+                    "err_vs_oracle": float(f"{abs(e_gpu - e_ora) / e_ora:.3e}"),
+                    "max_abs_Z": float(f"{np.max(np.abs(Z3)):.4f}"),
+                    "note": "oracle = the ID of the exact FP64 sketch, built on the host in column chunks"})
+        checks["rid_16384x65536_k512"] = rep
+    if bat is not None:
+        log("[bench] batched blocks within eps (FP64 errors on the host)")
+        blocks = bat["blocks"]
+        res = miid_api.batched_result(bat["out"])
+        within = 0
+        for b in range(len(blocks.m)):
+            mb, nb_, o = int(blocks.m[b]), int(blocks.n[b]), int(blocks.a_off[b])
+            Ab = blocks.A[o:o + mb * nb_].astype(np.float32).astype(np.float64).reshape(nb_, mb).T
+            Jb, Zb = res.block(b)
+            a = np.linalg.norm(Ab)
+            e = np.linalg.norm(Ab - Ab[:, Jb] @ Zb.astype(np.float64))
+            within += int(e <= 1e-6 * a * (1 + 1e-6) + 64 * 2.0 ** -24 * a)
+        checks["batched_fp32"] = {"blocks": len(blocks.m), "within_eps": within, "eps": 1e-6,
+                                  "note": "||A_b - C_b Z_b||_F <= eps ||A_b||_F (+64 u ||A_b||), FP64 on the host"}
+    return cpu, checks
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,10 +284,10 @@ def main() -> int:
                     help="build the 4096 x 16384 input with the numpy recipe on the host (no device QR; "
                          "for counter-collection runs)")
     ap.add_argument("--only", default="all",
-                    help="comma list of sections to run: id64,id32,rid,ridsample,twosided,paper,batched,bwd (default all); "
-                         "the value is the FP64 ID, so id64 always runs")
+                    help="comma list of sections to run: id64,id32,rid,rid3,ridsample,twosided,paper,batched,bwd "
+                         "(default all); the value is the FP64 ID, so id64 always runs")
     args = ap.parse_args()
-    sections = {"id64", "id32", "rid", "ridsample", "twosided", "paper", "batched", "bwd"}
+    sections = {"id64", "id32", "rid", "rid3", "ridsample", "twosided", "paper", "batched", "bwd"}
     only = set(args.only.split(",")) if args.only != "all" else sections
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the ID hot path is built for a single MI355X "
@@ -166,6 +317,7 @@ def main() -> int:
     log(f"[bench] FP64 ID {ms64:.3f} ms; GEMV {roof['achieved'] if roof else None} GB/s")
 
     extra = {}
+    out32 = None
     A32 = A64.to(torch.float32)
     if "id32" in only:
         log("[bench] FP32 ID")
@@ -187,6 +339,7 @@ def main() -> int:
     if piv:
         extra["id_fp64_pivot_col_ms"] = round(sum(r.ms for r in piv) / len(piv), 5)
 
+    rid = None
     if "rid" in only:
         # randomized ID (bfloat16 sketch on the matrix cores + FP32 CPQR of Y)
         log("[bench] mixed RID (split bf16 sketch, l = k + 10)")
@@ -217,6 +370,7 @@ def main() -> int:
         if stp:
             extra["rid_cpqr_step_us"] = round(1000.0 * sum(r.ms for r in stp) / len(stp), 2)
         log(f"[bench] RID {ms_rid:.3f} ms")
+        rid = {"Om": idgen.omega_bf16(77, l, m), "out": out_r}
         # the same RID with Z = C^+ A over the full A (the paper's Z)
         out_l = miid_api.rid_raw(A32, Om, k=k, mode=1, lstsq=True)
         for _ in range(args.warmup):
@@ -229,6 +383,41 @@ def main() -> int:
         t1 = time.perf_counter()
         extra["rid_lstsq_ms"] = round((t1 - t0) * 1000.0 / args.steps, 4)
         log(f"[bench] RID with least-squares Z {extra['rid_lstsq_ms']:.3f} ms")
+
+    big = None
+    if "rid3" in only:
+        # the large randomized workload: A 16384 x 65536 FP32 (4096 singular
+        # triplets, s_i = exp(-i/128)), Omega 522 x 16384, k = 512, split sketch
+        m3, n3, l3, k3 = 16384, 65536, 522, 512
+        log(f"[bench] mixed RID {m3}x{n3}, l = {l3}, k = {k3}")
+        A3 = idgen.lowrank_plus_noise_device(3, m3, n3, np.exp(-np.arange(4096) / 128.0), 1e-8, r=4096,
+                                             dtype=torch.float32)
+        Om3_h = idgen.omega_bf16(78, l3, m3)
+        Om3 = torch.tensor(Om3_h, dtype=torch.bfloat16, device="cuda")
+        out3 = miid_api.rid_raw(A3, Om3, k=k3, mode=1)
+        for _ in range(args.warmup):
+            miid_api.rid_raw(A3, Om3, k=k3, mode=1, out=out3)
+        torch.cuda.synchronize()
+        lib.miid_prof_begin(1)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            miid_api.rid_raw(A3, Om3, k=k3, mode=1, out=out3)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        recs3 = prof_records(lib)
+        ms3 = (t1 - t0) * 1000.0 / args.steps
+        pre = "rid_16384x65536_k512"
+        extra[pre + "_ms"] = round(ms3, 4)
+        sk3 = [r for r in recs3 if r.kernel == 4]
+        if sk3:
+            sk_ms = sum(r.ms for r in sk3) / args.steps
+            flops = 2.0 * 2 * l3 * m3 * n3
+            extra[pre + "_sketch_ms"] = round(sk_ms, 4)
+            extra[pre + "_sketch_TFLOPs"] = round(flops / (sk_ms * 1e-3) / 1e12, 1)
+            extra[pre + "_sketch_frac_bf16_peak"] = round(flops / (sk_ms * 1e-3) / 2.5e15, 4)
+            extra[pre + "_cpqr_ms"] = round(ms3 - sk_ms, 4)
+        log(f"[bench] large RID {ms3:.3f} ms (sketch {extra.get(pre + '_sketch_ms')} ms)")
+        big = {"A": A3, "Om": Om3_h, "out": out3, "k": k3}
 
     if "ridsample" in only:
         # the paper's randomized ID by column sampling (p = k + 0.2 k), FP64,
@@ -301,6 +490,7 @@ def main() -> int:
             f"(graph replay {extra['paper_784x1000_k190_id_fp64_graph_ms']:.3f} ms), "
             f"sampled RID {extra['paper_784x1000_k190_rid_sample_fp64_ms']:.3f} ms")
 
+    bat = None
     if "batched" in only:
         # batched IDs: 4096 kernel-matrix blocks, tolerance 1e-6, FP32, one launch
         log("[bench] batched IDs (4096 blocks, eps = 1e-6)")
@@ -339,6 +529,37 @@ def main() -> int:
         extra["batched_graph_ms"] = round((t1 - t0) * 1000.0 / args.steps, 4)
         log(f"[bench] batched {ms_b:.3f} ms = {extra['batched_ids_per_s']:.0f} IDs/s "
             f"(graph replay {extra['batched_graph_ms']} ms)")
+        # the same blocks in FP64, batched, and block by block through the
+        # single-matrix entry point (id_cpqr, tolerance mode, FP64): the
+        # batched form's speedup
+        Ab64 = torch.tensor(blocks.A, dtype=torch.float64, device="cuda")
+        out_b64 = miid_api.batched_raw(Ab64, blocks.a_off, blocks.m, blocks.n, 1e-6, 64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            miid_api.batched_raw(Ab64, blocks.a_off, blocks.m, blocks.n, 1e-6, 64, out=out_b64)
+        torch.cuda.synchronize()
+        ms_b64 = (time.perf_counter() - t0) * 1000.0 / args.steps
+        extra["batched_fp64_ms"] = round(ms_b64, 4)
+        views = []
+        for b in range(len(blocks.m)):
+            mb, nb_, o = int(blocks.m[b]), int(blocks.n[b]), int(blocks.a_off[b])
+            views.append(Ab64[o:o + mb * nb_].view(nb_, mb).t())
+        # one untimed pass allocates every block's outputs; the timed pass
+        # reuses them
+        outs = [miid_api.id_raw(v, eps=1e-6, kmax=min(64, v.shape[0])) for v in views]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for v, o in zip(views, outs):
+            miid_api.id_raw(v, eps=1e-6, kmax=min(64, v.shape[0]), out=o)
+        torch.cuda.synchronize()
+        ms_one = (time.perf_counter() - t0) * 1000.0
+        del outs
+        extra["batched_blockwise_id_cpqr_fp64_ms"] = round(ms_one, 2)
+        extra["batched_speedup_vs_blockwise_fp64"] = round(ms_one / ms_b64, 1)
+        extra["batched_fp32_speedup_vs_blockwise_fp64"] = round(ms_one / ms_b, 1)
+        log(f"[bench] batched FP64 {ms_b64:.3f} ms; block by block (id_cpqr FP64) {ms_one:.1f} ms")
+        bat = {"blocks": blocks, "out": out_b}
 
     if "bwd" in only:
         # differentiable ID: forward (FP32 ID, k = 128) + adjoint on 2048 x 8192
@@ -374,21 +595,9 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        log("[bench] oracle on the host (one full FP64 ID)")
-        A_host = A64.cpu().numpy()
-        t0 = time.perf_counter()
-        ref = oracle.id(A_host, k=k)
-        t1 = time.perf_counter()
-        cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
-        J = out64["J"].cpu().numpy()
-        cpu = {"value": round((t1 - t0) * 1000.0, 1), "unit": "ms per 4096x16384 k=256 FP64 ID", "cores": cores,
-               "kind": "oracle",
-               "sample": "one complete 4096x16384 k=256 FP64 ID of the same input (input generation and the "
-                         "host copy excluded): unblocked Householder CPQR with exact per-step column norms + "
-                         "back substitution, OpenMP over columns",
-               "pivots_match_gpu": bool(np.array_equal(J, ref.J))}
-        log(f"[bench] oracle {cpu['value']} ms on {cores} threads")
+        cpu, checks = cpu_baseline_leg(args, A64, out64, k, A32, out32 if "id32" in only else None,
+                                       rid if "rid" in only else None, big, bat)
+        extra["vs_oracle"] = checks
 
     rec = {
         "metric": METRIC,

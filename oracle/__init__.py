@@ -60,6 +60,10 @@ def _load():
                                   P, ctypes.c_int, P, P, P, P, P, P, P]
         lib.oracle_matmul.restype = None
         lib.oracle_matmul.argtypes = [P, I64, P, I64, P, I64, I64, I64, I64]
+        lib.oracle_set_threads.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = []
         _lib = lib
     return _lib
 
@@ -157,6 +161,17 @@ def _id_of(W: np.ndarray, transposed: bool, k, eps, kmax, force) -> IDResult:
     return IDResult(J=J[:kout].copy(), Z=np.asfortranarray(Z[:kout]), R=np.asfortranarray(R[:kout]), k=kout,
                     transposed=transposed, nu1=nu1, nu2=nu2, nuo=nuo, resid=resid,
                     a_norm=float(np.linalg.norm(W)))
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (for timing; results do not
+    depend on it)."""
+    _load().oracle_set_threads(int(n))
+
+
+def threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(_load().oracle_threads())
 
 
 def matmul(X: np.ndarray, Y: np.ndarray) -> np.ndarray:

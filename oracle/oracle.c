@@ -242,3 +242,11 @@ void oracle_matmul(const double *A, int64_t lda, const double *B, int64_t ldb, d
         }
     }
 }
+
+/*
+ * Thread count of the OpenMP loops above (timing only: the results do not
+ * depend on it, every parallel loop writes disjoint columns).
+ */
+#include <omp.h>
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_threads(void) { return omp_get_max_threads(); }

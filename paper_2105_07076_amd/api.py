@@ -472,8 +472,13 @@ def batched(A: torch.Tensor, a_off, m, n, eps: float, kmax: int = 64, hints: int
     m[b] x n[b] (column-major) at A[a_off[b]:]; its rank is the smallest k with
     ||R22||_F <= eps ||A_b||_F, at most min(m_b, n_b, kmax).  ``noalloc``: the
     allocation-free entry point (id_batched_noalloc)."""
-    import numpy as np
     out = batched_raw(A, a_off, m, n, eps, kmax, hints=hints, noalloc=noalloc)
+    return batched_result(out)
+
+
+def batched_result(out: dict) -> BatchedResult:
+    """The BatchedResult of a finished batched_raw call (reads info)."""
+    import numpy as np
     raw = out["info"].cpu().numpy().tobytes()
     sz = ctypes.sizeof(_abi.MiidInfo)
     infos = [_abi.MiidInfo.from_buffer_copy(raw[i * sz:(i + 1) * sz]) for i in range(out["nblk"])]
