@@ -371,6 +371,14 @@ def main() -> int:
             extra["rid_cpqr_step_us"] = round(1000.0 * sum(r.ms for r in stp) / len(stp), 2)
         log(f"[bench] RID {ms_rid:.3f} ms")
         rid = {"Om": idgen.omega_bf16(77, l, m), "out": out_r}
+        # the same RID with the three-part split of A (mode 2)
+        out_r2 = miid_api.rid_raw(A32, Om, k=k, mode=2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            miid_api.rid_raw(A32, Om, k=k, mode=2, out=out_r2)
+        torch.cuda.synchronize()
+        extra["rid_mixed_mode2_ms"] = round((time.perf_counter() - t0) * 1000.0 / args.steps, 4)
         # the same RID with Z = C^+ A over the full A (the paper's Z)
         out_l = miid_api.rid_raw(A32, Om, k=k, mode=1, lstsq=True)
         for _ in range(args.warmup):

@@ -207,9 +207,12 @@ int id_cpqr(miid_handle h, const void *A, int64_t m, int64_t n, int64_t lda, mii
  *
  *  A      (2)  m x n FP32, lda >= m, m <= n (else MIID_E_UNSUPPORTED)
  *  Omega  (6)  l x m bfloat16 bit patterns, column-major, ldo >= l
- *  mode   (9)  0: A rounded once to bfloat16 (one matrix-core pass);
- *              1: A split as hi + lo, both bfloat16 (two passes, error
- *                 ~ 2^-16 relative in Y)
+ *  mode   (9)  0: A rounded once to bfloat16 (one matrix-core pass,
+ *                 |a - hi| <= 2^-8 |a|);
+ *              1: A split as hi + mid, both bfloat16 (two passes,
+ *                 |a - hi - mid| <= 2^-16 |a|);
+ *              2: A split as hi + mid + lo (three passes, 2^-24 |a|: the
+ *                 sketch as accurate as FP32 accumulation allows)
  *  J, Z, C, R11, info: as in id_cpqr with dtype FP32; Z is kmax x n
  *  Y      (16) nullable, l x n FP32, ldy >= l: the sketch
  * With MIID_LSTSQ_Z in opts.flags (fixed rank, k <= m) Z is instead the
@@ -219,7 +222,8 @@ int id_cpqr(miid_handle h, const void *A, int64_t m, int64_t n, int64_t lda, mii
  * Cholesky factor of C^T C (computed in FP64, R11^T R11 = C^T C, positive
  * diagonal) and Z solves R11^T R11 Z = C^T A with Z[:, J] = I.  info still
  * describes the CPQR of Y, plus MIID_LSTSQ_BREAKDOWN.
- * Limits: k <= l <= min(n, 1024) (kmax <= l in tolerance mode), m <= n.
+ * Limits: k <= l <= min(n, 1024) (kmax <= l in tolerance mode), m <= n,
+ * lda <= 2^23.
  * ---------------------------------------------------------------------- */
 size_t miid_rid_workspace(miid_handle h, int64_t m, int64_t n, int32_t l, const miid_opts *opts);
 int rid_sketch_cpqr(miid_handle h, const float *A, int64_t m, int64_t n, int64_t lda,

@@ -384,11 +384,12 @@ def rid(A: torch.Tensor, omega: torch.Tensor, k: int | None = None, eps: float |
     Y = omega A computed on the matrix cores.
 
     ``omega`` is an l x m bfloat16 tensor (the random numbers the method
-    draws are an input).  ``mode`` 1 splits A as hi + lo bfloat16 (two
-    passes), 0 rounds it once.  J and T come from the CPQR of Y; C = A[:, J].
+    draws are an input).  ``mode`` 1 splits A as hi + mid bfloat16 (two
+    passes, 2^-16 relative per entry), 2 as hi + mid + lo (three passes,
+    2^-24), 0 rounds it once.  J and T come from the CPQR of Y; C = A[:, J].
     With ``lstsq`` (fixed rank) Z is instead C^+ A over the full A, the
-    paper's way of forming the randomized ID's Z: J is then the sketch's
-    skeleton reordered by the pivoted QR of C, and R11 is that QR's factor.
+    paper's way of forming the randomized ID's Z, for the same J: R11 is then
+    the Cholesky factor of C^T C.
     ``a_norm``/``r22_norm`` in the result refer to Y."""
     out = rid_raw(A, omega, k=k, eps=eps, kmax=kmax, mode=mode, nb=nb, refine=refine, want_C=want_C,
                   want_Y=want_Y, want_R11=want_R11, hints=hints, lstsq=lstsq)

@@ -7,10 +7,12 @@
 // Gaussian Omega; the CPQR of Y (the driver shared with id_cpqr, FP32 with
 // FP64 norms and an FP64 triangular solve) gives J and T, and C = A[:, J].
 //
-// The sketch runs on the matrix cores: v_mfma_f32_16x16x32_bf16, Omega exact
-// in bfloat16, A rounded to bfloat16 once (mode 0) or split as hi + lo with
-// hi = bf16(a), lo = bf16(a - hi) (mode 1, two passes, relative error of Y
-// about 2^-16), FP32 accumulation.
+// The sketch runs on the matrix cores: v_mfma_f32_32x32x16_bf16, Omega exact
+// in bfloat16, A rounded to bfloat16 once (mode 0), split as hi + mid with
+// hi = bf16(a), mid = bf16(a - hi) (mode 1, two passes: |a - hi - mid| <=
+// 2^-16 |a|, bfloat16's unit roundoff being 2^-8), or as hi + mid + lo
+// (mode 2, three passes: 2^-24 |a|, FP32's own rounding), FP32 accumulation;
+// the differences a - hi and a - hi - mid are exact in FP32.
 #include <algorithm>
 
 #include "common.hpp"
@@ -21,12 +23,9 @@
 namespace miid {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef float f4v_t __attribute__((ext_vector_type(4)));
+typedef float f16v_t __attribute__((ext_vector_type(16)));
 
-constexpr int kSkThreads = 256;
-constexpr int kSkCols = 64;   // columns of A (and Y) per workgroup, 16 per wave
-constexpr int kSkK = 32;      // K per MFMA
-constexpr int kSkLdsRow = kSkK + 8;  // bf16 per LDS row (padding against bank conflicts)
+constexpr int kSkK = 16;  // K of one v_mfma_f32_32x32x16_bf16
 
 // Omega (l x m, column-major, bf16 bits) -> Wt (lpad x mpad, k contiguous),
 // zero padded.
@@ -49,177 +48,314 @@ __global__ void k_omega_t(const uint16_t* __restrict__ Om, int l, int64_t m, int
     }
 }
 
-// Y tile (16 * mtb rows starting at tile mt0, 64 columns) = Omega A.
-// D = A_tile^T Omega_tile^T so that one accumulator element of 16
-// neighbouring lanes is 16 consecutive rows of one column of Y.
-// Operand layout (measured on gfx950): lane l holds row l % 16 and
-// k = 8 (l / 16) + e of the A operand, k = 8 (l / 16) + e and column l % 16
-// of the B operand; output element r of lane l is row 4 (l / 16) + r,
-// column l % 16.
-// K advances in chunks of KC (KC / 32 MFMA steps): the Omega chunk
-// (16 MTB rows x KC) is double-buffered in LDS and the next chunk's Omega
-// and A loads are in flight while the current chunk is multiplied, so there
-// is one barrier per chunk.
-template <bool SPLIT, bool VEC, int MTB, int KC>
-__global__ void __launch_bounds__(kSkThreads) k_sketch(const float* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                                                       const uint16_t* __restrict__ Wt, int64_t mpad, int mt_total,
-                                                       float* __restrict__ S, int64_t ldw, float* __restrict__ Yout,
-                                                       int64_t ldy, int l) {
-    constexpr int LR = KC + 8;             // bf16 per LDS row (padding against bank conflicts)
-    constexpr int KS = KC / kSkK;          // MFMA steps per chunk
-    constexpr int ROWS = MTB * 16;
-    constexpr int SEG = KC / 8;            // 16-byte segments of a row of the chunk
-    constexpr int NSEG = ROWS * SEG;
-    constexpr int SPT = (NSEG + kSkThreads - 1) / kSkThreads;  // segments staged per thread
+// Y = Omega A on the matrix cores, 32 x 32 tiles of Y (v_mfma_f32_32x32x16_bf16:
+// 32 x 16 by 16 x 32, FP32 accumulation).  A workgroup of WR x WC waves owns
+// 32 WC columns of Y and every row tile: wave (wr, wc) accumulates row tiles
+// RT wr .. RT wr + RT - 1 of the 32 columns starting at 32 wc.  Operand
+// layout of the instruction: lane l holds row l % 32 and k = 8 (l / 32) + e
+// (e < 8) of the Omega operand, and k = 8 (l / 32) + e of column l % 32 of the
+// A operand; accumulator element r of lane l is row 8 (r / 4) + 4 (l / 32) +
+// r % 4, column l % 32.
+//
+// K runs in chunks of 32.  A chunk's Omega rows (64 bytes each) and A
+// columns (128 bytes each) go straight from memory into an NS-stage ring in
+// LDS (global_load_lds / buffer_load ... lds, 1 KiB per wave instruction, no
+// registers), NS - 1 chunks ahead of the one being multiplied; each wave
+// waits only for its own copies of the current chunk (an exact count of
+// outstanding loads) before the one barrier per chunk.  Within a row or a
+// column the 16-byte segments are stored XOR-permuted, so that the lanes that
+// read the same segment of consecutive rows or columns hit different banks.
+// A is read through a buffer resource based at the workgroup's first column
+// (loads past its last element return zero); the last chunk, when m is not a
+// multiple of 32, is copied through registers with the rows >= m zeroed.
+// A is split into NSPLIT bfloat16 parts (1: hi = bf16(a); 2: hi + mid with
+// mid = bf16(a - hi); 3: hi + mid + lo with lo = bf16(a - hi - mid)), one
+// product per part and Omega operand.  Rows lpad .. ldw - 1 of S are written
+// as zeros.
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+constexpr int kSkKC = 32;  // K per chunk
+constexpr int64_t kSkMaxLda = (int64_t)1 << 23;  // 128 columns of A within 32-bit byte offsets
+
+// segment permutations (Omega rows: 4 segments, A columns: 8)
+__device__ __forceinline__ int om_swz(int row) { return ((row >> 1) ^ (row >> 3)) & 3; }
+__device__ __forceinline__ int a_swz(int col) { return (col ^ (col >> 3)) & 7; }
+
+// wait until at most N vector-memory operations of this wave are outstanding
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
+
+// Workgroup barrier after this wave's LDS writes are done.  Written as one
+// asm statement: the compiler's own barrier would also wait for every
+// outstanding copy into LDS (later chunks included).
+__device__ __forceinline__ void ring_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
+// The LDS reads of one MFMA step: RT Omega tiles at aw + 2048 t and the two
+// A segments at aa0, aa1 (LDS byte addresses), issued together and waited
+// for in the same asm statement.
+template <int RT>
+struct StepReads;
+#define MIID_SK_RD(i) "ds_read_b128 %" #i ", %[aw] offset:" #i "*2048\n\t"
+template <>
+struct StepReads<5> {
+    __device__ __forceinline__ static void run(uint32_t aw, uint32_t aa0, uint32_t aa1, v4i_t (&w)[5], v4i_t& a0,
+                                               v4i_t& a1) {
+        asm volatile(MIID_SK_RD(0) MIID_SK_RD(1) MIID_SK_RD(2) MIID_SK_RD(3) MIID_SK_RD(4)
+                     "ds_read_b128 %[a0], %[aa0]\n\tds_read_b128 %[a1], %[aa1]\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2]), "=&v"(w[3]), "=&v"(w[4]), [a0] "=&v"(a0),
+                       [a1] "=&v"(a1)
+                     : [aw] "v"(aw), [aa0] "v"(aa0), [aa1] "v"(aa1)
+                     : "memory");
+    }
+};
+template <>
+struct StepReads<8> {
+    __device__ __forceinline__ static void run(uint32_t aw, uint32_t aa0, uint32_t aa1, v4i_t (&w)[8], v4i_t& a0,
+                                               v4i_t& a1) {
+        asm volatile(MIID_SK_RD(0) MIID_SK_RD(1) MIID_SK_RD(2) MIID_SK_RD(3) MIID_SK_RD(4) MIID_SK_RD(5)
+                         MIID_SK_RD(6) MIID_SK_RD(7)
+                     "ds_read_b128 %[a0], %[aa0]\n\tds_read_b128 %[a1], %[aa1]\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2]), "=&v"(w[3]), "=&v"(w[4]), "=&v"(w[5]), "=&v"(w[6]),
+                       "=&v"(w[7]), [a0] "=&v"(a0), [a1] "=&v"(a1)
+                     : [aw] "v"(aw), [aa0] "v"(aa0), [aa1] "v"(aa1)
+                     : "memory");
+    }
+};
+template <>
+struct StepReads<9> {
+    __device__ __forceinline__ static void run(uint32_t aw, uint32_t aa0, uint32_t aa1, v4i_t (&w)[9], v4i_t& a0,
+                                               v4i_t& a1) {
+        asm volatile(MIID_SK_RD(0) MIID_SK_RD(1) MIID_SK_RD(2) MIID_SK_RD(3) MIID_SK_RD(4) MIID_SK_RD(5)
+                         MIID_SK_RD(6) MIID_SK_RD(7) MIID_SK_RD(8)
+                     "ds_read_b128 %[a0], %[aa0]\n\tds_read_b128 %[a1], %[aa1]\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2]), "=&v"(w[3]), "=&v"(w[4]), "=&v"(w[5]), "=&v"(w[6]),
+                       "=&v"(w[7]), "=&v"(w[8]), [a0] "=&v"(a0), [a1] "=&v"(a1)
+                     : [aw] "v"(aw), [aa0] "v"(aa0), [aa1] "v"(aa1)
+                     : "memory");
+    }
+};
+#undef MIID_SK_RD
+
+template <int NSPLIT, int RT, int WR, int WC, int NS>
+__global__ void __launch_bounds__(64 * WR * WC) k_sketch(const float* __restrict__ A, int64_t lda, int64_t m,
+                                                         int64_t n, const uint16_t* __restrict__ Wt, int64_t mpad,
+                                                         int rt_total, float* __restrict__ S, int64_t ldw,
+                                                         float* __restrict__ Yout, int64_t ldy, int l) {
+    constexpr int NW = WR * WC;
+    constexpr int ROWS = WR * RT * 32;     // Omega rows of the workgroup
+    constexpr int COLS = 32 * WC;          // columns of the workgroup
+    constexpr int OM_BYTES = ROWS * 64;    // Omega chunk: ROWS x 32 bf16
+    constexpr int A_BYTES = COLS * 128;    // A chunk: COLS x 32 floats
+    constexpr int STAGE = OM_BYTES + A_BYTES;
+    constexpr int OM_INS = OM_BYTES / 1024, A_INS = A_BYTES / 1024, INS = OM_INS + A_INS;
+    constexpr int BASE = INS / NW, REM = INS % NW;  // copy instructions per wave and stage
+    constexpr int KS = kSkKC / kSkK;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    uint16_t* sW = reinterpret_cast<uint16_t*>(smem_raw);  // [2][ROWS][LR]
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
-    const int mt0 = blockIdx.y * MTB;
-    const int mtb = min(MTB, mt_total - mt0);
-    const int64_t col = (int64_t)blockIdx.x * kSkCols + wave * 16 + lane % 16;  // this lane's A column
-    const int kl = 8 * (lane / 16);                                            // this lane's k offset
-    const bool colok = col < n;
-    const float* ac = A + (colok ? col : 0) * lda;
+    const int wr = wave % WR, wc = wave / WR;
+    const int rt0 = wr * RT;
+    const int nrt = min(RT, rt_total - rt0);  // this wave's row tiles (may be <= 0)
+    const int rows_st = rt_total * 32;        // rows of Wt
+    const int64_t col0 = (int64_t)blockIdx.x * COLS;
+    const int ncv = (int)min<int64_t>(COLS, n - col0);
+    const uint32_t arec = (uint32_t)min<int64_t>(((int64_t)(ncv - 1) * lda + m) * 4, (int64_t)0x7FFFFFF0);
+    const __amdgpu_buffer_rsrc_t rsA =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(A + col0 * lda), (short)0, (int)arec, 0x00020000);
+    const int nfull = (int)(m / kSkKC);       // chunks with every row < m
+    const int nch = (int)(mpad / kSkKC);      // all chunks (mpad = m rounded up to 32)
 
-    f4v_t acc[MTB];
-#pragma unroll
-    for (int t = 0; t < MTB; ++t) acc[t] = f4v_t{0.f, 0.f, 0.f, 0.f};
-
-    uint4 stg[SPT];
-    auto load_w = [&](int64_t k0) {
-#pragma unroll
-        for (int i = 0; i < SPT; ++i) {
-            const int seg = tid + kSkThreads * i;
-            const int row = seg / SEG, sg = seg % SEG;
-            const int64_t kk = k0 + 8 * sg;
-            stg[i] = (seg < NSEG && row < 16 * mtb && kk < mpad)
-                         ? *reinterpret_cast<const uint4*>(Wt + (int64_t)(mt0 * 16 + row) * mpad + kk)
-                         : make_uint4(0u, 0u, 0u, 0u);
-        }
-    };
-    auto store_w = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < SPT; ++i) {
-            const int seg = tid + kSkThreads * i;
-            const int row = seg / SEG, sg = seg % SEG;
-            if (seg < NSEG) *reinterpret_cast<uint4*>(sW + (buf * ROWS + row) * LR + 8 * sg) = stg[i];
-        }
-    };
-    auto load_a = [&](int64_t k0, float (&x)[KS][8]) {
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int64_t kb = k0 + kSkK * ks + kl;
-            if (VEC && colok && kb + 8 <= m) {
-                const float4 v0 = *reinterpret_cast<const float4*>(ac + kb);
-                const float4 v1 = *reinterpret_cast<const float4*>(ac + kb + 4);
-                x[ks][0] = v0.x; x[ks][1] = v0.y; x[ks][2] = v0.z; x[ks][3] = v0.w;
-                x[ks][4] = v1.x; x[ks][5] = v1.y; x[ks][6] = v1.z; x[ks][7] = v1.w;
+    // stage c of the ring: Omega rows and A columns of chunk c
+    auto issue = [&](int c) {
+        unsigned char* sb = smem_raw + (c % NS) * STAGE;
+        const int64_t k0 = (int64_t)c * kSkKC;
+        const bool tail = c >= nfull;
+        for (int ins = wave; ins < INS; ins += NW) {
+            if (ins < OM_INS) {
+                const int row = 16 * ins + lane / 4;
+                const int q = (lane % 4) ^ om_swz(row);
+                const int srow = row < rows_st ? row : 0;  // rows past Wt: any valid row (never read)
+                __builtin_amdgcn_global_load_lds((const void*)(Wt + (int64_t)srow * mpad + k0 + 8 * q),
+                                                 (lds_void_t*)(sb + ins * 1024), 16, 0, 0);
             } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) x[ks][e] = (colok && kb + e < m) ? ac[kb + e] : 0.f;
-            }
-        }
-    };
-
-    float xa[KS][8], xn[KS][8];
-    load_w(0);
-    load_a(0, xa);
-    store_w(0);
-    __syncthreads();
-    int cur = 0;
-    for (int64_t k0 = 0; k0 < mpad; k0 += KC) {
-        const bool more = k0 + KC < mpad;
-        if (more) {
-            load_w(k0 + KC);
-            load_a(k0 + KC, xn);
-        }
-        const uint16_t* wb = sW + cur * ROWS * LR;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            bf16x8_t hi, lo;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const __bf16 h = (__bf16)xa[ks][e];
-                hi[e] = h;
-                if (SPLIT) lo[e] = (__bf16)(xa[ks][e] - (float)h);
-            }
-#pragma unroll
-            for (int t = 0; t < MTB; ++t) {
-                if (t < mtb) {
-                    const bf16x8_t w =
-                        *reinterpret_cast<const bf16x8_t*>(wb + (t * 16 + lane % 16) * LR + kSkK * ks + kl);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, w, acc[t], 0, 0, 0);
-                    if (SPLIT) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, w, acc[t], 0, 0, 0);
+                const int ia = ins - OM_INS;
+                const int c_ = 8 * ia + lane / 8;
+                const int q = (lane % 8) ^ a_swz(c_);
+                const uint32_t voff = (uint32_t)(((int64_t)c_ * lda + k0 + 4 * q) * 4);
+                if (!tail) {
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsA, (lds_void_t*)(sb + OM_BYTES + ia * 1024), 16,
+                                                             voff, 0, 0, 0);
+                } else {
+                    // the last chunk: rows >= m (the caller's padding or the
+                    // next column) are zeroed
+                    float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsA, voff, 0, 0));
+                    const int64_t kr = k0 + 4 * q;
+                    if (kr + 0 >= m) v.x = 0.f;
+                    if (kr + 1 >= m) v.y = 0.f;
+                    if (kr + 2 >= m) v.z = 0.f;
+                    if (kr + 3 >= m) v.w = 0.f;
+                    *reinterpret_cast<float4*>(sb + OM_BYTES + ia * 1024 + lane * 16) = v;
                 }
             }
         }
-        if (more) {
-            store_w(cur ^ 1);
+    };
+
+    f16v_t acc[RT];
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
-                for (int e = 0; e < 8; ++e) xa[ks][e] = xn[ks][e];
+        for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+
+    const int cl = wc * 32 + lane % 32;  // this lane's A column within the workgroup
+    const int ga = a_swz(cl);
+    const int h = lane / 32;
+    // LDS byte addresses: the ring, this lane's first Omega row (tile t is
+    // 2048 t further; every tile's rows share the row's segment permutation)
+    // and this lane's A column
+    const uint32_t lds0 = (uint32_t)(uintptr_t)(lds_void_t*)smem_raw;
+    const int row0 = rt0 * 32 + lane % 32;
+    const uint32_t woff = (uint32_t)(row0 * 64);
+    const int sw = om_swz(row0);
+    const uint32_t aoff = (uint32_t)(OM_BYTES + cl * 128);
+#pragma unroll
+    for (int c = 0; c < NS - 1; ++c)
+        if (c < nch) issue(c);
+    for (int c = 0; c < nch; ++c) {
+        // this wave's copies of chunk c are done once only those of the
+        // NS - 2 later (full) chunks can be outstanding
+        if (NS > 2 && c + NS - 2 < nfull) {
+            if (REM != 0 && wave < REM)
+                wait_vm<(BASE + 1) * (NS > 2 ? NS - 2 : 0)>();
+            else
+                wait_vm<BASE * (NS > 2 ? NS - 2 : 0)>();
+        } else {
+            wait_vm<0>();
         }
-        __syncthreads();
-        cur ^= 1;
+        ring_barrier();  // everyone's copies of chunk c are in LDS; chunk c - 1's buffer is free
+        if (c + NS - 1 < nch) issue(c + NS - 1);
+        const uint32_t sb = lds0 + (uint32_t)((c % NS) * STAGE);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int q0 = 4 * ks + 2 * h;
+            v4i_t wv[RT], av0, av1;
+            StepReads<RT>::run(sb + woff + 16 * ((2 * ks + h) ^ sw), sb + aoff + 16 * (q0 ^ ga),
+                               sb + aoff + 16 * ((q0 + 1) ^ ga), wv, av0, av1);
+            const float4 a0 = __builtin_bit_cast(float4, av0);
+            const float4 a1 = __builtin_bit_cast(float4, av1);
+            const float x[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+            // a = hi + mid + lo: each part the bfloat16 rounding of what the
+            // earlier parts leave (exact differences in FP32)
+            bf16x8_t hi, mid, lo;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const __bf16 hh = (__bf16)x[e];
+                hi[e] = hh;
+                const float r1 = x[e] - (float)hh;
+                const __bf16 mm = (__bf16)r1;
+                mid[e] = mm;
+                lo[e] = (__bf16)(r1 - (float)mm);
+            }
+            // the hi products of every tile, then the lo products: a tile's
+            // second product comes RT instructions after its first (back to
+            // back they would wait for each other).  Tiles past the last row
+            // tile multiply rows of the stage that are never stored (no
+            // branches: a predicate per tile would make the compiler copy the
+            // accumulators around it)
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, wv[t]), hi, acc[t], 0,
+                                                                  0, 0);
+            if (NSPLIT >= 2) {
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, wv[t]), mid,
+                                                                      acc[t], 0, 0, 0);
+            }
+            if (NSPLIT >= 3) {
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, wv[t]), lo,
+                                                                      acc[t], 0, 0, 0);
+            }
+        }
     }
-    // output element r of lane l: Y[row = tile row + l % 16][col = wave col + 4 (l / 16) + r]
-    // (a predicate, not a break: a data-dependent exit from the unrolled loop
-    // would put acc in scratch memory)
+    const int64_t col = col0 + cl;
+    if (col >= n) return;
+    // accumulator elements 4 q .. 4 q + 3 are four consecutive rows of the
+    // column: one 16-byte store each into S (ldw is a multiple of 64)
+    float* sc = S + col * ldw;
 #pragma unroll
-    for (int t = 0; t < MTB; ++t) {
-        const int64_t row = (int64_t)(mt0 + t) * 16 + lane % 16;
+    for (int t = 0; t < RT; ++t) {
+        if (t < nrt) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t c = (int64_t)blockIdx.x * kSkCols + wave * 16 + 4 * (lane / 16) + r;
-            if (t < mtb && c < n && row < ldw) S[row + c * ldw] = acc[t][r];
-            if (t < mtb && Yout && c < n && row < l) Yout[row + c * ldy] = acc[t][r];
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = (int64_t)(rt0 + t) * 32 + 8 * q + 4 * h;
+                if (row < ldw)
+                    *reinterpret_cast<float4*>(sc + row) = float4(acc[t][4 * q], acc[t][4 * q + 1],
+                                                                 acc[t][4 * q + 2], acc[t][4 * q + 3]);
+                if (Yout) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (row + e < l) Yout[row + e + col * ldy] = acc[t][4 * q + e];
+                }
+            }
         }
+    }
+    // the rows below the last tile, zero (the CPQR reads ldw rows)
+    if (wr == 0) {
+        for (int64_t row = (int64_t)rt_total * 32 + 4 * h; row < ldw; row += 8)
+            *reinterpret_cast<float4*>(sc + row) = float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 
-// LDS bytes of a k_sketch instantiation (two Omega chunks)
-constexpr size_t sketch_lds(int mtb, int kc) { return (size_t)2 * mtb * 16 * (kc + 8) * 2; }
+// LDS bytes of a k_sketch instantiation
+constexpr size_t sketch_lds(int rt, int wr, int wc, int ns) {
+    return (size_t)ns * ((size_t)wr * rt * 32 * 64 + (size_t)32 * wc * 128);
+}
 
-template <bool SPLIT, bool VEC, int MTB, int KC>
-static hipError_t launch_sketch(int pr, hipStream_t s, int64_t n, int mt_total, const float* A, int64_t lda, int64_t m,
+template <int NSPLIT, int RT, int WR, int WC, int NS>
+static hipError_t launch_sketch(int pr, hipStream_t s, int64_t n, int rt_total, const float* A, int64_t lda, int64_t m,
                                 const uint16_t* Wt, int64_t mpad, float* S, int64_t ldw, float* Y, int64_t ldy,
                                 int l) {
-    constexpr size_t lds = sketch_lds(MTB, KC);
+    constexpr size_t lds = sketch_lds(RT, WR, WC, NS);
+    static_assert(lds <= 160 * 1024, "LDS of a CU");
     {
-        const hipError_t e = lds_limit_once((const void*)k_sketch<SPLIT, VEC, MTB, KC>, (int)lds);
+        const hipError_t e = lds_limit_once((const void*)k_sketch<NSPLIT, RT, WR, WC, NS>, (int)lds);
         if (e != hipSuccess) return e;
     }
-    dim3 grid((unsigned)((n + kSkCols - 1) / kSkCols), (unsigned)((mt_total + MTB - 1) / MTB));
-    MIID_LAUNCH(pr, (k_sketch<SPLIT, VEC, MTB, KC>), grid, dim3(kSkThreads), lds, s, A, lda, m, n, Wt, mpad,
-                mt_total, S, ldw, Y, ldy, l);
+    dim3 grid((unsigned)((n + 32 * WC - 1) / (32 * WC)));
+    MIID_LAUNCH(pr, (k_sketch<NSPLIT, RT, WR, WC, NS>), grid, dim3(64 * WR * WC), lds, s, A, lda, m, n, Wt, mpad,
+                rt_total, S, ldw, Y, ldy, l);
     return hipGetLastError();
 }
 
-// Tile rows per workgroup: every 16-row tile of Y in one workgroup when
-// l <= 528 (A is then read once), 33 tiles per workgroup row beyond.
-template <bool SPLIT, bool VEC>
-static hipError_t launch_sketch_mt(int pr, hipStream_t s, int64_t n, int mt_total, const float* A, int64_t lda,
-                                   int64_t m, const uint16_t* Wt, int64_t mpad, float* S, int64_t ldw, float* Y,
-                                   int64_t ldy, int l) {
-    if (mt_total <= 9)
-        return launch_sketch<SPLIT, VEC, 9, 128>(pr, s, n, mt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l);
-    if (mt_total <= 17)
-        return launch_sketch<SPLIT, VEC, 17, 128>(pr, s, n, mt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l);
-    return launch_sketch<SPLIT, VEC, 33, 64>(pr, s, n, mt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l);
-}
-
-template <typename T>
-__global__ void k_fill_rid(T* __restrict__ p, int64_t count, T value) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = value;
+// Workgroup shape from the 32-row tiles of Y: two waves along the rows with
+// 5 or 9 tiles each up to 18 tiles (576 rows), four with 8 tiles beyond (at
+// most 32 tiles: l <= 1024); four waves along the columns when that still
+// gives two workgroups per CU, else two.  The ring depth fills the LDS.
+template <int NSPLIT>
+static hipError_t launch_sketch_shape(int pr, hipStream_t s, int64_t n, int rt_total, const float* A, int64_t lda,
+                                      int64_t m, const uint16_t* Wt, int64_t mpad, float* S, int64_t ldw, float* Y,
+                                      int64_t ldy, int l) {
+    const bool wide = (n + 127) / 128 >= 2 * (int64_t)dev_info().cus;
+    if (rt_total <= 10)
+        return wide ? launch_sketch<NSPLIT, 5, 2, 4, 4>(pr, s, n, rt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l)
+                    : launch_sketch<NSPLIT, 5, 2, 2, 4>(pr, s, n, rt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l);
+    if (rt_total <= 18)
+        return wide ? launch_sketch<NSPLIT, 9, 2, 4, 3>(pr, s, n, rt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l)
+                    : launch_sketch<NSPLIT, 9, 2, 2, 3>(pr, s, n, rt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l);
+    return launch_sketch<NSPLIT, 8, 4, 2, 2>(pr, s, n, rt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l);
 }
 
 struct RidPlan {
     IdPlan id;
-    int lpad;        // rows of Wt (16-row tiles)
-    int mt_total;    // 16-row tiles of Y
+    int lpad;        // rows of Wt (32-row tiles)
+    int rt_total;    // 32-row tiles of Y
     int64_t mpad;    // K padded to 32
     size_t oWt, total;
     // least-squares Z over the full A for the sketch's skeleton
@@ -240,10 +376,10 @@ static int make_rid_plan(int64_t m, int64_t n, int32_t l, const miid_opts* opts,
     if (m > n || l > n) return MIID_E_UNSUPPORTED;
     const int rc = make_plan(l, n, MIID_F32, opts, &R->id);
     if (rc != 0) return rc == -2 ? -6 : (rc == -6 ? -9 : rc);
-    R->mt_total = (l + 15) / 16;
-    R->lpad = R->mt_total * 16;
+    R->rt_total = (l + 31) / 32;
+    R->lpad = R->rt_total * 32;
     if (R->lpad > R->id.ldw) return MIID_E_UNSUPPORTED;
-    R->mpad = (int64_t)align_up((size_t)m, kSkK);
+    R->mpad = (int64_t)align_up((size_t)m, 32);
     R->oWt = align_up(R->id.total, 256);
     R->total = align_up(R->oWt + (size_t)R->lpad * R->mpad * 2, 256);
     R->lstsq = opts && (opts->flags & MIID_LSTSQ_Z);
@@ -279,8 +415,10 @@ static int rid_body(const float* A, int64_t m, int64_t n, int64_t lda, const uin
     const int rc = make_rid_plan(m, n, l, opts, &R);
     if (rc != 0) return rc;
     if (lda < m) return -4;
+    // the sketch addresses a workgroup's 128 columns of A with 32-bit offsets
+    if (lda > kSkMaxLda) return MIID_E_UNSUPPORTED;
     if (ldo < l) return -7;
-    if (mode != 0 && mode != 1) return -8;
+    if (mode < 0 || mode > 2) return -8;
     if (!J) return -10;
     if (!Z) return -11;
     if (ldz < R.id.kmax) return -12;
@@ -296,26 +434,19 @@ static int rid_body(const float* A, int64_t m, int64_t n, int64_t lda, const uin
     uint16_t* Wt = reinterpret_cast<uint16_t*>(w + R.oWt);
     const int64_t ldw = R.id.ldw;
 
-    // rows of S beyond the sketch tiles must be zero
-    {
-        const int64_t cnt = ldw * n;
-        const int blocks = (int)std::min<int64_t>((cnt + 255) / 256, 8192);
-        hipLaunchKernelGGL(k_fill_rid<float>, dim3(blocks), dim3(256), 0, s, S, cnt, 0.f);
-    }
     {
         dim3 grid((unsigned)((R.mpad + 63) / 64), (unsigned)((R.lpad + 63) / 64));
         hipLaunchKernelGGL(k_omega_t, grid, dim3(256), 0, s, Omega, l, m, ldo, Wt, R.lpad, R.mpad);
     }
     {
-        const bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
         const int pr = prof_take(MIID_K_SKETCH, 0, m, n);
         hipError_t e;
-        if (mode == 1)
-            e = vec ? launch_sketch_mt<true, true>(pr, s, n, R.mt_total, A, lda, m, Wt, R.mpad, S, ldw, Y, ldy, l)
-                    : launch_sketch_mt<true, false>(pr, s, n, R.mt_total, A, lda, m, Wt, R.mpad, S, ldw, Y, ldy, l);
+        if (mode == 2)
+            e = launch_sketch_shape<3>(pr, s, n, R.rt_total, A, lda, m, Wt, R.mpad, S, ldw, Y, ldy, l);
+        else if (mode == 1)
+            e = launch_sketch_shape<2>(pr, s, n, R.rt_total, A, lda, m, Wt, R.mpad, S, ldw, Y, ldy, l);
         else
-            e = vec ? launch_sketch_mt<false, true>(pr, s, n, R.mt_total, A, lda, m, Wt, R.mpad, S, ldw, Y, ldy, l)
-                    : launch_sketch_mt<false, false>(pr, s, n, R.mt_total, A, lda, m, Wt, R.mpad, S, ldw, Y, ldy, l);
+            e = launch_sketch_shape<1>(pr, s, n, R.rt_total, A, lda, m, Wt, R.mpad, S, ldw, Y, ldy, l);
         MIID_HIP(e);
     }
     MIID_HIP(hipGetLastError());

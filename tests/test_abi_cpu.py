@@ -92,7 +92,7 @@ def test_argument_validation_before_any_device_work():
     # randomized ID: m > n unsupported, bad mode -> -9
     assert lib.rid_sketch_cpqr(h, dummy, 30, 20, 30, dummy, 8, 8, 1, ctypes.byref(o), dummy, dummy, 4, None, 1, None,
                                1, None, 1, dummy, dummy, 1 << 30, None) == _abi.MIID_E_UNSUPPORTED
-    assert lib.rid_sketch_cpqr(h, dummy, 10, 20, 10, dummy, 8, 8, 2, ctypes.byref(o), dummy, dummy, 4, None, 1, None,
+    assert lib.rid_sketch_cpqr(h, dummy, 10, 20, 10, dummy, 8, 8, 3, ctypes.byref(o), dummy, dummy, 4, None, 1, None,
                                1, None, 1, dummy, dummy, 1 << 30, None) == -9
     # batched: kmax out of range in the options -> -8
     ob = _abi.MiidOpts()
