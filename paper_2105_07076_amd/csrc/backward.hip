@@ -174,6 +174,163 @@ __global__ void __launch_bounds__(kBwThreads) k_bw_gemm_nt(const T* __restrict__
         }
 }
 
+// FP32 products on the matrix cores with LDS tiles (v_mfma_f32_32x32x2f32):
+// OUT (rows x cols, column-major, ldo) = X Y over the K range of this
+// workgroup, X rows x K column-major (ldx), and Y either K x cols column-major
+// (YKC: K contiguous, ldy) or stored as cols x K column-major (Y[kk][c] at
+// c + kk ldy).  128 x 128 output tile per workgroup, 64 x 64 per wave (2 x 2
+// tiles of 32 x 32); K in chunks of 32, both operands staged in LDS as
+// [k][row] / [k][col] (every lane of an MFMA operand read hits consecutive
+// words), the next chunk's loads in flight while the current one is
+// multiplied.  Operand layout: lane l holds row (column) l % 32 and
+// k = l / 32; accumulator element r of lane l is row 8 (r / 4) + 4 (l / 32) +
+// r % 4, column l % 32.  Workgroup z takes K range [z kper, (z + 1) kper)
+// and writes OUT + z zstride (a split-K partial when gridDim.z > 1).
+constexpr int kGlT = 128;  // output tile side
+constexpr int kGlK = 32;   // K per chunk
+constexpr int kGlLd = 132;  // LDS row stride (floats) of the row-contiguous tiles
+constexpr int kGlLdT = 129; // LDS row stride of a transposed (K-contiguous) tile
+
+typedef float bwf16_t __attribute__((ext_vector_type(16)));
+
+template <bool YKC, bool VEC>
+__global__ void __launch_bounds__(kBwThreads) k_bw_gemm_lds(const float* __restrict__ X, int64_t ldx,
+                                                            const float* __restrict__ Y, int64_t ldy,
+                                                            float* __restrict__ OUT, int64_t ldo, int64_t zstride,
+                                                            int64_t rows, int64_t cols, int64_t K, int64_t kper) {
+    __shared__ __align__(16) float sX[2][kGlK * kGlLd];
+    __shared__ __align__(16) float sY[2][kGlK * kGlLd];
+    constexpr int LY = YKC ? kGlLdT : kGlLd;
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
+    const int64_t r0 = (int64_t)blockIdx.x * kGlT, c0 = (int64_t)blockIdx.y * kGlT;
+    const int wr = (wave & 1) * 64, wcol = (wave >> 1) * 64;
+    const int64_t kbeg = (int64_t)blockIdx.z * kper;
+    const int64_t kend = std::min<int64_t>(K, kbeg + kper);
+    OUT += (int64_t)blockIdx.z * zstride;
+
+    // a chunk of a row-contiguous operand (P: rows x K, ld): 32 k of 128
+    // rows, four rows per 16-byte load, four loads per thread
+    auto load_rc = [&](const float* P, int64_t ld, int64_t p0, int64_t plim, int64_t k0, float4 (&v)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = tid + kBwThreads * i;
+            const int kk = f / 32, q = f % 32;
+            const int64_t p = p0 + 4 * q, k = k0 + kk;
+            if (VEC && k < kend && p + 4 <= plim) {
+                v[i] = *reinterpret_cast<const float4*>(P + p + k * ld);
+            } else {
+                float e[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) e[t] = (k < kend && p + t < plim) ? P[p + t + k * ld] : 0.f;
+                v[i] = float4(e[0], e[1], e[2], e[3]);
+            }
+        }
+    };
+    auto store_rc = [&](float* S, const float4 (&v)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = tid + kBwThreads * i;
+            *reinterpret_cast<float4*>(S + (f / 32) * kGlLd + 4 * (f % 32)) = v[i];
+        }
+    };
+    // a chunk of a K-contiguous operand (Y: K x cols, ldy): 32 k of 128
+    // columns, four k per 16-byte load, stored transposed
+    auto load_kc = [&](int64_t k0, float4 (&v)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = tid + kBwThreads * i;
+            const int c = f / 8, q = f % 8;
+            const int64_t col = c0 + c, k = k0 + 4 * q;
+            if (VEC && col < cols && k + 4 <= kend) {
+                v[i] = *reinterpret_cast<const float4*>(Y + k + col * ldy);
+            } else {
+                float e[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) e[t] = (col < cols && k + t < kend) ? Y[k + t + col * ldy] : 0.f;
+                v[i] = float4(e[0], e[1], e[2], e[3]);
+            }
+        }
+    };
+    auto store_kc = [&](float* S, const float4 (&v)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = tid + kBwThreads * i;
+            const int c = f / 8, q = f % 8;
+            S[(4 * q + 0) * kGlLdT + c] = v[i].x;
+            S[(4 * q + 1) * kGlLdT + c] = v[i].y;
+            S[(4 * q + 2) * kGlLdT + c] = v[i].z;
+            S[(4 * q + 3) * kGlLdT + c] = v[i].w;
+        }
+    };
+    auto load = [&](int64_t k0, float4 (&vx)[4], float4 (&vy)[4]) {
+        load_rc(X, ldx, r0, rows, k0, vx);
+        if (YKC)
+            load_kc(k0, vy);
+        else
+            load_rc(Y, ldy, c0, cols, k0, vy);
+    };
+    auto store = [&](int buf, const float4 (&vx)[4], const float4 (&vy)[4]) {
+        store_rc(sX[buf], vx);
+        if (YKC)
+            store_kc(sY[buf], vy);
+        else
+            store_rc(sY[buf], vy);
+    };
+
+    bwf16_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    float4 vx[4], vy[4];
+    load(kbeg, vx, vy);
+    store(0, vx, vy);
+    __syncthreads();
+    int cur = 0;
+    const int hl = lane / 32, l32 = lane % 32;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += kGlK) {
+        const bool more = k0 + kGlK < kend;
+        if (more) load(k0 + kGlK, vx, vy);
+        const float* xs = sX[cur] + hl * kGlLd + wr + l32;
+        const float* ys = sY[cur] + hl * LY + wcol + l32;
+#pragma unroll
+        for (int ks = 0; ks < kGlK / 2; ++ks) {
+            const float a0 = xs[2 * ks * kGlLd], a1 = xs[2 * ks * kGlLd + 32];
+            const float b0 = ys[2 * ks * LY], b1 = ys[2 * ks * LY + 32];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        if (more) store(cur ^ 1, vx, vy);
+        __syncthreads();
+        cur ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t col = c0 + wcol + 32 * j + l32;
+            if (col >= cols) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = r0 + wr + 32 * i + 8 * q + 4 * hl;
+                float* o = OUT + row + col * ldo;
+                if (VEC && row + 4 <= rows) {
+                    *reinterpret_cast<float4*>(o) =
+                        float4(acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (row + t < rows) o[t] = acc[i][j][4 * q + t];
+                }
+            }
+        }
+}
+
 // OUT[e] = sum_z PART[z][e] in a fixed order
 template <typename T>
 __global__ void k_bw_reduce(const T* __restrict__ PART, int nz, int64_t count, T* __restrict__ OUT) {
@@ -251,21 +408,64 @@ static int run_bw(const T* A, int64_t m, int64_t n, int64_t lda, const int32_t* 
         hipLaunchKernelGGL(k_bw_zero<T>, dim3((unsigned)std::min<int64_t>((cnt + 255) / 256, 4096)), dim3(256), 0, s, M,
                            cnt);
     }
-    int pr = prof_take(MIID_K_BWD_GEMM, 0, m, n);
-    // gA = C M  (J columns come out zero: M[:, J] = 0)
-    MIID_LAUNCH(pr, k_bw_gemm_nn<T>, dim3((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64)), dim3(kBwThreads),
-                       0, s, C, m, M, (int64_t)k, gA, ldga, m, n, k);
-    // P = A M^T (m x k), split over n
-    pr = prof_take(MIID_K_BWD_GEMM, 0, m, n);
-    MIID_LAUNCH(pr, k_bw_gemm_nt<T>, dim3((unsigned)((m + 63) / 64), (unsigned)((k + 63) / 64), (unsigned)B.nz),
-                dim3(kBwThreads), 0, s, A, lda, M, (int64_t)k, part, m, (int64_t)k, n);
-    hipLaunchKernelGGL(k_bw_reduce<T>, dim3((unsigned)std::min<int64_t>((m * k + 255) / 256, 4096)), dim3(256), 0, s,
-                       part, B.nz, m * k, P);
-    // Q = Z M^T (k x k), split over n
-    hipLaunchKernelGGL(k_bw_gemm_nt<T>, dim3((unsigned)((k + 63) / 64), (unsigned)((k + 63) / 64), (unsigned)B.nz),
-                       dim3(kBwThreads), 0, s, Z, ldz, M, (int64_t)k, part, (int64_t)k, (int64_t)k, n);
-    hipLaunchKernelGGL(k_bw_reduce<T>, dim3((unsigned)std::min<int64_t>(((int64_t)k * k + 255) / 256, 4096)), dim3(256),
-                       0, s, part, B.nz, (int64_t)k * k, Q);
+    if constexpr (sizeof(T) == 4) {
+        // FP32: LDS-tiled products on the 32x32x2 matrix-core instruction
+        const uintptr_t al = 15;
+        const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(Z) |
+                           reinterpret_cast<uintptr_t>(gA)) & al) == 0 &&
+                         lda % 4 == 0 && ldz % 4 == 0 && ldga % 4 == 0 && m % 4 == 0 && k % 4 == 0;
+        auto gemm = [&](int pr, bool ykc, const T* X, int64_t ldx, const T* Y, int64_t ldy, T* OUT, int64_t ldo,
+                        int64_t zstride, int64_t rows, int64_t cols, int64_t K, int nz) -> hipError_t {
+            const int64_t kper = (int64_t)align_up((size_t)((K + nz - 1) / nz), kGlK);
+            const dim3 grid((unsigned)((rows + kGlT - 1) / kGlT), (unsigned)((cols + kGlT - 1) / kGlT),
+                            (unsigned)((K + kper - 1) / kper));
+            if (ykc) {
+                if (vec)
+                    MIID_LAUNCH(pr, (k_bw_gemm_lds<true, true>), grid, dim3(kBwThreads), 0, s, X, ldx, Y, ldy, OUT,
+                                ldo, zstride, rows, cols, K, kper);
+                else
+                    MIID_LAUNCH(pr, (k_bw_gemm_lds<true, false>), grid, dim3(kBwThreads), 0, s, X, ldx, Y, ldy, OUT,
+                                ldo, zstride, rows, cols, K, kper);
+            } else {
+                if (vec)
+                    MIID_LAUNCH(pr, (k_bw_gemm_lds<false, true>), grid, dim3(kBwThreads), 0, s, X, ldx, Y, ldy, OUT,
+                                ldo, zstride, rows, cols, K, kper);
+                else
+                    MIID_LAUNCH(pr, (k_bw_gemm_lds<false, false>), grid, dim3(kBwThreads), 0, s, X, ldx, Y, ldy,
+                                OUT, ldo, zstride, rows, cols, K, kper);
+            }
+            return hipGetLastError();
+        };
+        // gA = C M  (J columns come out zero: M[:, J] = 0)
+        MIID_HIP(gemm(prof_take(MIID_K_BWD_GEMM, 0, m, n), true, C, m, M, (int64_t)k, gA, ldga, 0, m, n, k, 1));
+        // P = A M^T (m x k): Y[kk][c] = M[c, kk]; split over n, fixed-order sum
+        MIID_HIP(gemm(prof_take(MIID_K_BWD_GEMM, 1, m, n), false, A, lda, M, (int64_t)k, part, m, m * k, m, k, n,
+                      B.nz));
+        hipLaunchKernelGGL(k_bw_reduce<T>, dim3((unsigned)std::min<int64_t>((m * k + 255) / 256, 4096)), dim3(256), 0,
+                           s, part, B.nz, m * k, P);
+        // Q = Z M^T (k x k), split over n
+        MIID_HIP(gemm(-1, false, Z, ldz, M, (int64_t)k, part, (int64_t)k, (int64_t)k * k, (int64_t)k, (int64_t)k, n,
+                      B.nz));
+        hipLaunchKernelGGL(k_bw_reduce<T>, dim3((unsigned)std::min<int64_t>(((int64_t)k * k + 255) / 256, 4096)),
+                           dim3(256), 0, s, part, B.nz, (int64_t)k * k, Q);
+    } else {
+        int pr = prof_take(MIID_K_BWD_GEMM, 0, m, n);
+        // gA = C M  (J columns come out zero: M[:, J] = 0)
+        MIID_LAUNCH(pr, k_bw_gemm_nn<T>, dim3((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64)),
+                    dim3(kBwThreads), 0, s, C, m, M, (int64_t)k, gA, ldga, m, n, k);
+        // P = A M^T (m x k), split over n
+        pr = prof_take(MIID_K_BWD_GEMM, 0, m, n);
+        MIID_LAUNCH(pr, k_bw_gemm_nt<T>, dim3((unsigned)((m + 63) / 64), (unsigned)((k + 63) / 64), (unsigned)B.nz),
+                    dim3(kBwThreads), 0, s, A, lda, M, (int64_t)k, part, m, (int64_t)k, n);
+        hipLaunchKernelGGL(k_bw_reduce<T>, dim3((unsigned)std::min<int64_t>((m * k + 255) / 256, 4096)), dim3(256), 0,
+                           s, part, B.nz, m * k, P);
+        // Q = Z M^T (k x k), split over n
+        hipLaunchKernelGGL(k_bw_gemm_nt<T>, dim3((unsigned)((k + 63) / 64), (unsigned)((k + 63) / 64),
+                                                 (unsigned)B.nz),
+                           dim3(kBwThreads), 0, s, Z, ldz, M, (int64_t)k, part, (int64_t)k, (int64_t)k, n);
+        hipLaunchKernelGGL(k_bw_reduce<T>, dim3((unsigned)std::min<int64_t>(((int64_t)k * k + 255) / 256, 4096)),
+                           dim3(256), 0, s, part, B.nz, (int64_t)k * k, Q);
+    }
     hipLaunchKernelGGL(k_bw_jcols<T>, dim3((unsigned)std::min<int64_t>((m + 255) / 256, 64), (unsigned)k), dim3(256), 0,
                        s, C, P, Q, gC, ldgc, J, m, k, gA, ldga);
     MIID_HIP(hipGetLastError());
