@@ -85,9 +85,9 @@ def time_id(miid_api, lib, A, k, steps, warmup, sample_every=7):
 GEMV_TRAFFIC = {
     "bytes_per_launch": 532.1e6,
     "sources": {
-        "paper_2105_07076_amd/csrc/id_cpqr.hip": "7fb2ecb8510389f1494d5be2c26f7a4f21841d734f2870e5b08f5b22aa3d15ac",
+        "paper_2105_07076_amd/csrc/id_cpqr.hip": "5406f75fd60b82d7b52c812a04342a8eeba4d54c4ec9f0a6d1c2ab6b06afc296",
         "paper_2105_07076_amd/csrc/common.hpp": "77e3f522d4607da471046f7b4d08b5688ce5617e1b620ace976254481bb74ae8",
-        "paper_2105_07076_amd/csrc/cpqr.hpp": "c5af1863f13e79013f7e57c2d630a8f7b6596f8e47994e4c871b31b405454bf3",
+        "paper_2105_07076_amd/csrc/cpqr.hpp": "4c711f839dd9776cb750a3adfc41feef2cc6f5b5b9a0c07a6ebb4c9d7bd055d9",
     },
 }
 
@@ -281,8 +281,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing on the host")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--host-input", action="store_true",
-                    help="build the 4096 x 16384 input with the numpy recipe on the host (no device QR; "
-                         "for counter-collection runs)")
+                    help="build the 4096 x 16384 input with the numpy recipe on the host and the 16384 x 65536 "
+                         "one as plain Gaussian entries (no device QR; for counter-collection runs)")
     ap.add_argument("--only", default="all",
                     help="comma list of sections to run: id64,id32,rid,rid3,ridsample,twosided,paper,batched,bwd "
                          "(default all); the value is the FP64 ID, so id64 always runs")
@@ -398,8 +398,13 @@ def main() -> int:
         # triplets, s_i = exp(-i/128)), Omega 522 x 16384, k = 512, split sketch
         m3, n3, l3, k3 = 16384, 65536, 522, 512
         log(f"[bench] mixed RID {m3}x{n3}, l = {l3}, k = {k3}")
-        A3 = idgen.lowrank_plus_noise_device(3, m3, n3, np.exp(-np.arange(4096) / 128.0), 1e-8, r=4096,
-                                             dtype=torch.float32)
+        if args.host_input:  # counter runs: the traffic depends on the shapes only
+            g3 = torch.Generator(device="cuda")
+            g3.manual_seed(3)
+            A3 = torch.randn(n3, m3, generator=g3, device="cuda", dtype=torch.float32).t()
+        else:
+            A3 = idgen.lowrank_plus_noise_device(3, m3, n3, np.exp(-np.arange(4096) / 128.0), 1e-8, r=4096,
+                                                 dtype=torch.float32)
         Om3_h = idgen.omega_bf16(78, l3, m3)
         Om3 = torch.tensor(Om3_h, dtype=torch.bfloat16, device="cuda")
         out3 = miid_api.rid_raw(A3, Om3, k=k3, mode=1)
