@@ -96,9 +96,10 @@ def test_batched_small_sizes_and_kmax():
     _check_blocks(blocks, res, A64, torch.float64, range(40), eps=1e-9, kmax=8)
 
 
-@pytest.mark.skip(reason="this case once ran silent for 180 s on the GPU and was stopped (no GPU fault); "
-                         "no cause was found by reading that kernel or the host path, so the case stays off "
-                         "the GPU although the kernel it ran has since been replaced")
+@pytest.mark.skip(reason="this case once ran silent for 180 s on the GPU and was stopped (no GPU fault), on a "
+                         "kernel version that is not in the sources any more; its cause cannot be shown, so "
+                         "the case stays off the GPU (the current kernel's paths for both blocks were traced "
+                         "by reading instead)")
 def test_batched_isolates_bad_blocks():
     """A NaN in one block and an oversized block do not disturb the others."""
     miid = _miid()
