@@ -83,9 +83,9 @@ def time_id(miid_api, lib, A, k, steps, warmup, sample_every=7):
 # passes (scaled against a copy kernel of known size), valid only for the
 # kernel sources they were taken on.
 GEMV_TRAFFIC = {
-    "bytes_per_launch": 532.1e6,
+    "bytes_per_launch": 529.2e6,
     "sources": {
-        "paper_2105_07076_amd/csrc/id_cpqr.hip": "5406f75fd60b82d7b52c812a04342a8eeba4d54c4ec9f0a6d1c2ab6b06afc296",
+        "paper_2105_07076_amd/csrc/id_cpqr.hip": "a914d41fe212e5f5da15d86ab7195f002507cc01fc2a54c3386b559e4134ff9c",
         "paper_2105_07076_amd/csrc/common.hpp": "77e3f522d4607da471046f7b4d08b5688ce5617e1b620ace976254481bb74ae8",
         "paper_2105_07076_amd/csrc/cpqr.hpp": "4c711f839dd9776cb750a3adfc41feef2cc6f5b5b9a0c07a6ebb4c9d7bd055d9",
     },
@@ -626,7 +626,7 @@ def main() -> int:
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "deterministic ID, A 4096x16384 FP64 = U diag(exp(-i/64)) V^T + 1e-8 G, k=256",
-                   "m": m, "n": n, "k": k, "nb": 32},
+                   "m": m, "n": n, "k": k, "nb": 64},
         "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,

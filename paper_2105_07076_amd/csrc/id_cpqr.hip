@@ -384,19 +384,24 @@ __global__ void __launch_bounds__(kThreads) k_gemv(const T* __restrict__ S, int6
     const VT* sp[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) sp[c] = reinterpret_cast<const VT*>(S + (col0 + c) * ldw + j0);
-    // the stream over S; NTL: loads marked nontemporal
+    // the stream over S; NTL: loads marked nontemporal.  Every pass issues
+    // its U loads per column together, the last one masked per lane at the
+    // end of the column (a remainder loop of single loads would wait a full
+    // memory round trip per 64 groups).
     auto stream = [&](auto ntl) {
         constexpr bool NTL = decltype(ntl)::value;
-        int64_t g = lane;
-        for (; g + (U - 1) * kWave < ngroups; g += U * kWave) {
+        for (int64_t g = lane; g < ngroups; g += U * kWave) {
             VT sv[C][U], uv[U];
 #pragma unroll
-            for (int q = 0; q < U; ++q) uv[q] = up[g + q * kWave];
+            for (int q = 0; q < U; ++q) uv[q] = g + q * kWave < ngroups ? up[g + q * kWave] : VT{};
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 if (alive[c]) {
 #pragma unroll
-                    for (int q = 0; q < U; ++q) sv[c][q] = NTL ? load_nt(&sp[c][g + q * kWave]) : sp[c][g + q * kWave];
+                    for (int q = 0; q < U; ++q) {
+                        const int64_t gq = g + q * kWave;
+                        sv[c][q] = gq < ngroups ? (NTL ? load_nt(&sp[c][gq]) : sp[c][gq]) : VT{};
+                    }
                 }
             }
 #pragma unroll
@@ -410,25 +415,15 @@ __global__ void __launch_bounds__(kThreads) k_gemv(const T* __restrict__ S, int6
                 }
             }
         }
-        for (; g < ngroups; g += kWave) {
-            const VT uv = up[g];
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                if (alive[c]) {
-                    const VT sv = NTL ? load_nt(&sp[c][g]) : sp[c][g];
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) acc[c] += (double)get(sv, e) * (double)get(uv, e);
-                }
-            }
-        }
     };
     // FP64: the first third of the workgroups in dispatch order (the columns
     // the previous step read last, still in the memory-side cache) load
     // nontemporally, so that re-reading them does not push out what the rest
     // of this step brings in -- the part the next step, sweeping back, reads
     // first.  FP32 steps (half the bytes) nearly fit that cache and stay
-    // ordinary.  Measured on the 4096 x 16384 FP64 ID: 27.8 -> 27.3 ms (no
-    // nontemporal loads / first third; a half and two thirds are slower).
+    // ordinary.  Measured on the 4096 x 16384 FP64 ID with 64-wide panels:
+    // 26.4 ms with no nontemporal loads, 25.6 with the first third, 26.8 with
+    // two thirds, 27.0 with all of them.
     if (sizeof(T) == 8 && 3 * (int64_t)blockIdx.x < (int64_t)gridDim.x)
         stream(std::true_type{});
     else
@@ -1279,12 +1274,13 @@ __global__ void k_finalize(const DevState* __restrict__ st, const ColPartial* __
 // host side
 // ---------------------------------------------------------------------------
 
-// Columns per wave of the F-GEMV (1, 2 or 4): the CPW hint, else one in FP64
-// and two in FP32 (timed fastest for 4096-row matrices).
-static int gemv_cols_per_wave(uint32_t flags, size_t esz) {
+// Columns per wave of the F-GEMV (1, 2 or 4): the CPW hint, else one (timed
+// fastest for 4096-row matrices in both precisions: more columns per wave
+// mean fewer, longer workgroups and a longer ragged end of each launch).
+static int gemv_cols_per_wave(uint32_t flags) {
     const int h = (int)((flags >> MIID_HINT_CPW_SHIFT) & 15u);
     if (h == 1 || h == 2 || h == 4) return h;
-    return esz == 4 ? 2 : 1;
+    return 1;
 }
 
 // The fused path is taken where eligible unless the PATH hint asks for the
@@ -1324,7 +1320,7 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
     P->esz = dtype == MIID_F64 ? 8 : 4;
     P->ldw = (int64_t)align_up((size_t)P->m, 64);
     if ((size_t)P->ldw * P->esz > kMaxVecLds) return MIID_E_UNSUPPORTED;
-    P->cpw = gemv_cols_per_wave(o->flags, P->esz);
+    P->cpw = gemv_cols_per_wave(o->flags);
     P->npart = (int)((P->n + 4 * P->cpw - 1) / (4 * P->cpw));
     P->NA = (int)((P->ldw + kRowsPerChunk - 1) / kRowsPerChunk);
     P->fnp = fused_np(P->n, o->flags);
@@ -1336,10 +1332,11 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
         P->fgl = per_lane <= 5 ? 5 : (per_lane <= 9 ? 9 : 0);
     }
     P->fused = P->ldw <= kFusedMaxRows && P->fgl > 0 && P->nb <= kFusedMaxNb && fused_enabled(o->flags);
-    // FP32 blocked path: 16 timed fastest for 4096 x 16384 IDs; the fused
-    // path keeps 32 (fewer roundings of the eagerly updated trailing matrix
-    // for the same time)
-    if (o->nb == 0 && dtype == MIID_F32 && !P->fused) P->nb = 16;
+    // blocked path: FP32 16 and FP64 64 timed fastest for 4096 x 16384 IDs
+    // (FP64: three trailing updates instead of seven, each reading and
+    // writing the trailing matrix once); the fused path keeps 32 (fewer
+    // roundings of the eagerly updated trailing matrix for the same time)
+    if (o->nb == 0 && !P->fused) P->nb = dtype == MIID_F32 ? 16 : 64;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o2 = off;
@@ -1540,6 +1537,8 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
                 MIID_LAUNCH(pr, (k_trail<T, 32>), grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
             else if (nb == 16)
                 MIID_LAUNCH(pr, (k_trail<T, 16>), grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
+            else if (nb == 64)
+                MIID_LAUNCH(pr, (k_trail<T, 64>), grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
             else
                 MIID_LAUNCH(pr, (k_trail<T, 0>), grid, dim3(kThreads), 0, stream, S, ldw, n, V, F, nb, nb, r0, st);
         }
