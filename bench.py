@@ -626,7 +626,7 @@ def main() -> int:
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "deterministic ID, A 4096x16384 FP64 = U diag(exp(-i/64)) V^T + 1e-8 G, k=256",
-                   "m": m, "n": n, "k": k, "nb": 64},
+                   "m": m, "n": n, "k": k, "nb": 32},
         "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,

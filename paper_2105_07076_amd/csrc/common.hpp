@@ -219,4 +219,15 @@ __device__ __forceinline__ double get(const float4& v, int e) {
 
 __device__ __forceinline__ bool is_finite_d(double x) { return !(isnan(x) || isinf(x)); }
 
+// p[idx] where ok, else `other`, with no branch: the load always issues (from
+// p[safe], a valid element, where !ok) and the choice is a select.  A load
+// written under a condition becomes a branch whose other side writes the same
+// register, and the compiler then waits for the load before that write, so a
+// run of such loads goes out one memory round trip at a time.
+template <typename X>
+__device__ __forceinline__ X load_or(const X* p, int64_t idx, bool ok, int64_t safe, X other) {
+    const X v = p[ok ? idx : safe];
+    return ok ? v : other;
+}
+
 }  // namespace miid

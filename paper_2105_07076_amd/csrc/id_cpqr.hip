@@ -176,9 +176,10 @@ __global__ void k_fill(T* __restrict__ p, int64_t count, T value) {
 
 // ---------------------------------------------------------------------------
 // a2 + a3 + first half of a4: pivot search, lazy update of the pivot column,
-// partial sums for the reflector.  One thread per row, 256 rows per workgroup.
+// partial sums for the reflector.  One thread per row, 256 rows per workgroup;
+// NBT >= nb bounds the unrolled loops over the panel.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NBT>
 __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S, int64_t ldw, int64_t m,
                                                         const T* __restrict__ V, const T* __restrict__ F, int nb,
                                                         T* __restrict__ u, const ColPartial* __restrict__ part,
@@ -195,6 +196,7 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
     const int64_t r = (int64_t)blockIdx.x * kRowsPerChunk + tid;
     const bool active = r >= j && r < m;
     const int stop_in = st->stop;
+    const double a_prev = st->a_norm;
 
     // a2: pivot = argmax of the per-workgroup column partials (same order in
     // every workgroup, no atomics).  The first kPU per thread are all issued
@@ -212,9 +214,14 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
     // row r of the panel's reflectors does not depend on the pivot: its loads
     // go out now, behind the partials (so waiting for those does not wait
     // for these)
-    double vr[kMaxNb];
+    // (columns q >= i load column i - 1 again, a cache hit, so that the
+    // loads need no branch and the traffic stays i columns)
+    double vr[NBT];
+    const int64_t rv = r < ldw ? r : 0;
+    const int qlast = i > 0 ? i - 1 : 0;
 #pragma unroll
-    for (int q = 0; q < kMaxNb; ++q) vr[q] = (active && q < i) ? (double)V[r + (int64_t)q * ldw] : 0.0;
+    for (int q = 0; q < NBT; ++q)
+        vr[q] = (double)load_or(V, r + (int64_t)q * ldw, active && q < i, rv + (int64_t)min(q, qlast) * ldw, T(0));
 #pragma unroll
     for (int k = 0; k < kPU; ++k) {
         if (argmax_better(cp[k].best, cp[k].idx, best.v, best.i)) best = {cp[k].best, cp[k].idx};
@@ -240,7 +247,7 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
     __syncthreads();
     fold_waves<4>(w_best, w_idx, w_sum, w_nf, best, sumsq, nf);
 
-    const double a_norm = (j == 0) ? sqrt(sumsq) : st->a_norm;
+    const double a_norm = (j == 0) ? sqrt(sumsq) : a_prev;
     uint32_t status = 0;
     bool stop = false;
     if (nf) {
@@ -264,15 +271,16 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
     }
     if (stop) return;
     const int64_t p = best.i;
-    if (tid < i) s_F[tid] = (double)F[p * nb + tid];
-    const double spr = active ? (double)S[r + p * ldw] : 0.0;
+    const double spr = (double)load_or(S, r + p * ldw, active, p * ldw, T(0));
+    const double fp = (double)load_or(F, p * nb + tid, tid < i, p * nb, T(0));
+    if (tid < i) s_F[tid] = fp;
     __syncthreads();
 
     // a3: lazily updated pivot column u = S[:, p] - V F[p, :]^T (rows j..m-1),
     // the sum over the panel in four interleaved chains
     double ua[4] = {spr, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < kMaxNb; ++q)
+    for (int q = 0; q < NBT; ++q)
         if (q < i) ua[q & 3] -= vr[q] * s_F[q];
     const double ur = (ua[0] + ua[1]) + (ua[2] + ua[3]);
     const T ut = (T)ur;
@@ -290,7 +298,7 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
     const int ldp = nb + 1;
     sP[tid * ldp] = w * w;
 #pragma unroll
-    for (int q = 0; q < kMaxNb; ++q)
+    for (int q = 0; q < NBT; ++q)
         if (q < i) sP[tid * ldp + 1 + q] = vr[q] * w;
     __syncthreads();
     for (int c = tid % 32; c < ncol; c += 32) {
@@ -572,11 +580,12 @@ template <typename T, int GL>
 struct ColChunk {
     using VT = typename Vec16<T>::type;
     VT v[GL];
-    __device__ __forceinline__ void load(const T* base, int64_t ngroups, int l16) {
+    // base: the column's row j0 where ok, else any valid element
+    __device__ __forceinline__ void load(const T* base, bool ok, int64_t ngroups, int l16) {
 #pragma unroll
         for (int t = 0; t < GL; ++t) {
             const int64_t g = l16 + 16 * t;
-            v[t] = (base && g < ngroups) ? reinterpret_cast<const VT*>(base)[g] : VT{};
+            v[t] = load_or(reinterpret_cast<const VT*>(base), g, ok && g < ngroups, 0, VT{});
         }
     }
     // sum over this lane's rows of x_r * u_r (u in LDS, indexed from j0)
@@ -628,7 +637,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     // the previous step's partials first: the loads below are independent of
     // them and of each other, so one memory round trip covers them all
     // (npart <= kFusedThreads partials: one per thread)
-    const ColPartial cp0 = tid < npart ? part_in[tid] : ColPartial{-1.0, INT32_MAX, 0, 0.0, 0.0};
+    const ColPartial cp0 = load_or(part_in, tid, tid < npart, 0, ColPartial{-1.0, INT32_MAX, 0, 0.0, 0.0});
 
     // this wave's columns and their per-column data, independent of the pivot
     // (loaded whatever the column's state; used only for alive columns)
@@ -639,13 +648,13 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     for (int ps = 0; ps < NP; ++ps) {
         col[ps] = (int64_t)wg * 32 * NP + (int64_t)wave * 4 * NP + ps * 4 + grp;
         in[ps] = col[ps] < n;
-        nuc[ps] = in[ps] ? nu[col[ps]] : -1.0;
-        nrf[ps] = in[ps] ? nuref[col[ps]] : 1.0;
-        sjc[ps] = in[ps] ? (double)S[col[ps] * ldw + j] : 0.0;
+        nuc[ps] = load_or(nu, col[ps], in[ps], 0, -1.0);
+        nrf[ps] = load_or(nuref, col[ps], in[ps], 0, 1.0);
+        sjc[ps] = (double)load_or(S, col[ps] * ldw + j, in[ps], 0, T(0));
 #pragma unroll
         for (int s = 0; s < kFusedMaxNb / 16; ++s) {
             const int q = l16 + 16 * s;
-            fq[ps][s] = (in[ps] && q < i) ? (double)F[col[ps] * nb + q] : 0.0;
+            fq[ps][s] = (double)load_or(F, col[ps] * nb + q, in[ps] && q < i, 0, T(0));
         }
     }
     // the first two column chunks and V[:, 0:i] (GL 16-byte groups per
@@ -653,13 +662,13 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     // pivot is found
     ColChunk<T, GL> buf[2];
 #pragma unroll
-    for (int ps = 0; ps < (NP < 2 ? NP : 2); ++ps) buf[ps].load(in[ps] ? S + col[ps] * ldw + j0 : nullptr, ngroups, l16);
+    for (int ps = 0; ps < (NP < 2 ? NP : 2); ++ps) buf[ps].load(in[ps] ? S + col[ps] * ldw + j0 : S, in[ps], ngroups, l16);
     const int64_t vtot = (ldw / VEC) * i;
     VT vst[GL];
 #pragma unroll
     for (int k = 0; k < GL; ++k) {
         const int64_t e = tid + (int64_t)k * kFusedThreads;
-        vst[k] = e < vtot ? reinterpret_cast<const VT*>(V)[e] : VT{};
+        vst[k] = load_or(reinterpret_cast<const VT*>(V), e, e < vtot, 0, VT{});
     }
 
     // 1. pivot from the previous step's partials
@@ -714,10 +723,18 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     }
     const int64_t p = best.i;
 
-    // 2. u = S[:, p] - V F[p, :]^T (rows j..m-1), the reflector
-    const int64_t r0 = tid;
-    const double sp0 = (r0 >= j && r0 < m) ? (double)S[r0 + p * ldw] : 0.0;
-    if (tid < i) s_F[tid] = (double)F[p * nb + tid];
+    // 2. u = S[:, p] - V F[p, :]^T (rows j..m-1), the reflector; the pivot
+    // column's rows (two per thread at most: ldw <= 2 x 512) and F[p, 0:i]
+    // are loaded together
+    static_assert(kFusedMaxRows <= 2 * kFusedThreads, "two pivot-column rows per thread at most");
+    double spc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t r = tid + (int64_t)h * kFusedThreads;
+        spc[h] = (double)load_or(S, r + p * ldw, r >= j && r < m, p * ldw, T(0));
+    }
+    const double fp = (double)load_or(F, p * nb + tid, tid < i, p * nb, T(0));
+    if (tid < i) s_F[tid] = fp;
 #pragma unroll
     for (int k = 0; k < GL; ++k) {
         const int64_t e = tid + (int64_t)k * kFusedThreads;
@@ -726,10 +743,13 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     lds_barrier();  // s_F, sV (and the w_* reads above are done)
     if (tid < i) s_vj[tid] = (double)sV[j + (int64_t)tid * ldw];
     double ss = 0.0;
-    for (int64_t r = tid; r < ldw; r += kFusedThreads) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t r = tid + (int64_t)h * kFusedThreads;
+        if (r >= ldw) break;
         double x = 0.0;
         if (r >= j && r < m) {
-            x = r == r0 ? sp0 : (double)S[r + p * ldw];
+            x = spc[h];
 #pragma unroll 8
             for (int q = 0; q < i; ++q) x -= (double)sV[r + (int64_t)q * ldw] * s_F[q];
             x = (double)(T)x;
@@ -774,7 +794,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     for (int ps = 0; ps < NP; ++ps) {
         const bool alive = in[ps] && col[ps] != p && nuc[ps] >= 0.0;
         acc[ps] = alive ? buf[ps & 1].dot(su, ngroups, l16) : 0.0;
-        if (ps + 2 < NP) buf[ps & 1].load(in[ps + 2] ? S + col[ps + 2] * ldw + j0 : nullptr, ngroups, l16);
+        if (ps + 2 < NP) buf[ps & 1].load(in[ps + 2] ? S + col[ps + 2] * ldw + j0 : S, in[ps + 2], ngroups, l16);
     }
     {
         const int q = 4 * wave + grp;
@@ -1108,7 +1128,8 @@ __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, in
             const int e = e0 + u * NT;
             const int q = e / NC, c = e % NC;
             const bool zc = JMODE == 1 && e < kend * NC && s_sel[c] >= 0;
-            v[u] = (e < kend * NC && q < K && c0 + c < n && !zc) ? (double)R[(int64_t)q * rs + (c0 + c) * cs] : 0.0;
+            v[u] = (double)load_or(R, (int64_t)q * rs + (c0 + c) * cs, e < kend * NC && q < K && c0 + c < n && !zc, 0,
+                                   T(0));
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -1161,7 +1182,7 @@ __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, in
                 if (sweep == 0)
                     acc[e] = sX[row * NCP + tc + l16];
                 else
-                    acc[e] = (row < K && col < n) ? (double)R[(int64_t)row * rs + col * cs] : 0.0;
+                    acc[e] = (double)load_or(R, (int64_t)row * rs + col * cs, row < K && col < n, 0, T(0));
             }
             // one kTB-deep slice of R11 at a time (kend - kstart is a
             // multiple of kTB): its eight operand loads are all in flight
@@ -1332,11 +1353,12 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
         P->fgl = per_lane <= 5 ? 5 : (per_lane <= 9 ? 9 : 0);
     }
     P->fused = P->ldw <= kFusedMaxRows && P->fgl > 0 && P->nb <= kFusedMaxNb && fused_enabled(o->flags);
-    // blocked path: FP32 16 and FP64 64 timed fastest for 4096 x 16384 IDs
-    // (FP64: three trailing updates instead of seven, each reading and
-    // writing the trailing matrix once); the fused path keeps 32 (fewer
-    // roundings of the eagerly updated trailing matrix for the same time)
-    if (o->nb == 0 && !P->fused) P->nb = dtype == MIID_F32 ? 16 : 64;
+    // blocked path: FP32 16 and FP64 32 timed fastest for 4096 x 16384 IDs
+    // (FP64 with 64: 26.3 against 25.8 ms -- four fewer trailing updates, but
+    // the pivot kernel's few workgroups read twice the panel rows per step);
+    // the fused path keeps 32 (fewer roundings of the eagerly updated
+    // trailing matrix for the same time)
+    if (o->nb == 0 && dtype == MIID_F32 && !P->fused) P->nb = 16;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o2 = off;
@@ -1434,7 +1456,9 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
     MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 64, true>, 256 * 65 * 8));
     MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 32, true>, 512 * 33 * 8));
     MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 16, true>, 1024 * 17 * 8));
-    MIID_HIP(lds_limit_once((const void*)k_pivot_col<T>, kThreads * (kMaxNb + 1) * 8));
+    MIID_HIP(lds_limit_once((const void*)k_pivot_col<T, 16>, kThreads * (16 + 1) * 8));
+    MIID_HIP(lds_limit_once((const void*)k_pivot_col<T, 32>, kThreads * (32 + 1) * 8));
+    MIID_HIP(lds_limit_once((const void*)k_pivot_col<T, kMaxNb>, kThreads * (kMaxNb + 1) * 8));
 
     // control block, R rows
     hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(64), 0, stream, reinterpret_cast<unsigned char*>(st),
@@ -1510,9 +1534,18 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
         const int jb = (j / nb) * nb;
         const int i = j - jb;
         int pr = prof_take(MIID_K_PIVOT, j, m - j, 1);
-        MIID_LAUNCH(pr, k_pivot_col<T>, dim3(P.NA), dim3(kThreads), (size_t)kThreads * (nb + 1) * 8, stream, S, ldw, m,
-                    V, F, nb, u, part,
-                    P.npart, partA, st, J, j, i, (int)P.tol, P.eps);
+        {
+            const size_t lds = (size_t)kThreads * (nb + 1) * 8;
+            if (nb <= 16)
+                MIID_LAUNCH(pr, (k_pivot_col<T, 16>), dim3(P.NA), dim3(kThreads), lds, stream, S, ldw, m, V, F, nb, u,
+                            part, P.npart, partA, st, J, j, i, (int)P.tol, P.eps);
+            else if (nb <= 32)
+                MIID_LAUNCH(pr, (k_pivot_col<T, 32>), dim3(P.NA), dim3(kThreads), lds, stream, S, ldw, m, V, F, nb, u,
+                            part, P.npart, partA, st, J, j, i, (int)P.tol, P.eps);
+            else
+                MIID_LAUNCH(pr, (k_pivot_col<T, kMaxNb>), dim3(P.NA), dim3(kThreads), lds, stream, S, ldw, m, V, F, nb,
+                            u, part, P.npart, partA, st, J, j, i, (int)P.tol, P.eps);
+        }
         pr = prof_take(MIID_K_GEMV, j, m - j, n - j);
         switch (P.cpw) {
             case 4:
@@ -2037,10 +2070,22 @@ __global__ void __launch_bounds__(256) k_chol_update(double* __restrict__ G, int
     const int t0 = r0 + kChB;
     const int i0 = t0 + bi * 64, c0 = t0 + bc * 64;
     __shared__ double sRi[kChB][65], sRc[kChB][65];
-    for (int e = threadIdx.x; e < kChB * 64; e += 256) {
+    // both tiles' loads in flight together, then into LDS
+    constexpr int kPer = kChB * 64 / 256;
+    static_assert(kChB * 64 % 256 == 0, "whole passes of the tile copy");
+    double ri[kPer], rc[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int e = threadIdx.x + 256 * t;
         const int j = e % kChB, x = e / kChB;
-        sRi[j][x] = i0 + x < k ? R[(r0 + j) + (int64_t)(i0 + x) * ldr] : 0.0;
-        sRc[j][x] = c0 + x < k ? R[(r0 + j) + (int64_t)(c0 + x) * ldr] : 0.0;
+        ri[t] = load_or(R, (r0 + j) + (int64_t)(i0 + x) * ldr, i0 + x < k, 0, 0.0);
+        rc[t] = load_or(R, (r0 + j) + (int64_t)(c0 + x) * ldr, c0 + x < k, 0, 0.0);
+    }
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int e = threadIdx.x + 256 * t;
+        sRi[e % kChB][e / kChB] = ri[t];
+        sRc[e % kChB][e / kChB] = rc[t];
     }
     __syncthreads();
     const int ti = (threadIdx.x % 16) * 4, tc = (threadIdx.x / 16) * 4;
@@ -2062,12 +2107,21 @@ __global__ void __launch_bounds__(256) k_chol_update(double* __restrict__ G, int
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
     }
+    // the sixteen G loads together, then the stores
+    double g[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int i = i0 + ti + u, c = c0 + tc + v;
-            if (i < k && c < k && i <= c) G[(int64_t)i * k + c] -= acc[u][v];
+            g[u][v] = load_or(G, (int64_t)i * k + c, i < k && c < k && i <= c, 0, 0.0);
+        }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + ti + u, c = c0 + tc + v;
+            if (i < k && c < k && i <= c) G[(int64_t)i * k + c] = g[u][v] - acc[u][v];
         }
 }
 
