@@ -67,7 +67,8 @@ typedef enum { MIID_F32 = 0, MIID_F64 = 1 } miid_dtype;
  *  CPW   id_cpqr/rid: columns per wave of the two-launch blocked path's
  *        F-GEMV (1, 2 or 4)
  *  NP    id_cpqr/rid: column passes per wave of the one-launch fused path
- *        for short matrices (1, 2 or 4)
+ *        for short matrices (1, 2, 4 or 8; default: the fewest that give
+ *        one workgroup per CU)
  *  PATH  id_cpqr/rid: 1 = blocked two-launch path, 2 = fused path (taken
  *        only where eligible: at most 576 rows in FP32 / 288 in FP64,
  *        panels of at most 32)

@@ -61,7 +61,7 @@ def id_candidates(m: int, n: int, dtype: torch.dtype, for_rid: bool = False):
         out.append((f"blocked nb={nb} cpw={cpw}", nb,
                     H(_abi.MIID_HINT_PATH_SHIFT, 1) | H(_abi.MIID_HINT_CPW_SHIFT, cpw)))
     if fused_ok:
-        for nb, np_ in itertools.product((16, 32), (1, 2, 4)):
+        for nb, np_ in itertools.product((16, 32), (1, 2, 4, 8)):
             out.append((f"fused nb={nb} np={np_}", nb,
                         H(_abi.MIID_HINT_PATH_SHIFT, 2) | H(_abi.MIID_HINT_NP_SHIFT, np_)))
     return out

@@ -640,7 +640,12 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     const ColPartial cp0 = load_or(part_in, tid, tid < npart, 0, ColPartial{-1.0, INT32_MAX, 0, 0.0, 0.0});
 
     // this wave's columns and their per-column data, independent of the pivot
-    // (loaded whatever the column's state; used only for alive columns)
+    // (loaded whatever the column's state; used only for alive columns).
+    // Up to four passes per wave the data is loaded here, in flight with the
+    // partials; with eight (one workgroup per CU over the widest matrices) it
+    // is loaded after the dot products, when the column chunks no longer hold
+    // registers.
+    constexpr bool kLate = NP > 4;
     int64_t col[NP];
     bool in[NP];
     double nuc[NP], nrf[NP], sjc[NP], fq[NP][kFusedMaxNb / 16];
@@ -648,15 +653,21 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     for (int ps = 0; ps < NP; ++ps) {
         col[ps] = (int64_t)wg * 32 * NP + (int64_t)wave * 4 * NP + ps * 4 + grp;
         in[ps] = col[ps] < n;
-        nuc[ps] = load_or(nu, col[ps], in[ps], 0, -1.0);
-        nrf[ps] = load_or(nuref, col[ps], in[ps], 0, 1.0);
-        sjc[ps] = (double)load_or(S, col[ps] * ldw + j, in[ps], 0, T(0));
-#pragma unroll
-        for (int s = 0; s < kFusedMaxNb / 16; ++s) {
-            const int q = l16 + 16 * s;
-            fq[ps][s] = (double)load_or(F, col[ps] * nb + q, in[ps] && q < i, 0, T(0));
-        }
     }
+    auto load_cols = [&]() {
+#pragma unroll
+        for (int ps = 0; ps < NP; ++ps) {
+            nuc[ps] = load_or(nu, col[ps], in[ps], 0, -1.0);
+            nrf[ps] = load_or(nuref, col[ps], in[ps], 0, 1.0);
+            sjc[ps] = (double)load_or(S, col[ps] * ldw + j, in[ps], 0, T(0));
+#pragma unroll
+            for (int s = 0; s < kFusedMaxNb / 16; ++s) {
+                const int q = l16 + 16 * s;
+                fq[ps][s] = (double)load_or(F, col[ps] * nb + q, in[ps] && q < i, 0, T(0));
+            }
+        }
+    };
+    if (!kLate) load_cols();
     // the first two column chunks and V[:, 0:i] (GL 16-byte groups per
     // thread at most: i ldw / VEC <= 32 * 16 GL) are in flight while the
     // pivot is found
@@ -792,10 +803,12 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     double acc[NP];
 #pragma unroll
     for (int ps = 0; ps < NP; ++ps) {
-        const bool alive = in[ps] && col[ps] != p && nuc[ps] >= 0.0;
+        // (kLate: every column in range; the dead ones' sums go unused)
+        const bool alive = kLate ? in[ps] : (in[ps] && col[ps] != p && nuc[ps] >= 0.0);
         acc[ps] = alive ? buf[ps & 1].dot(su, ngroups, l16) : 0.0;
         if (ps + 2 < NP) buf[ps & 1].load(in[ps + 2] ? S + col[ps + 2] * ldw + j0 : S, in[ps + 2], ngroups, l16);
     }
+    if (kLate) load_cols();
     {
         const int q = 4 * wave + grp;
         double a = 0.0;
@@ -1314,10 +1327,10 @@ static bool fused_enabled(uint32_t flags) {
 
 static int fused_np(int64_t n, uint32_t flags) {
     const int h = (int)((flags >> MIID_HINT_NP_SHIFT) & 15u);
-    if (h == 1 || h == 2 || h == 4) return h;
-    for (int v = 1; v <= 4; v *= 2)
+    if (h == 1 || h == 2 || h == 4 || h == 8) return h;
+    for (int v = 1; v <= 8; v *= 2)
         if (n <= (int64_t)256 * 32 * v) return v;  // one workgroup per CU
-    return 4;
+    return 8;
 }
 
 int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan* P) {
@@ -1415,6 +1428,9 @@ static hipError_t launch_fused(const IdPlan& P, int pr, hipStream_t stream, T* S
                                ColPartial* pout, int npin, DevState* st, int32_t* J, T* R, double* nu, double* nuref,
                                int32_t* sel, int32_t* recomp, int j, int i, double tol) {
     switch (P.fnp) {
+        case 8:
+            return launch_fused_np<T, 8>(P, pr, stream, S, V, F, pin, pout, npin, st, J, R, nu, nuref, sel, recomp,
+                                         j, i, tol);
         case 4:
             return launch_fused_np<T, 4>(P, pr, stream, S, V, F, pin, pout, npin, st, J, R, nu, nuref, sel, recomp,
                                          j, i, tol);
