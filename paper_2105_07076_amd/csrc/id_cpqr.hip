@@ -382,8 +382,10 @@ __global__ void __launch_bounds__(kThreads) k_gemv(const T* __restrict__ S, int6
         sjc[c] = alive[c] ? (double)S[col * ldw + j] : 0.0;
     }
 
-    // a5: acc_c = S[j0:, col_c] . u  (u is zero at rows <= j and >= m)
-    const int64_t j0 = (int64_t)j & ~(int64_t)(VEC - 1);
+    // a5: acc_c = S[j0:, col_c] . u  (u is zero at rows <= j and >= m).  j0
+    // is j rounded down to a 128-byte line, so that no line is split between
+    // two of a wave's loads (nontemporal loads would fetch it twice)
+    const int64_t j0 = (int64_t)j & ~(int64_t)(128 / sizeof(T) - 1);
     double acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0;
@@ -631,7 +633,8 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     const int wg = blockIdx.x;
     const int stop_in = st->stop;
     const double a_prev = st->a_norm;
-    const int64_t j0 = (int64_t)j & ~(int64_t)(VEC - 1);
+    // rows from j rounded down to a 128-byte line (u is zero at rows <= j)
+    const int64_t j0 = (int64_t)j & ~(int64_t)(128 / sizeof(T) - 1);
     const int64_t ngroups = (ldw - j0) / VEC;  // VEC-row groups from j0
 
     // the previous step's partials first: the loads below are independent of
