@@ -83,10 +83,10 @@ def time_id(miid_api, lib, A, k, steps, warmup, sample_every=7):
 # passes (scaled against a copy kernel of known size), valid only for the
 # kernel sources they were taken on.
 GEMV_TRAFFIC = {
-    "bytes_per_launch": 529.2e6,
+    "bytes_per_launch": 525.0e6,
     "sources": {
-        "paper_2105_07076_amd/csrc/id_cpqr.hip": "a914d41fe212e5f5da15d86ab7195f002507cc01fc2a54c3386b559e4134ff9c",
-        "paper_2105_07076_amd/csrc/common.hpp": "77e3f522d4607da471046f7b4d08b5688ce5617e1b620ace976254481bb74ae8",
+        "paper_2105_07076_amd/csrc/id_cpqr.hip": "30aec0b7425c0563db1acaef0606ac76daede5e86b580d3eb87e532784ea4423",
+        "paper_2105_07076_amd/csrc/common.hpp": "0f5a1f0dd742bf6d093d0f5b159aefe48206eed4d5fa8e86ea568ab9a9b55d8a",
         "paper_2105_07076_amd/csrc/cpqr.hpp": "4c711f839dd9776cb750a3adfc41feef2cc6f5b5b9a0c07a6ebb4c9d7bd055d9",
     },
 }
