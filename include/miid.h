@@ -70,7 +70,7 @@ typedef enum { MIID_F32 = 0, MIID_F64 = 1 } miid_dtype;
  *        for short matrices (1, 2, 4 or 8; default: the fewest that give
  *        one workgroup per CU)
  *  PATH  id_cpqr/rid: 1 = blocked two-launch path, 2 = fused path (taken
- *        only where eligible: at most 576 rows in FP32 / 288 in FP64,
+ *        only where eligible: at most 576 rows in FP32 / 320 in FP64,
  *        panels of at most 32)
  *  LPC   id_batched: cap on the lanes that share one column of a block
  *        (1, 2, 4 or 8; default 8: as many as n L <= 512 allows).  It

@@ -52,10 +52,10 @@ def _time(fn, reps: int) -> float:
 def id_candidates(m: int, n: int, dtype: torch.dtype, for_rid: bool = False):
     """(label, nb, hints) candidates for an ID whose CPQR works on m x n
     (m <= n after the transpose rule).  The fused path exists for at most
-    576 rows in FP32 (288 in FP64) and panels of at most 32."""
+    576 rows in FP32 (320 in FP64) and panels of at most 32."""
     esz = 4 if (for_rid or dtype == torch.float32) else 8
     ldw = (m + 63) // 64 * 64
-    fused_ok = ldw * esz <= 576 * 4 and (ldw * esz // 16 + 15) // 16 <= 9
+    fused_ok = ldw <= 576 and (ldw * esz // 16 + 15) // 16 <= (10 if esz == 8 else 9)
     out = []
     for nb, cpw in itertools.product((16, 32, 48, 64), (1, 2, 4)):
         out.append((f"blocked nb={nb} cpw={cpw}", nb,

@@ -21,10 +21,10 @@ struct IdPlan {
     size_t esz;
     int cpw;   // columns per wave in the column passes (k_norms, k_gemv)
     int npart, NA;
-    // fused one-launch-per-step path (at most 1024 rows): NP passes of four
+    // fused one-launch-per-step path (at most 576 rows): NP passes of four
     // columns per wave, fnpart workgroups
     bool fused;
-    int fnp, fnpart, fgl;  // fgl: 16-byte row groups per lane (5, 9 or 16)
+    int fnp, fnpart, fgl;  // fgl: 16-byte row groups per lane (5, 9 or 10)
     int kpad;  // kmax rounded up to the triangular solve's diagonal block
     size_t oS, oV, oF, ou, onu, onuref, oR, osel, opart, opartA, oR11, oDinv, ostate, orec, total;
 };

@@ -215,13 +215,18 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
     // go out now, behind the partials (so waiting for those does not wait
     // for these)
     // (columns q >= i load column i - 1 again, a cache hit, so that the
-    // loads need no branch and the traffic stays i columns)
+    // loads need no branch and the traffic stays i columns).  Beyond 32
+    // columns the rest is loaded with the pivot column, once the partials no
+    // longer hold registers.
+    constexpr int NLO = NBT > 32 ? 32 : NBT;
     double vr[NBT];
     const int64_t rv = r < ldw ? r : 0;
     const int qlast = i > 0 ? i - 1 : 0;
-#pragma unroll
-    for (int q = 0; q < NBT; ++q)
+    auto load_vr = [&](int q) {
         vr[q] = (double)load_or(V, r + (int64_t)q * ldw, active && q < i, rv + (int64_t)min(q, qlast) * ldw, T(0));
+    };
+#pragma unroll
+    for (int q = 0; q < NLO; ++q) load_vr(q);
 #pragma unroll
     for (int k = 0; k < kPU; ++k) {
         if (argmax_better(cp[k].best, cp[k].idx, best.v, best.i)) best = {cp[k].best, cp[k].idx};
@@ -271,6 +276,8 @@ __global__ void __launch_bounds__(kThreads) k_pivot_col(const T* __restrict__ S,
     }
     if (stop) return;
     const int64_t p = best.i;
+#pragma unroll
+    for (int q = NLO; q < NBT; ++q) load_vr(q);
     const double spr = (double)load_or(S, r + p * ldw, active, p * ldw, T(0));
     const double fp = (double)load_or(F, p * nb + tid, tid < i, p * nb, T(0));
     if (tid < i) s_F[tid] = fp;
@@ -550,7 +557,7 @@ __global__ void __launch_bounds__(kThreads) k_gemv(const T* __restrict__ S, int6
 
 // ---------------------------------------------------------------------------
 // a2-a6 (+ a8) in one launch per step for short matrices (the sketch Y of the
-// randomized ID, short IDs: at most 576 rows in FP32, 288 in FP64, panels of
+// randomized ID, short IDs: at most 576 rows in FP32, 320 in FP64, panels of
 // at most 32).  The working matrix then sits in the L2 caches and the step is
 // latency-bound: the separate pivot kernel's launch and its reduction over
 // thousands of partials cost more than the GEMV.  Here every workgroup (8
@@ -645,10 +652,10 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     // this wave's columns and their per-column data, independent of the pivot
     // (loaded whatever the column's state; used only for alive columns).
     // Up to four passes per wave the data is loaded here, in flight with the
-    // partials; with eight (one workgroup per CU over the widest matrices) it
-    // is loaded after the dot products, when the column chunks no longer hold
-    // registers.
-    constexpr bool kLate = NP > 4;
+    // partials; with eight (one workgroup per CU over the widest matrices),
+    // or four of the tallest FP64 columns, it is loaded after the dot
+    // products, when the column chunks no longer hold registers.
+    constexpr bool kLate = NP > 4 || (NP == 4 && GL >= 10);
     int64_t col[NP];
     bool in[NP];
     double nuc[NP], nrf[NP], sjc[NP], fq[NP][kFusedMaxNb / 16];
@@ -1366,7 +1373,8 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
         // 16-byte row groups per lane of a 16-lane column group
         const int64_t ng = P->ldw * (int64_t)P->esz / 16;  // 16-byte groups in a column
         const int64_t per_lane = (ng + 15) / 16;
-        P->fgl = per_lane <= 5 ? 5 : (per_lane <= 9 ? 9 : 0);
+        // (ten only in FP64: up to 320 rows; FP32 reaches 576 rows with nine)
+        P->fgl = per_lane <= 5 ? 5 : (per_lane <= 9 ? 9 : (per_lane <= 10 && P->esz == 8 ? 10 : 0));
     }
     P->fused = P->ldw <= kFusedMaxRows && P->fgl > 0 && P->nb <= kFusedMaxNb && fused_enabled(o->flags);
     // blocked path: FP32 16 and FP64 32 timed fastest for 4096 x 16384 IDs
@@ -1422,6 +1430,11 @@ static hipError_t launch_fused_np(const IdPlan& P, int pr, hipStream_t stream, T
     if (P.fgl == 5)
         return launch_fused_k<T, NP, 5>(P, pr, stream, S, V, F, pin, pout, npin, st, J, R, nu, nuref, sel, recomp, j,
                                         i, tol);
+    if constexpr (sizeof(T) == 8) {
+        if (P.fgl == 10)
+            return launch_fused_k<T, NP, 10>(P, pr, stream, S, V, F, pin, pout, npin, st, J, R, nu, nuref, sel, recomp,
+                                             j, i, tol);
+    }
     return launch_fused_k<T, NP, 9>(P, pr, stream, S, V, F, pin, pout, npin, st, J, R, nu, nuref, sel, recomp, j, i,
                                     tol);
 }

@@ -25,9 +25,14 @@ def test_id_candidates():
     c2 = autotune.id_candidates(4096, 16384, torch.float64)
     assert all(lbl.startswith("blocked") for lbl, _, _ in c2)
     assert {nb for _, nb, _ in c2} == {16, 32, 48, 64}
-    # FP64 with 320 rows (ldw 320: 16-byte groups per lane 10 > 9): blocked only
+    # FP64: 320 rows (ten 16-byte groups per lane) still fused, 321 not
     c3 = autotune.id_candidates(300, 1000, torch.float64)
-    assert all(lbl.startswith("blocked") for lbl, _, _ in c3)
+    assert any(lbl.startswith("fused") for lbl, _, _ in c3)
+    c4 = autotune.id_candidates(321, 1000, torch.float64)
+    assert all(lbl.startswith("blocked") for lbl, _, _ in c4)
+    # FP32 reaches 576 rows
+    assert any(lbl.startswith("fused") for lbl, _, _ in autotune.id_candidates(576, 4096, torch.float32))
+    assert all(lbl.startswith("blocked") for lbl, _, _ in autotune.id_candidates(577, 4096, torch.float32))
     assert len(autotune.batched_candidates()) == 4
 
 

@@ -31,7 +31,7 @@ def kappa_tol(ref, dtype, floor):
 
 @pytest.fixture(params=["fused", "blocked"])
 def path(request):
-    """The PATH hint for the call: matrices of at most 576 rows (FP32) / 288
+    """The PATH hint for the call: matrices of at most 576 rows (FP32) / 320
     (FP64) take the fused one-launch-per-step kernel unless the hint asks for
     the two-launch blocked path."""
     from paper_2105_07076_amd import _abi
@@ -107,6 +107,15 @@ def test_random_shapes(dtype, m, n, k, path):
     g = idgen.rng(7 * m + n)
     A = g.standard_normal((m, n)) * (0.97 ** np.arange(n))[None, :]
     _check_id(A, k, dtype, exact_pivots=False, hints=path)
+
+
+@pytest.mark.parametrize("m", [289, 320])
+def test_fp64_fused_tallest(m, path):
+    # 289..320 rows in FP64: ten 16-byte groups per lane of a column group on
+    # the fused path; planted so that the pivots are exact
+    A, planted, U, perm = idgen.planted_id(11 + m, m, 1500, 96, r=0.93)
+    r, ref, _ = _check_id(A, 96, torch.float64, hints=path)
+    assert list(to_np(r.J)) == list(planted)
 
 
 def test_dual_tall_matrix(path):
