@@ -220,14 +220,27 @@ __device__ __forceinline__ double get(const float4& v, int e) {
 __device__ __forceinline__ bool is_finite_d(double x) { return !(isnan(x) || isinf(x)); }
 
 // p[idx] where ok, else `other`, with no branch: the load always issues (from
-// p[safe], a valid element, where !ok) and the choice is a select.  A load
-// written under a condition becomes a branch whose other side writes the same
-// register, and the compiler then waits for the load before that write, so a
-// run of such loads goes out one memory round trip at a time.
+// p[safe], a valid element, where !ok) and the choice is a bitwise merge
+// under a mask the compiler cannot see through.  A load written under a
+// condition becomes a branch whose other side writes the same register, and
+// the compiler then waits for the load before that write, so a run of such
+// loads goes out one memory round trip at a time; a plain select on the
+// loaded value is turned back into such a branch.
 template <typename X>
 __device__ __forceinline__ X load_or(const X* p, int64_t idx, bool ok, int64_t safe, X other) {
+    static_assert(sizeof(X) % 4 == 0, "whole 32-bit words");
+    constexpr int W = (int)(sizeof(X) / 4);
     const X v = p[ok ? idx : safe];
-    return ok ? v : other;
+    uint32_t m = ok ? 0xffffffffu : 0u;
+    asm volatile("" : "+v"(m));
+    uint32_t a[W], b[W];
+    __builtin_memcpy(a, &v, sizeof(X));
+    __builtin_memcpy(b, &other, sizeof(X));
+#pragma unroll
+    for (int w = 0; w < W; ++w) a[w] = (a[w] & m) | (b[w] & ~m);
+    X r;
+    __builtin_memcpy(&r, a, sizeof(X));
+    return r;
 }
 
 }  // namespace miid

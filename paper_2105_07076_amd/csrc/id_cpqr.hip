@@ -653,9 +653,10 @@ __global__ void __launch_bounds__(kFusedThreads) k_step_fused(const T* __restric
     // (loaded whatever the column's state; used only for alive columns).
     // Up to four passes per wave the data is loaded here, in flight with the
     // partials; with eight (one workgroup per CU over the widest matrices),
-    // or four of the tallest FP64 columns, it is loaded after the dot
-    // products, when the column chunks no longer hold registers.
-    constexpr bool kLate = NP > 4 || (NP == 4 && GL >= 10);
+    // or four over columns of nine or ten 16-byte groups per lane, it is
+    // loaded after the dot products, when the column chunks no longer hold
+    // registers.
+    constexpr bool kLate = NP > 4 || (NP == 4 && GL >= 9);
     int64_t col[NP];
     bool in[NP];
     double nuc[NP], nrf[NP], sjc[NP], fq[NP][kFusedMaxNb / 16];
