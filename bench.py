@@ -85,9 +85,9 @@ def time_id(miid_api, lib, A, k, steps, warmup, sample_every=7):
 GEMV_TRAFFIC = {
     "bytes_per_launch": 525.0e6,
     "sources": {
-        "paper_2105_07076_amd/csrc/id_cpqr.hip": "30aec0b7425c0563db1acaef0606ac76daede5e86b580d3eb87e532784ea4423",
-        "paper_2105_07076_amd/csrc/common.hpp": "0f5a1f0dd742bf6d093d0f5b159aefe48206eed4d5fa8e86ea568ab9a9b55d8a",
-        "paper_2105_07076_amd/csrc/cpqr.hpp": "4c711f839dd9776cb750a3adfc41feef2cc6f5b5b9a0c07a6ebb4c9d7bd055d9",
+        "paper_2105_07076_amd/csrc/id_cpqr.hip": "c9c2acaf7e646a5c75c7c77fe83104416a3c3808fe63e5cd6169b6ba8acb9d47",
+        "paper_2105_07076_amd/csrc/common.hpp": "bba9391732c3ff7fbbc98bd9a751dabbe8faba50964622b34c3c3b794be5ddcb",
+        "paper_2105_07076_amd/csrc/cpqr.hpp": "f0aff2f110aba8d622a1c3591023c3d7431d8b68d0e390a3ac64a861375c2f9f",
     },
 }
 

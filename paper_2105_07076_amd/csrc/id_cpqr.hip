@@ -369,24 +369,26 @@ __global__ void __launch_bounds__(kThreads) k_gemv(const T* __restrict__ S, int6
 #pragma unroll
     for (int k = 0; k < kPrefetchA; ++k) {
         const int e = tid + k * kThreads;
-        pa[k] = e < na ? partA[(int64_t)(e / (i + 1)) * kPartAStride + e % (i + 1)] : 0.0;
+        pa[k] = load_or(partA, (int64_t)(e / (i + 1)) * kPartAStride + e % (i + 1), e < na, 0, 0.0);
     }
     const double u0 = (double)u[ldw];
-    const double vjq = tid < i ? (double)V[j + (int64_t)tid * ldw] : 0.0;
+    const double vjq = (double)load_or(V, j + (int64_t)tid * ldw, tid < i, 0, T(0));
 
-    // per-column scalars, loaded together before the stream
+    // per-column scalars, loaded together before the stream (on the range
+    // only: none of these loads waits for another; reading the dead columns
+    // too, to spare the stream the wait for their norms, cost more)
     bool alive[C];
     double fq[C], nuc[C], nrf[C], sjc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int64_t col = col0 + c;
         const bool in = col < n;
-        const double nv = in ? nu[col] : -1.0;
-        alive[c] = in && col != p && nv >= 0.0;
+        const double nv = load_or(nu, col, in, 0, -1.0);
+        nrf[c] = load_or(nuref, col, in, 0, 1.0);
+        fq[c] = (double)load_or(F, col * nb + lane, in && lane < i, 0, T(0));
+        sjc[c] = (double)load_or(S, col * ldw + j, in, 0, T(0));
         nuc[c] = nv;
-        nrf[c] = alive[c] ? nuref[col] : 1.0;
-        fq[c] = (alive[c] && lane < i) ? (double)F[col * nb + lane] : 0.0;
-        sjc[c] = alive[c] ? (double)S[col * ldw + j] : 0.0;
+        alive[c] = in && col != p && nv >= 0.0;
     }
 
     // a5: acc_c = S[j0:, col_c] . u  (u is zero at rows <= j and >= m).  j0
