@@ -118,6 +118,16 @@ def test_fp64_fused_tallest(m, path):
     assert list(to_np(r.J)) == list(planted)
 
 
+@pytest.mark.parametrize("dtype,m", [(torch.float32, 400), (torch.float64, 300)])
+def test_fused_four_passes_tall_columns(dtype, m, path):
+    # 20000 columns: four column passes per wave on the fused path; 400 FP32
+    # rows (nine 16-byte groups per lane) and 300 FP64 rows (ten) load their
+    # per-column data after the dot products
+    A, planted, U, perm = idgen.planted_id(31 + m, m, 20000, 64, r=0.95)
+    r, ref, _ = _check_id(A, 64, dtype, hints=path)
+    assert list(to_np(r.J)) == list(planted)
+
+
 def test_dual_tall_matrix(path):
     g = idgen.rng(9)
     A = g.standard_normal((300, 120)) @ np.diag(0.93 ** np.arange(120))
