@@ -1359,8 +1359,7 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
     P->tol = o->k == 0;
     P->kmax = P->tol ? o->kmax : o->k;
     P->eps = o->eps;
-    // panel width: the caller's, else 32 (FP32 on the blocked path: 16, set
-    // below once the path is known)
+    // panel width: the caller's, else 32
     P->nb = o->nb != 0 ? o->nb : 32;
     P->refine = !(o->flags & MIID_NO_REFINE);
     if (P->nb > kMaxNb || P->kmax > P->m || P->kmax > P->n || P->kmax > kMaxK) return MIID_E_UNSUPPORTED;
@@ -1380,12 +1379,12 @@ int make_plan(int64_t M, int64_t N, miid_dtype dtype, const miid_opts* o, IdPlan
         P->fgl = per_lane <= 5 ? 5 : (per_lane <= 9 ? 9 : (per_lane <= 10 && P->esz == 8 ? 10 : 0));
     }
     P->fused = P->ldw <= kFusedMaxRows && P->fgl > 0 && P->nb <= kFusedMaxNb && fused_enabled(o->flags);
-    // blocked path: FP32 16 and FP64 32 timed fastest for 4096 x 16384 IDs
-    // (FP64 with 64: 26.3 against 25.8 ms -- four fewer trailing updates, but
-    // the pivot kernel's few workgroups read twice the panel rows per step);
-    // the fused path keeps 32 (fewer roundings of the eagerly updated
-    // trailing matrix for the same time)
-    if (o->nb == 0 && dtype == MIID_F32 && !P->fused) P->nb = 16;
+    // 32 also timed fastest on the blocked path for 4096 x 16384 IDs in both
+    // precisions (FP64 with 64: 26.3 against 25.8 ms -- four fewer trailing
+    // updates, but the pivot kernel's few workgroups read twice the panel
+    // rows per step; FP32 with 16: 13.8 against 13.7 ms); on the fused path
+    // it is also the fewest roundings of the eagerly updated trailing matrix
+    // for the same time
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o2 = off;
