@@ -102,12 +102,35 @@ template <int RT>
 struct StepReads;
 #define MIID_SK_RD(i) "ds_read_b128 %" #i ", %[aw] offset:" #i "*2048\n\t"
 template <>
+struct StepReads<3> {
+    __device__ __forceinline__ static void run(uint32_t aw, uint32_t aa0, uint32_t aa1, v4i_t (&w)[3], v4i_t& a0,
+                                               v4i_t& a1) {
+        asm volatile(MIID_SK_RD(0) MIID_SK_RD(1) MIID_SK_RD(2)
+                     "ds_read_b128 %[a0], %[aa0]\n\tds_read_b128 %[a1], %[aa1]\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2]), [a0] "=&v"(a0), [a1] "=&v"(a1)
+                     : [aw] "v"(aw), [aa0] "v"(aa0), [aa1] "v"(aa1)
+                     : "memory");
+    }
+};
+template <>
 struct StepReads<5> {
     __device__ __forceinline__ static void run(uint32_t aw, uint32_t aa0, uint32_t aa1, v4i_t (&w)[5], v4i_t& a0,
                                                v4i_t& a1) {
         asm volatile(MIID_SK_RD(0) MIID_SK_RD(1) MIID_SK_RD(2) MIID_SK_RD(3) MIID_SK_RD(4)
                      "ds_read_b128 %[a0], %[aa0]\n\tds_read_b128 %[a1], %[aa1]\n\ts_waitcnt lgkmcnt(0)"
                      : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2]), "=&v"(w[3]), "=&v"(w[4]), [a0] "=&v"(a0),
+                       [a1] "=&v"(a1)
+                     : [aw] "v"(aw), [aa0] "v"(aa0), [aa1] "v"(aa1)
+                     : "memory");
+    }
+};
+template <>
+struct StepReads<6> {
+    __device__ __forceinline__ static void run(uint32_t aw, uint32_t aa0, uint32_t aa1, v4i_t (&w)[6], v4i_t& a0,
+                                               v4i_t& a1) {
+        asm volatile(MIID_SK_RD(0) MIID_SK_RD(1) MIID_SK_RD(2) MIID_SK_RD(3) MIID_SK_RD(4) MIID_SK_RD(5)
+                     "ds_read_b128 %[a0], %[aa0]\n\tds_read_b128 %[a1], %[aa1]\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2]), "=&v"(w[3]), "=&v"(w[4]), "=&v"(w[5]), [a0] "=&v"(a0),
                        [a1] "=&v"(a1)
                      : [aw] "v"(aw), [aa0] "v"(aa0), [aa1] "v"(aa1)
                      : "memory");
@@ -141,12 +164,12 @@ struct StepReads<9> {
 };
 #undef MIID_SK_RD
 
-template <int NSPLIT, int RT, int WR, int WC, int NS>
-__global__ void __launch_bounds__(64 * WR * WC) k_sketch(const float* __restrict__ A, int64_t lda, int64_t m,
+template <int NSPLIT, int RT, int WR, int WC, int NS, int KG>
+__global__ void __launch_bounds__(64 * WR * WC * KG) k_sketch(const float* __restrict__ A, int64_t lda, int64_t m,
                                                          int64_t n, const uint16_t* __restrict__ Wt, int64_t mpad,
                                                          int rt_total, float* __restrict__ S, int64_t ldw,
                                                          float* __restrict__ Yout, int64_t ldy, int l) {
-    constexpr int NW = WR * WC;
+    constexpr int NW = WR * WC;            // waves of one K group
     constexpr int ROWS = WR * RT * 32;     // Omega rows of the workgroup
     constexpr int COLS = 32 * WC;          // columns of the workgroup
     constexpr int OM_BYTES = ROWS * 64;    // Omega chunk: ROWS x 32 bf16
@@ -157,7 +180,9 @@ __global__ void __launch_bounds__(64 * WR * WC) k_sketch(const float* __restrict
     constexpr int KS = kSkKC / kSkK;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
+    const int wave_all = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
+    const int kg = wave_all / NW;          // K group: chunks kg, kg + KG, kg + 2 KG, ...
+    const int wave = wave_all % NW;        // the wave within its group
     const int wr = wave % WR, wc = wave / WR;
     const int rt0 = wr * RT;
     const int nrt = min(RT, rt_total - rt0);  // this wave's row tiles (may be <= 0)
@@ -169,10 +194,16 @@ __global__ void __launch_bounds__(64 * WR * WC) k_sketch(const float* __restrict
         __builtin_amdgcn_make_buffer_rsrc((void*)(A + col0 * lda), (short)0, (int)arec, 0x00020000);
     const int nfull = (int)(m / kSkKC);       // chunks with every row < m
     const int nch = (int)(mpad / kSkKC);      // all chunks (mpad = m rounded up to 32)
+    const int nit = (nch + KG - 1) / KG;      // iterations: one chunk per K group each
+    unsigned char* const ring = smem_raw + kg * NS * STAGE;  // this group's ring
+    // the chunk of iteration i for this wave's group (>= nch: none)
+    auto chunk_of = [&](int i) { return KG * i + kg; };
 
-    // stage c of the ring: Omega rows and A columns of chunk c
-    auto issue = [&](int c) {
-        unsigned char* sb = smem_raw + (c % NS) * STAGE;
+    // stage i % NS of the group's ring: Omega rows and A columns of the
+    // chunk of iteration i
+    auto issue = [&](int i) {
+        unsigned char* sb = ring + (i % NS) * STAGE;
+        const int c = chunk_of(i);
         const int64_t k0 = (int64_t)c * kSkKC;
         const bool tail = c >= nfull;
         for (int ins = wave; ins < INS; ins += NW) {
@@ -223,12 +254,12 @@ __global__ void __launch_bounds__(64 * WR * WC) k_sketch(const float* __restrict
     const int sw = om_swz(row0);
     const uint32_t aoff = (uint32_t)(OM_BYTES + cl * 128);
 #pragma unroll
-    for (int c = 0; c < NS - 1; ++c)
-        if (c < nch) issue(c);
-    for (int c = 0; c < nch; ++c) {
-        // this wave's copies of chunk c are done once only those of the
-        // NS - 2 later (full) chunks can be outstanding
-        if (NS > 2 && c + NS - 2 < nfull) {
+    for (int i = 0; i < NS - 1; ++i)
+        if (chunk_of(i) < nch) issue(i);
+    for (int i = 0; i < nit; ++i) {
+        // this wave's copies of iteration i's chunk are done once only those
+        // of the NS - 2 later (full) chunks of its group can be outstanding
+        if (NS > 2 && chunk_of(i + NS - 2) < nfull) {
             if (REM != 0 && wave < REM)
                 wait_vm<(BASE + 1) * (NS > 2 ? NS - 2 : 0)>();
             else
@@ -236,9 +267,12 @@ __global__ void __launch_bounds__(64 * WR * WC) k_sketch(const float* __restrict
         } else {
             wait_vm<0>();
         }
-        ring_barrier();  // everyone's copies of chunk c are in LDS; chunk c - 1's buffer is free
-        if (c + NS - 1 < nch) issue(c + NS - 1);
-        const uint32_t sb = lds0 + (uint32_t)((c % NS) * STAGE);
+        // every group's copies of iteration i are in LDS; iteration i - 1's
+        // buffers are free
+        ring_barrier();
+        if (chunk_of(i + NS - 1) < nch) issue(i + NS - 1);
+        if (chunk_of(i) >= nch) continue;  // the last iteration of a group without a chunk (uniform per wave)
+        const uint32_t sb = lds0 + (uint32_t)(kg * NS * STAGE + (i % NS) * STAGE);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int q0 = 4 * ks + 2 * h;
@@ -284,6 +318,26 @@ __global__ void __launch_bounds__(64 * WR * WC) k_sketch(const float* __restrict
             }
         }
     }
+    if constexpr (KG == 2) {
+        // the second group's sums into the first group's (one addition per
+        // element, the same order everywhere): through LDS, laid out
+        // [wave][tile][element][lane] over the ring, which no copy targets any
+        // more (every issued chunk was waited for)
+        float* red = reinterpret_cast<float*>(smem_raw);
+        __syncthreads();
+        if (kg == 1) {
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) red[((wave * RT + t) * 16 + r) * kWave + lane] = acc[t][r];
+        }
+        __syncthreads();
+        if (kg == 1) return;
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[t][r] += red[((wave * RT + t) * 16 + r) * kWave + lane];
+    }
     const int64_t col = col0 + cl;
     if (col >= n) return;
     // accumulator elements 4 q .. 4 q + 3 are four consecutive rows of the
@@ -313,23 +367,26 @@ __global__ void __launch_bounds__(64 * WR * WC) k_sketch(const float* __restrict
     }
 }
 
-// LDS bytes of a k_sketch instantiation
-constexpr size_t sketch_lds(int rt, int wr, int wc, int ns) {
-    return (size_t)ns * ((size_t)wr * rt * 32 * 64 + (size_t)32 * wc * 128);
+// LDS bytes of a k_sketch instantiation (a ring per K group)
+constexpr size_t sketch_lds(int rt, int wr, int wc, int ns, int kg) {
+    return (size_t)kg * ns * ((size_t)wr * rt * 32 * 64 + (size_t)32 * wc * 128);
 }
 
-template <int NSPLIT, int RT, int WR, int WC, int NS>
+template <int NSPLIT, int RT, int WR, int WC, int NS, int KG = 1>
 static hipError_t launch_sketch(int pr, hipStream_t s, int64_t n, int rt_total, const float* A, int64_t lda, int64_t m,
                                 const uint16_t* Wt, int64_t mpad, float* S, int64_t ldw, float* Y, int64_t ldy,
                                 int l) {
-    constexpr size_t lds = sketch_lds(RT, WR, WC, NS);
+    constexpr size_t lds = sketch_lds(RT, WR, WC, NS, KG);
     static_assert(lds <= 160 * 1024, "LDS of a CU");
+    static_assert(KG == 1 || KG == 2, "one or two K groups");
+    // the second group's accumulators pass through the first group's ring
+    static_assert(KG == 1 || (size_t)WR * WC * RT * 16 * kWave * 4 <= lds, "reduction fits the ring");
     {
-        const hipError_t e = lds_limit_once((const void*)k_sketch<NSPLIT, RT, WR, WC, NS>, (int)lds);
+        const hipError_t e = lds_limit_once((const void*)k_sketch<NSPLIT, RT, WR, WC, NS, KG>, (int)lds);
         if (e != hipSuccess) return e;
     }
     dim3 grid((unsigned)((n + 32 * WC - 1) / (32 * WC)));
-    MIID_LAUNCH(pr, (k_sketch<NSPLIT, RT, WR, WC, NS>), grid, dim3(64 * WR * WC), lds, s, A, lda, m, n, Wt, mpad,
+    MIID_LAUNCH(pr, (k_sketch<NSPLIT, RT, WR, WC, NS, KG>), grid, dim3(64 * WR * WC * KG), lds, s, A, lda, m, n, Wt, mpad,
                 rt_total, S, ldw, Y, ldy, l);
     return hipGetLastError();
 }
@@ -337,17 +394,23 @@ static hipError_t launch_sketch(int pr, hipStream_t s, int64_t n, int rt_total, 
 // Workgroup shape from the 32-row tiles of Y: two waves along the rows with
 // 5 or 9 tiles each up to 18 tiles (576 rows), four with 8 tiles beyond (at
 // most 32 tiles: l <= 1024); four waves along the columns when that still
-// gives two workgroups per CU, else two.  The ring depth fills the LDS.
+// gives two workgroups per CU, else two.  The ring depth fills the LDS.  Up
+// to 9 tiles with fewer than two 128-column workgroups per CU (one wave per
+// SIMD in the shape above), three waves of 3 tiles along the rows, two along
+// the columns, and two K groups, each with its own ring, taking alternate
+// chunks of K: three waves per SIMD on the same 64 columns.
 template <int NSPLIT>
 static hipError_t launch_sketch_shape(int pr, hipStream_t s, int64_t n, int rt_total, const float* A, int64_t lda,
                                       int64_t m, const uint16_t* Wt, int64_t mpad, float* S, int64_t ldw, float* Y,
                                       int64_t ldy, int l) {
     const bool wide = (n + 127) / 128 >= 2 * (int64_t)dev_info().cus;
+    if (rt_total <= 9 && !wide)
+        return launch_sketch<NSPLIT, 3, 3, 2, 3, 2>(pr, s, n, rt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l);
     if (rt_total <= 10)
         return wide ? launch_sketch<NSPLIT, 5, 2, 4, 4>(pr, s, n, rt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l)
                     : launch_sketch<NSPLIT, 5, 2, 2, 4>(pr, s, n, rt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l);
     if (rt_total <= 18)
-        return wide ? launch_sketch<NSPLIT, 9, 2, 4, 3>(pr, s, n, rt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l)
+        return wide ? launch_sketch<NSPLIT, 6, 3, 4, 3>(pr, s, n, rt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l)
                     : launch_sketch<NSPLIT, 9, 2, 2, 3>(pr, s, n, rt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l);
     return launch_sketch<NSPLIT, 8, 4, 2, 2>(pr, s, n, rt_total, A, lda, m, Wt, mpad, S, ldw, Y, ldy, l);
 }
