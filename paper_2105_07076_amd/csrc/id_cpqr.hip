@@ -1120,24 +1120,34 @@ __global__ void __launch_bounds__(kTB) k_trsm_dinv(const double* __restrict__ R1
 // exact unit vectors (Z[:, J] = I); JMODE 1: their right-hand sides are read
 // as zero (the solution's columns come out zero).  The right-hand side
 // element (q, c) is R[q rs + c cs] (rows of R: rs = n, cs = 1).
-template <typename T, int NC, bool SEMI = false, int JMODE = 0>
-__global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, int64_t n,
+// KG = 2 (back substitution only): two groups of NC / 8 waves on the same
+// columns, group g taking the R11 slices g, g + 2, ... of each row block's
+// product; the second group's sums reach the first through LDS (added in
+// the same order in every run) and the first finishes the block.  Where
+// the right-hand sides fill the LDS (one workgroup per CU) this doubles the
+// waves per SIMD.
+template <typename T, int NC, bool SEMI = false, int JMODE = 0, int KG = 1>
+__global__ void __launch_bounds__(8 * NC * KG) k_trsm_blk(const T* __restrict__ R, int64_t n,
                                                      const double* __restrict__ R11s, int kpad,
                                                      const double* __restrict__ Dinv,
                                                      const DevState* __restrict__ st, int ksteps,
                                                      const int32_t* __restrict__ sel, T* __restrict__ Z,
                                                      int64_t ldz, int kmax, int refine, int64_t rs,
                                                      int64_t cs) {
-    constexpr int NT = 8 * NC;
+    static_assert(KG == 1 || (KG == 2 && !SEMI), "K groups in the back substitution only");
+    constexpr int NT = 8 * NC * KG;
     constexpr int NCP = NC + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sX = reinterpret_cast<double*>(smem_raw);  // [kpad][NCP]
     __shared__ double sT[kTB][NCP];
+    __shared__ double sT1[KG == 2 ? kTB : 1][NCP];  // the second group's sums
     const int K = st->stop ? st->k_out : ksteps;
     const int nbk = (K + kTB - 1) / kTB;
     const int kend = nbk * kTB;
     const int tid = threadIdx.x;
-    const int wave = tid / kWave, lane = tid % kWave;
+    const int wave_all = tid / kWave, lane = tid % kWave;
+    const int kgi = wave_all / (NC / 8);  // K group
+    const int wave = wave_all % (NC / 8);
     const int tr = 16 * (wave % 2), tc = 16 * (wave / 2);
     const int l16 = lane % 16, lq = lane / 16;
     const int64_t c0 = (int64_t)blockIdx.x * NC;
@@ -1205,7 +1215,9 @@ __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, in
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = r0 + tr + lq + 4 * e;
-                if (sweep == 0)
+                if (kgi != 0)
+                    acc[e] = 0.0;
+                else if (sweep == 0)
                     acc[e] = sX[row * NCP + tc + l16];
                 else
                     acc[e] = (double)load_or(R, (int64_t)row * rs + col * cs, row < K && col < n, 0, T(0));
@@ -1215,7 +1227,7 @@ __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, in
             // before the first product waits on them
             const int kstart = sweep == 0 ? r0 + kTB : r0;
             const double* ap = R11s + (r0 + tr + l16) + (int64_t)lq * kpad;
-            for (int k0 = kstart; k0 < kend; k0 += kTB) {
+            for (int k0 = kstart + kgi * kTB; k0 < kend; k0 += KG * kTB) {
                 double av[kTB / 4], xv[kTB / 4];
 #pragma unroll
                 for (int q = 0; q < kTB / 4; ++q) av[q] = ap[(int64_t)(k0 + 4 * q) * kpad];
@@ -1224,21 +1236,36 @@ __global__ void __launch_bounds__(8 * NC) k_trsm_blk(const T* __restrict__ R, in
 #pragma unroll
                 for (int q = 0; q < kTB / 4; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[q], xv[q], acc, 0, 0, 0);
             }
+            if constexpr (KG == 2) {
+                if (kgi == 1) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) sT[tr + lq + 4 * e][tc + l16] = acc[e];
-            __syncthreads();
-            const double* Db = Dinv + (int64_t)b * kTB * kTB;
-            d4_t out = {0.0, 0.0, 0.0, 0.0};
+                    for (int e = 0; e < 4; ++e) sT1[tr + lq + 4 * e][tc + l16] = acc[e];
+                }
+                __syncthreads();
+                if (kgi == 0) {
 #pragma unroll
-            for (int k0 = 0; k0 < kTB; k0 += 4) {
-                const double av = Db[(tr + l16) + (k0 + lq) * kTB];
-                const double xv = sT[k0 + lq][tc + l16];
-                out = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xv, out, 0, 0, 0);
+                    for (int e = 0; e < 4; ++e)
+                        sT[tr + lq + 4 * e][tc + l16] = acc[e] + sT1[tr + lq + 4 * e][tc + l16];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sT[tr + lq + 4 * e][tc + l16] = acc[e];
             }
+            __syncthreads();
+            if (kgi == 0) {
+                const double* Db = Dinv + (int64_t)b * kTB * kTB;
+                d4_t out = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                double* xp = &sX[(r0 + tr + lq + 4 * e) * NCP + tc + l16];
-                *xp = sweep == 0 ? out[e] : *xp + out[e];
+                for (int k0 = 0; k0 < kTB; k0 += 4) {
+                    const double av = Db[(tr + l16) + (k0 + lq) * kTB];
+                    const double xv = sT[k0 + lq][tc + l16];
+                    out = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xv, out, 0, 0, 0);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    double* xp = &sX[(r0 + tr + lq + 4 * e) * NCP + tc + l16];
+                    *xp = sweep == 0 ? out[e] : *xp + out[e];
+                }
             }
             __syncthreads();
         }
@@ -1485,7 +1512,7 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
     // solve (the largest kpad of each variant: 256, 512, 1024 rows of NC + 1
     // doubles) and the pivot kernel's per-row products (kThreads x (nb + 1))
     MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 64>, 256 * 65 * 8));
-    MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 32>, 512 * 33 * 8));
+    MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 32, false, 0, 2>, 512 * 33 * 8));
     MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 16>, 1024 * 17 * 8));
     MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 64, true>, 256 * 65 * 8));
     MIID_HIP(lds_limit_once((const void*)k_trsm_blk<T, 32, true>, 512 * 33 * 8));
@@ -1634,7 +1661,8 @@ int run_id(const IdPlan& P, const T* A, int64_t lda, int32_t* J, T* Z, int64_t l
                         (size_t)P.kpad * 65 * 8, stream, R, n, R11s, P.kpad, Dinv, st, ksteps, sel, Z, ldz, P.kmax,
                         (int)P.refine, n, (int64_t)1);
         } else if (P.kpad <= 512) {
-            MIID_LAUNCH(pr, (k_trsm_blk<T, 32>), dim3((unsigned)((n + 31) / 32)), dim3(8 * 32),
+            // the right-hand sides fill the LDS: two K groups (eight waves)
+            MIID_LAUNCH(pr, (k_trsm_blk<T, 32, false, 0, 2>), dim3((unsigned)((n + 31) / 32)), dim3(8 * 32 * 2),
                         (size_t)P.kpad * 33 * 8, stream, R, n, R11s, P.kpad, Dinv, st, ksteps, sel, Z, ldz, P.kmax,
                         (int)P.refine, n, (int64_t)1);
         } else {
