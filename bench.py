@@ -85,7 +85,7 @@ def time_id(miid_api, lib, A, k, steps, warmup, sample_every=7):
 GEMV_TRAFFIC = {
     "bytes_per_launch": 525.0e6,
     "sources": {
-        "paper_2105_07076_amd/csrc/id_cpqr.hip": "eea3e83bb07e1d399e4fb078829fac814a47c0b91a203f03c01ae78d277e1933",
+        "paper_2105_07076_amd/csrc/id_cpqr.hip": "115593bcf856d3dea91c62d6360f71dddf025003517240a98c255e667a106eab",
         "paper_2105_07076_amd/csrc/common.hpp": "bba9391732c3ff7fbbc98bd9a751dabbe8faba50964622b34c3c3b794be5ddcb",
         "paper_2105_07076_amd/csrc/cpqr.hpp": "f0aff2f110aba8d622a1c3591023c3d7431d8b68d0e390a3ac64a861375c2f9f",
     },
