@@ -77,7 +77,12 @@ def _check(A_np, l, k, mode, e2e_tol=None, nb=0, hints=0):
 
 @pytest.mark.parametrize("mode", [2, 1, 0])
 @pytest.mark.parametrize("m,n,l,k", [(64, 200, 26, 16), (100, 333, 50, 40), (257, 1000, 74, 64),
-                                     (33, 65, 33, 20)])
+                                     (33, 65, 33, 20),
+                                     # one 32-row chunk of K (the second K group has none), a
+                                     # ragged one, 9 row tiles exactly (two K groups), 10 (one
+                                     # group, five tiles per wave) and 19 (eight per wave)
+                                     (5, 40, 5, 3), (31, 90, 12, 8), (300, 1200, 288, 200),
+                                     (320, 1000, 300, 250), (640, 1400, 600, 400)])
 def test_rid_small(mode, m, n, l, k):
     g = idgen.rng(m * 7 + n)
     A = g.standard_normal((m, n)) @ np.diag(0.97 ** np.arange(n))
