@@ -82,7 +82,10 @@ def _check(A_np, l, k, mode, e2e_tol=None, nb=0, hints=0):
                                      # ragged one, 9 row tiles exactly (two K groups), 10 (one
                                      # group, five tiles per wave) and 19 (eight per wave)
                                      (5, 40, 5, 3), (31, 90, 12, 8), (300, 1200, 288, 200),
-                                     (320, 1000, 300, 250), (640, 1400, 600, 400)])
+                                     (320, 1000, 300, 250), (640, 1400, 600, 400),
+                                     # 13 row tiles on two-by-two waves of nine; at least 65409
+                                     # columns (two 128-column workgroups per CU) with 2 tiles
+                                     (600, 2000, 400, 300), (64, 65536, 40, 30)])
 def test_rid_small(mode, m, n, l, k):
     g = idgen.rng(m * 7 + n)
     A = g.standard_normal((m, n)) @ np.diag(0.97 ** np.arange(n))
